@@ -1,0 +1,217 @@
+/*
+ * libim — influence maximization by Stop-and-Stare (SSA, D-SSA) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (Nguyen, Thai, Dinh,
+ * "Stop-and-Stare: Optimal Sampling Algorithms for Viral Marketing in
+ * Billion-scale Networks", SIGMOD 2016): given a weighted digraph
+ * G = (V, E, w), a diffusion model (IC or LT, Section 2.1) and a budget
+ * 1 <= k <= |V|, return k seeds S_k that maximise the expected spread
+ * (Section 2.2, Definition 1).
+ *
+ * Conventions for every entry point:
+ *   - Pointer arguments are HOST pointers unless the name says `_dev`.
+ *   - Handles own all the device memory they use; the caller owns host
+ *     arrays and must keep them valid for the duration of the call only.
+ *   - All device work runs on the stream given to im_ctx_create; an entry
+ *     point that returns results to the host synchronises that stream.
+ *   - Handles are not thread-safe: serialise calls on one context.
+ *   - Return IM_OK (0) or a negative im_status; im_last_error() then holds
+ *     a thread-local message. Outputs are untouched on error.
+ */
+#ifndef IM_H
+#define IM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IM_OK = 0,
+    IM_E_ARG = -1,             /* invalid argument (range, ordering, null) */
+    IM_E_OOM = -2,             /* device or host allocation failed */
+    IM_E_LT_WEIGHTS = -3,      /* LT in-weights of some node sum above 1 */
+    IM_E_DEVICE = -4,          /* a HIP call failed */
+    IM_E_STREAM_MISMATCH = -5, /* pool extended with a key it was not made for */
+    IM_E_STATE = -6,           /* handle in the wrong state for the call */
+} im_status;
+
+typedef enum { IM_IC = 0, IM_LT = 1 } im_model;
+
+typedef struct im_ctx im_ctx;
+typedef struct im_graph im_graph;
+typedef struct im_pool im_pool;
+
+/* Device allocator hooks: alloc returns a device pointer of >= bytes
+ * (256-byte aligned) or NULL; free releases it. */
+typedef void *(*im_alloc_fn)(size_t bytes, void *user);
+typedef void (*im_free_fn)(void *ptr, void *user);
+
+/*
+ * Create a context on HIP device `device` whose work is queued on `stream`
+ * (a hipStream_t; NULL = the null stream). alloc/free may be NULL, in which
+ * case hipMalloc/hipFree are used. Errors: IM_E_ARG (bad device),
+ * IM_E_DEVICE.
+ */
+im_status im_ctx_create(int device, void *stream, im_alloc_fn alloc, im_free_fn free_, void *user,
+                        im_ctx **out);
+void im_ctx_free(im_ctx *ctx);
+
+/*
+ * Load G = (V, E, w) (Section 2) into device memory as a reverse adjacency.
+ * n = |V|; m = |E|; edge e is src[e] -> dst[e]. Edges must be sorted by
+ * (dst, src) with no repeated pair (the canonical order that keys every
+ * edge coin). w_ic[e] is the IC activation probability of edge e and
+ * w_lt[e] its LT weight (Section 2.1); either may be NULL, but not both,
+ * and a graph used with a model needs that model's weights.
+ * Device form: off[n+1] u64; per edge {u32 src, u32 thr}:
+ *   IC thr = floor(w * 2^32) clamped to 2^32-1 (live iff coin < thr; 2^32-1
+ *      is always live);
+ *   LT thr = floor(2^32 * (w_1 + ... + w_i)) clamped, FP64 sum left to right
+ *      over the node's in-edges (edge i kept iff thr_{i-1} <= coin < thr_i).
+ * Errors: IM_E_ARG (ids >= n, unsorted or repeated pairs, w outside [0,1],
+ * n == 0), IM_E_LT_WEIGHTS (some node's LT weights sum above 1 + 1e-6),
+ * IM_E_OOM.
+ */
+im_status im_graph_load(im_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                        const float *w_ic, const float *w_lt, im_graph **out);
+
+/*
+ * Weighted RR-set sources for targeted viral marketing (Section 7.3, WRIS):
+ * node_w[v] >= 0 integer relevance of v, n entries, not all zero. After this
+ * call RR sets of this graph pick their source v with probability
+ * node_w[v] / sum(node_w); NULL restores uniform sources (Definition 2).
+ * Pools created before the call are unaffected only if they are not
+ * extended again. Errors: IM_E_ARG (all zero), IM_E_OOM.
+ */
+im_status im_graph_set_source_weights(im_graph *g, const uint32_t *node_w);
+void im_graph_free(im_graph *g);
+
+/* Graph properties: n, m, which models it holds weights for (bit 0 IC,
+ * bit 1 LT). */
+im_status im_graph_info(const im_graph *g, uint32_t *n, uint64_t *m, uint32_t *models);
+
+/*
+ * An empty collection R of RR sets (Section 3.1.1) of one stream: set j is
+ * the RR set of sample j under `stream_key`, for model `model`.
+ * Errors: IM_E_ARG (graph lacks the model's weights), IM_E_OOM.
+ */
+im_status im_pool_create(im_ctx *ctx, const im_graph *g, im_model model, uint64_t stream_key,
+                         im_pool **out);
+void im_pool_free(im_pool *p);
+
+/*
+ * Append the RR sets (Definition 2) of samples [count, count + n_sets) of
+ * the pool's stream. Each set is a pure function of (graph, model, key,
+ * sample index): random source, then the nodes that reach it through live
+ * edges (IC: reverse breadth-first search; LT: reverse walk keeping at most
+ * one in-edge per node, stopping at a node with none or on a revisit).
+ * Errors: IM_E_STREAM_MISMATCH (stream_key or model differs from the
+ * pool's), IM_E_ARG (graph is not the pool's), IM_E_OOM, IM_E_DEVICE.
+ */
+im_status im_sample_rr(const im_graph *g, im_model model, uint64_t n_sets, uint64_t stream_key,
+                       im_pool *pool);
+
+/* Number of sets and total number of node entries in the pool. */
+im_status im_pool_info(const im_pool *p, uint64_t *count, uint64_t *total_nodes);
+
+/*
+ * Copy sets [begin, end) to the host: off_out[0 .. end-begin] (u64, relative
+ * to the first copied set) and nodes_out (u32, off_out[end-begin] entries,
+ * each set's nodes in traversal order, not sorted). Pass nodes_out = NULL to
+ * get the offsets only. Errors: IM_E_ARG (range).
+ */
+im_status im_pool_read(const im_pool *p, uint64_t begin, uint64_t end, uint64_t *off_out,
+                       uint32_t *nodes_out);
+
+/* Device views of the pool (valid until the pool next grows or is freed):
+ * poff_dev[count+1] u64 and pnodes_dev[poff[count]] u32. */
+im_status im_pool_device(const im_pool *p, const uint64_t **poff_dev, const uint32_t **pnodes_dev);
+
+/*
+ * Max-Coverage (Algorithm 2) over sets [begin, end) of the pool: k greedy
+ * rounds, each adding the node that covers the most not-yet-covered sets;
+ * ties go to the lowest node id, chosen nodes are never chosen again (when
+ * every remaining gain is 0 the lowest unchosen id is taken). Writes
+ * seeds_out[k] in selection order and *cov_out = Cov_R(S_k) (Eq. 1); the
+ * estimate n * Cov / |R| of Algorithm 2 is left to the caller.
+ * Errors: IM_E_ARG (k == 0 or k > n, bad range).
+ */
+im_status im_max_coverage(const im_pool *p, uint32_t k, uint32_t *seeds_out, uint64_t *cov_out);
+im_status im_max_coverage_range(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k,
+                                uint32_t *seeds_out, uint64_t *cov_out);
+
+/*
+ * Cov over sets [begin, end) (Eq. 1) of the seed set seeds[k] (the D-SSA
+ * stare step on R^c_t, Algorithm 4). Errors: IM_E_ARG.
+ */
+im_status im_coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds,
+                            uint32_t k, uint64_t *cov_out);
+
+/*
+ * Estimate-Inf (Algorithm 3): draw RR sets of samples 0, 1, 2, ... of
+ * stream `stream_key`, and at the first T with #{j <= T : R_j meets S} >=
+ * Lambda2 = 1 + (1 + eps_p) Upsilon(eps_p, delta_p) return
+ * *ic_out = n Lambda2 / T and *t_out = T; after floor(t_max) sets without
+ * reaching it return *ic_out = -1 and *t_out = floor(t_max).
+ * Errors: IM_E_ARG (eps_p, delta_p outside (0,1), seeds out of range).
+ */
+im_status im_estimate_inf(const im_graph *g, im_model model, const uint32_t *seeds, uint32_t k,
+                          double eps_p, double delta_p, double t_max, uint64_t stream_key,
+                          double *ic_out, uint64_t *t_out);
+
+#define IM_MAX_ITERS 64
+
+/* Statistics of one SSA / D-SSA run (host FP64 checkpoint logic). */
+typedef struct im_stats {
+    uint32_t iterations;     /* checkpoints visited */
+    uint32_t stopped_by_cap; /* 1 if the N_max cap ended the run */
+    uint64_t n_sets;         /* SSA |R| at stop; D-SSA |R_t| + |R^c_t| at stop */
+    uint64_t n_verify;       /* SSA: RR sets drawn by Estimate-Inf, all iterations */
+    uint64_t cov;            /* Cov_R(S_k) at stop */
+    uint64_t cov_c;          /* D-SSA Cov on R^c_t; SSA Estimate-Inf T at stop */
+    double i_hat;            /* n Cov / |R| at stop */
+    double i_c;              /* verification estimate at stop, -1 if none */
+    double eps1, eps2, eps3, eps_t;
+    uint64_t edges;          /* edges traversed by every RR set drawn */
+    uint64_t it_sets[IM_MAX_ITERS];
+    uint64_t it_cov[IM_MAX_ITERS];
+    uint64_t it_cov_c[IM_MAX_ITERS]; /* D-SSA Cov_c; SSA Estimate-Inf T (0 = not run) */
+    double it_eps_t[IM_MAX_ITERS];   /* D-SSA eps_t; SSA I_c (-1 = not run / failed) */
+    double ms_sample, ms_cover, ms_verify, ms_total; /* wall time per stage */
+} im_stats;
+
+/*
+ * SSA (Algorithm 1) with the default eps1, eps2, eps3 of Eq. 15. Checks
+ * at |R| = ceil(Lambda) 2^(t-1), t = 1, 2, ... (the schedule of the text
+ * and proofs of Section 4), condition C1 Cov >= Lambda1, then Estimate-Inf
+ * on stream derived_key(key, t) and condition C2 n Cov/|R| <= (1+eps1) I_c;
+ * stops after the iteration whose |R| reaches N_max. seeds_out[k].
+ * Errors: IM_E_ARG (k outside [1,n], eps outside (0, 1-1/e), delta outside
+ * (0,1), graph lacks the model).
+ */
+im_status im_ssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                 uint32_t *seeds_out, im_stats *st);
+
+/*
+ * D-SSA (Algorithm 4): one stream; at iteration t the first
+ * N_t = ceil(Lambda) 2^(t-1) sets find S_k, the next N_t verify it
+ * (condition D1 Cov_c >= Lambda1, then eps_t <= eps, condition D2); stops
+ * after the iteration whose N_t reaches N_max. Same errors as im_ssa.
+ */
+im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                  uint32_t *seeds_out, im_stats *st);
+
+/* The stream key of SSA iteration i's verification pool, derived from key. */
+uint64_t im_derived_key(uint64_t key, uint64_t i);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *im_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
