@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libim (include/im.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts
+numpy arrays to pointers, passes torch's current HIP stream and caching
+allocator to the context, and turns error codes into exceptions. Importing
+it on a machine without the built library raises at once.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libim.so"
+
+IM_IC, IM_LT = 0, 1
+MODELS = {"ic": IM_IC, "lt": IM_LT, IM_IC: IM_IC, IM_LT: IM_LT}
+MAX_ITERS = 64
+
+STATUS = {0: "IM_OK", -1: "IM_E_ARG", -2: "IM_E_OOM", -3: "IM_E_LT_WEIGHTS", -4: "IM_E_DEVICE",
+          -5: "IM_E_STREAM_MISMATCH", -6: "IM_E_STATE"}
+
+# Every symbol include/im.h declares.
+EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source_weights", "im_graph_free",
+           "im_graph_info", "im_pool_create", "im_pool_free", "im_sample_rr", "im_pool_info", "im_pool_read",
+           "im_pool_device", "im_max_coverage", "im_max_coverage_range", "im_coverage_range", "im_estimate_inf",
+           "im_ssa", "im_dssa", "im_derived_key", "im_last_error"]
+
+
+class ImError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_uint32), ("stopped_by_cap", ctypes.c_uint32),
+                ("n_sets", ctypes.c_uint64), ("n_verify", ctypes.c_uint64),
+                ("cov", ctypes.c_uint64), ("cov_c", ctypes.c_uint64),
+                ("i_hat", ctypes.c_double), ("i_c", ctypes.c_double),
+                ("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("eps3", ctypes.c_double),
+                ("eps_t", ctypes.c_double), ("edges", ctypes.c_uint64),
+                ("it_sets", ctypes.c_uint64 * MAX_ITERS), ("it_cov", ctypes.c_uint64 * MAX_ITERS),
+                ("it_cov_c", ctypes.c_uint64 * MAX_ITERS), ("it_eps_t", ctypes.c_double * MAX_ITERS),
+                ("ms_sample", ctypes.c_double), ("ms_cover", ctypes.c_double),
+                ("ms_verify", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        t = min(self.iterations, MAX_ITERS)
+        return dict(iterations=self.iterations, stopped_by_cap=bool(self.stopped_by_cap), n_sets=self.n_sets,
+                    n_verify=self.n_verify, cov=self.cov, cov_c=self.cov_c, i_hat=self.i_hat, i_c=self.i_c,
+                    eps1=self.eps1, eps2=self.eps2, eps3=self.eps3, eps_t=self.eps_t, edges=self.edges,
+                    it_sets=list(self.it_sets[:t]), it_cov=list(self.it_cov[:t]),
+                    it_cov_c=list(self.it_cov_c[:t]), it_eps_t=list(self.it_eps_t[:t]),
+                    ms_sample=self.ms_sample, ms_cover=self.ms_cover, ms_verify=self.ms_verify,
+                    ms_total=self.ms_total)
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def load_library(path: Path | str | None = None):
+    """Load libim.so and declare every entry point's signature."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise ImportError(f"libim.so is not built at {p}; run __graft_entry__.build()")
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7) and asks for
+    # it under an unversioned name; loading torch first lets libim's
+    # dependency resolve to that same runtime instead of a second copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(str(p))
+    vp, u32p, u64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
+    f32p, f64p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+    st = ctypes.c_int
+    sig = {
+        "im_ctx_create": (st, [ctypes.c_int, vp, ALLOC_FN, FREE_FN, vp, ctypes.POINTER(vp)]),
+        "im_ctx_free": (None, [vp]),
+        "im_graph_load": (st, [vp, ctypes.c_uint32, ctypes.c_uint64, u32p, u32p, f32p, f32p, ctypes.POINTER(vp)]),
+        "im_graph_set_source_weights": (st, [vp, u32p]),
+        "im_graph_free": (None, [vp]),
+        "im_graph_info": (st, [vp, u32p, u64p, u32p]),
+        "im_pool_create": (st, [vp, vp, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(vp)]),
+        "im_pool_free": (None, [vp]),
+        "im_sample_rr": (st, [vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, vp]),
+        "im_pool_info": (st, [vp, u64p, u64p]),
+        "im_pool_read": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, u64p, u32p]),
+        "im_pool_device": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "im_max_coverage": (st, [vp, ctypes.c_uint32, u32p, u64p]),
+        "im_max_coverage_range": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, u32p, u64p]),
+        "im_coverage_range": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint32, u64p]),
+        "im_estimate_inf": (st, [vp, ctypes.c_int, u32p, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_uint64, f64p, u64p]),
+        "im_ssa": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                        u32p, ctypes.POINTER(Stats)]),
+        "im_dssa": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                         u32p, ctypes.POINTER(Stats)]),
+        "im_derived_key": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
+        "im_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = _lib.im_last_error().decode(errors="replace")
+        raise ImError(rc, msg)
+
+
+def _u32(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _f32(a):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Context:
+    """im_ctx on one HIP device, queued on torch's current stream, allocating
+    through torch's caching allocator."""
+
+    def __init__(self, device: int = 0, use_torch: bool = True):
+        lib = load_library()
+        self.device = device
+        stream = None
+        self._alloc = ALLOC_FN()
+        self._free = FREE_FN()
+        if use_torch:
+            import torch
+
+            if not torch.cuda.is_available():
+                raise RuntimeError("no HIP device visible to torch")
+            torch.cuda.set_device(device)
+            self._torch_stream = torch.cuda.current_stream(device)
+            stream = ctypes.c_void_p(self._torch_stream.cuda_stream)
+
+            def _a(nbytes, user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, self._torch_stream)
+
+            def _f(ptr, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._alloc = ALLOC_FN(_a)
+            self._free = FREE_FN(_f)
+        h = ctypes.c_void_p()
+        _check(lib.im_ctx_create(device, stream, self._alloc, self._free, None, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().im_ctx_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """im_graph: G = (V, E, w) resident on the device."""
+
+    def __init__(self, ctx: Context, n: int, src, dst, w_ic=None, w_lt=None):
+        lib = load_library()
+        s, sp = _u32(src)
+        d, dp = _u32(dst)
+        wi, wip = _f32(w_ic)
+        wl, wlp = _f32(w_lt)
+        h = ctypes.c_void_p()
+        _check(lib.im_graph_load(ctx.h, n, s.shape[0], sp, dp, wip, wlp, ctypes.byref(h)))
+        self.ctx, self.h, self.n, self.m = ctx, h, n, int(s.shape[0])
+
+    def set_source_weights(self, node_w):
+        if node_w is None:
+            _check(load_library().im_graph_set_source_weights(self.h, None))
+        else:
+            w, wp = _u32(node_w)
+            _check(load_library().im_graph_set_source_weights(self.h, wp))
+
+    def info(self):
+        n, m, models = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+        _check(load_library().im_graph_info(self.h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(models)))
+        return int(n.value), int(m.value), int(models.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().im_graph_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def estimate_inf(self, model, seeds, eps_p, delta_p, t_max, key):
+        s, sp = _u32(seeds)
+        ic, T = ctypes.c_double(), ctypes.c_uint64()
+        _check(load_library().im_estimate_inf(self.h, MODELS[model], sp, s.shape[0], eps_p, delta_p, t_max, key,
+                                              ctypes.byref(ic), ctypes.byref(T)))
+        return float(ic.value), int(T.value)
+
+    def _run(self, fn, model, k, eps, delta, key):
+        seeds = np.zeros(k, dtype=np.uint32)
+        st = Stats()
+        _check(fn(self.h, MODELS[model], k, eps, delta, key, seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                  ctypes.byref(st)))
+        return seeds, st.as_dict()
+
+    def ssa(self, model, k, eps, delta, key):
+        return self._run(load_library().im_ssa, model, k, eps, delta, key)
+
+    def dssa(self, model, k, eps, delta, key):
+        return self._run(load_library().im_dssa, model, k, eps, delta, key)
+
+
+class Pool:
+    """im_pool: RR sets of one (graph, model, stream key)."""
+
+    def __init__(self, graph: Graph, model, key: int):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.im_pool_create(graph.ctx.h, graph.h, MODELS[model], key, ctypes.byref(h)))
+        self.graph, self.model, self.key, self.h = graph, MODELS[model], key, h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().im_pool_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sample(self, n_sets: int, key: int | None = None, model=None):
+        _check(load_library().im_sample_rr(self.graph.h, self.model if model is None else MODELS[model], n_sets,
+                                           self.key if key is None else key, self.h))
+
+    def info(self):
+        c, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load_library().im_pool_info(self.h, ctypes.byref(c), ctypes.byref(t)))
+        return int(c.value), int(t.value)
+
+    @property
+    def count(self) -> int:
+        return self.info()[0]
+
+    def read(self, begin: int = 0, end: int | None = None):
+        """(offsets, nodes) of sets [begin, end); nodes in traversal order."""
+        end = self.count if end is None else end
+        off = np.zeros(end - begin + 1, dtype=np.uint64)
+        lib = load_library()
+        _check(lib.im_pool_read(self.h, begin, end, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), None))
+        nodes = np.zeros(max(int(off[-1]), 1), dtype=np.uint32)
+        _check(lib.im_pool_read(self.h, begin, end, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+        return off, nodes[: int(off[-1])]
+
+    def device_pointers(self):
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(load_library().im_pool_device(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def max_coverage(self, k: int, begin: int = 0, end: int | None = None):
+        end = self.count if end is None else end
+        seeds = np.zeros(k, dtype=np.uint32)
+        cov = ctypes.c_uint64()
+        _check(load_library().im_max_coverage_range(self.h, begin, end, k,
+                                                     seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                                     ctypes.byref(cov)))
+        return seeds, int(cov.value)
+
+    def coverage(self, seeds, begin: int = 0, end: int | None = None) -> int:
+        end = self.count if end is None else end
+        s, sp = _u32(seeds)
+        cov = ctypes.c_uint64()
+        _check(load_library().im_coverage_range(self.h, begin, end, sp, s.shape[0], ctypes.byref(cov)))
+        return int(cov.value)
+
+
+def derived_key(key: int, i: int) -> int:
+    return int(load_library().im_derived_key(key, i))

@@ -1,0 +1,612 @@
+// C-ABI entry points of libim and the host-side checkpoint logic of SSA
+// (Algorithm 1) and D-SSA (Algorithm 4), kept in FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "im_internal.hpp"
+
+namespace im {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+im_status dev_alloc(im_ctx *ctx, DevBuf &b, size_t bytes) {
+    b.ptr = nullptr;
+    b.bytes = 0;
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (ctx->alloc) {
+        p = ctx->alloc(bytes, ctx->user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (!p) {
+        set_error("device allocation of %zu bytes failed", bytes);
+        return IM_E_OOM;
+    }
+    b.ptr = p;
+    b.bytes = bytes;
+    return IM_OK;
+}
+
+void dev_free(im_ctx *ctx, DevBuf &b) {
+    if (b.ptr) {
+        if (ctx->free_) {
+            ctx->free_(b.ptr, ctx->user);
+        } else {
+            (void)hipFree(b.ptr);
+        }
+    }
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+im_status dev_reserve(im_ctx *ctx, DevBuf &b, size_t bytes) {
+    if (b.ptr && b.bytes >= bytes) return IM_OK;
+    // the stream may still use the old buffer
+    IM_HIP(hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, b);
+    size_t want = bytes + bytes / 4;
+    return dev_alloc(ctx, b, want);
+}
+
+im_status to_host_sync(im_ctx *ctx, void *dst, const void *src_dev, size_t bytes) {
+    IM_HIP(hipMemcpyAsync(ctx->host_pinned, src_dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    IM_HIP(hipStreamSynchronize(ctx->stream));
+    std::memcpy(dst, ctx->host_pinned, bytes);
+    return IM_OK;
+}
+
+// Philox4x32-10 on the host (Salmon et al., SC 2011), for derived keys.
+static void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = uint64_t(0xD2511F53u) * c[0];
+        const uint64_t pb = uint64_t(0xCD9E8D57u) * c[2];
+        const uint32_t n0 = uint32_t(pb >> 32) ^ c[1] ^ k0;
+        const uint32_t n1 = uint32_t(pb);
+        const uint32_t n2 = uint32_t(pa >> 32) ^ c[3] ^ k1;
+        const uint32_t n3 = uint32_t(pa);
+        c[0] = n0;
+        c[1] = n1;
+        c[2] = n2;
+        c[3] = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+uint64_t derived_key(uint64_t key, uint64_t i) {
+    uint32_t c[4] = {uint32_t(i), uint32_t(i >> 32), 0u, 3u};
+    philox_host(c, uint32_t(key), uint32_t(key >> 32));
+    return uint64_t(c[0]) | (uint64_t(c[1]) << 32);
+}
+
+// ---- constants (Table 1, Algorithms 1, 3, 4, Eq. 15) ----
+
+static double ups_ln(double eps, double ln_inv_delta) {
+    return (2.0 + 2.0 * eps / 3.0) * ln_inv_delta / (eps * eps);
+}
+
+double upsilon(double eps, double delta) { return ups_ln(eps, std::log(1.0 / delta)); }
+
+double ln_choose(uint32_t n, uint32_t k) {
+    double s = 0.0;
+    for (uint32_t i = 1; i <= k; ++i) s += std::log(double(n - k + i) / double(i));
+    return s;
+}
+
+struct Caps {
+    double n_max, i_max, lambda;
+};
+
+// N_max = 8 (1-1/e)/(2+2eps/3) Upsilon(eps, delta/6/C(n,k)) n/k ;
+// i_max = ceil(log2(2 N_max / Upsilon(eps, delta/3))) ;
+// Lambda = Upsilon(eps, delta/(3 i_max)).
+static Caps caps(uint32_t n, uint32_t k, double eps, double delta) {
+    const double one_m = 1.0 - std::exp(-1.0);
+    Caps c;
+    c.n_max = 8.0 * one_m / (2.0 + 2.0 * eps / 3.0) * ups_ln(eps, std::log(6.0 / delta) + ln_choose(n, k)) * double(n) /
+              double(k);
+    c.i_max = std::ceil(std::log2(2.0 * c.n_max / upsilon(eps, delta / 3.0)));
+    c.lambda = upsilon(eps, delta / (3.0 * c.i_max));
+    return c;
+}
+
+static im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps, double delta) {
+    const double one_m = 1.0 - std::exp(-1.0);
+    if (!g) {
+        set_error("null graph");
+        return IM_E_ARG;
+    }
+    if (model != IM_IC && model != IM_LT) {
+        set_error("unknown model %d", int(model));
+        return IM_E_ARG;
+    }
+    if (!(g->models & (model == IM_IC ? 1u : 2u))) {
+        set_error("graph has no %s weights", model == IM_IC ? "IC" : "LT");
+        return IM_E_ARG;
+    }
+    if (k == 0 || k > g->n) {
+        set_error("k = %u outside [1, n = %u]", k, g->n);
+        return IM_E_ARG;
+    }
+    if (!(eps > 0.0 && eps < one_m)) {
+        set_error("eps = %g outside (0, 1-1/e)", eps);
+        return IM_E_ARG;
+    }
+    if (!(delta > 0.0 && delta < 1.0)) {
+        set_error("delta = %g outside (0, 1)", delta);
+        return IM_E_ARG;
+    }
+    return IM_OK;
+}
+
+// Largest batch drawn at once: LT reserves a staging region per sample.
+static uint64_t max_batch(im_model model) { return model == IM_LT ? (1ull << 20) : (1ull << 24); }
+
+static im_status pool_extend_to(im_pool *p, uint64_t target, double *ms) {
+    const double t0 = now_ms();
+    while (p->count < target) {
+        const uint64_t count = std::min<uint64_t>(target - p->count, max_batch(p->model));
+        SampleResult r;
+        IM_TRY(sample_batch(p->ctx, p->g, p->model, p->key, p->count, count, SampleMode::Pool,
+                            p->mean_size > 0 ? p->mean_size : 0.0, &r));
+        IM_TRY(pool_append_staged(p, count, r.total_nodes));
+        p->edges += r.edges;
+        p->mean_size = double(p->total) / double(p->count);
+    }
+    if (ms) *ms += now_ms() - t0;
+    return IM_OK;
+}
+
+im_status estimate_inf(const im_graph *g, im_model model, const uint32_t *seeds, uint32_t k, double eps_p,
+                       double delta_p, double t_max, uint64_t key, double t_hint, double *ic_out, uint64_t *t_out,
+                       uint64_t *edges_out) {
+    im_ctx *ctx = g->ctx;
+    const double lambda2 = 1.0 + (1.0 + eps_p) * upsilon(eps_p, delta_p);
+    const uint64_t need = uint64_t(std::ceil(lambda2));  // Cov >= Lambda2 for an integer Cov
+    const uint64_t t_last = t_max >= 1.8e19 ? ~0ull : uint64_t(std::floor(t_max));
+    IM_TRY(set_seed_bits(ctx, g->n, seeds, k));
+    uint64_t done = 0, cov = 0, edges = 0;
+    double guess = t_hint > 0 ? t_hint : 16.0 * double(need);
+    uint64_t chunk = uint64_t(std::min(1.1 * guess + 1024.0, 4.0e8));
+    while (done < t_last) {
+        const uint64_t c = std::min<uint64_t>(std::min<uint64_t>(std::max<uint64_t>(chunk, 1024), max_batch(model)),
+                                              t_last - done);
+        SampleResult r;
+        IM_TRY(sample_batch(ctx, g, model, key, done, c, SampleMode::Hits, 0.0, &r));
+        edges += r.edges;
+        int64_t idx = -1;
+        uint64_t hits = 0;
+        IM_TRY(first_crossing(ctx, c, need - cov, &idx, &hits));
+        if (idx >= 0) {
+            const uint64_t T = done + uint64_t(idx) + 1;
+            *ic_out = double(g->n) * lambda2 / double(T);
+            *t_out = T;
+            if (edges_out) *edges_out = edges;
+            return IM_OK;
+        }
+        cov += hits;
+        done += c;
+        chunk = std::max<uint64_t>(uint64_t(0.25 * guess) + 1024, chunk / 2);
+    }
+    *ic_out = -1.0;
+    *t_out = t_last;
+    if (edges_out) *edges_out = edges;
+    return IM_OK;
+}
+
+}  // namespace im
+
+using namespace im;
+
+// ------------------------------------------------------------- context ----
+
+extern "C" im_status im_ctx_create(int device, void *stream, im_alloc_fn alloc, im_free_fn free_, void *user,
+                                   im_ctx **out) {
+    clear_error();
+    if (!out) {
+        set_error("null output");
+        return IM_E_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        set_error("no HIP device %d (found %d)", device, ndev);
+        return IM_E_ARG;
+    }
+    IM_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    IM_HIP(hipGetDeviceProperties(&prop, device));
+    auto *c = new (std::nothrow) im_ctx();
+    if (!c) return IM_E_OOM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->alloc = alloc;
+    c->free_ = free_;
+    c->user = user;
+    c->cu_count = prop.multiProcessorCount;
+    c->total_mem = prop.totalGlobalMem;
+    if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        set_error("pinned host allocation failed");
+        return IM_E_OOM;
+    }
+    *out = c;
+    return IM_OK;
+}
+
+extern "C" void im_ctx_free(im_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits,
+                      &c->zflags})
+        dev_free(c, *b);
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    delete c;
+}
+
+// --------------------------------------------------------------- graph ----
+
+extern "C" im_status im_graph_load(im_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                                   const float *w_ic, const float *w_lt, im_graph **out) {
+    clear_error();
+    if (!ctx || !out || n == 0 || n == 0xFFFFFFFFu || (m && (!src || !dst)) || (!w_ic && !w_lt)) {
+        set_error("im_graph_load: bad arguments (n must be in [1, 2^32-2]; src, dst and one weight array required)");
+        return IM_E_ARG;
+    }
+    auto *g = new (std::nothrow) im_graph();
+    if (!g) return IM_E_OOM;
+    g->ctx = ctx;
+    g->n = n;
+    g->m = m;
+    im_status rc = graph_build(g, src, dst, w_ic, w_lt);
+    if (rc != IM_OK) {
+        im_graph_free(g);
+        return rc;
+    }
+    *out = g;
+    return IM_OK;
+}
+
+extern "C" im_status im_graph_set_source_weights(im_graph *g, const uint32_t *node_w) {
+    clear_error();
+    if (!g) return IM_E_ARG;
+    return graph_source_weights(g, node_w);
+}
+
+extern "C" void im_graph_free(im_graph *g) {
+    if (!g) return;
+    (void)hipStreamSynchronize(g->ctx->stream);
+    dev_free(g->ctx, g->off);
+    dev_free(g->ctx, g->edges_ic);
+    dev_free(g->ctx, g->edges_lt);
+    dev_free(g->ctx, g->src_cum);
+    delete g;
+}
+
+extern "C" im_status im_graph_info(const im_graph *g, uint32_t *n, uint64_t *m, uint32_t *models) {
+    clear_error();
+    if (!g) return IM_E_ARG;
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (models) *models = g->models;
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------- pool ----
+
+extern "C" im_status im_pool_create(im_ctx *ctx, const im_graph *g, im_model model, uint64_t stream_key,
+                                    im_pool **out) {
+    clear_error();
+    if (!ctx || !g || !out || g->ctx != ctx) {
+        set_error("im_pool_create: bad arguments");
+        return IM_E_ARG;
+    }
+    if ((model != IM_IC && model != IM_LT) || !(g->models & (model == IM_IC ? 1u : 2u))) {
+        set_error("im_pool_create: graph has no weights for model %d", int(model));
+        return IM_E_ARG;
+    }
+    auto *p = new (std::nothrow) im_pool();
+    if (!p) return IM_E_OOM;
+    p->ctx = ctx;
+    p->g = g;
+    p->model = model;
+    p->key = stream_key;
+    im_status rc = IM_OK;
+    // empty pool: poff = {0}
+    p->cap_sets = 1024;
+    p->cap_nodes = 1 << 16;
+    if ((rc = dev_alloc(ctx, p->poff, (p->cap_sets + 1) * 8)) || (rc = dev_alloc(ctx, p->pnodes, p->cap_nodes * 4))) {
+        im_pool_free(p);
+        return rc;
+    }
+    if (hipMemsetAsync(p->poff.ptr, 0, 8, ctx->stream) != hipSuccess) {
+        im_pool_free(p);
+        set_error("memset failed");
+        return IM_E_DEVICE;
+    }
+    *out = p;
+    return IM_OK;
+}
+
+extern "C" void im_pool_free(im_pool *p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->ctx->stream);
+    dev_free(p->ctx, p->poff);
+    dev_free(p->ctx, p->pnodes);
+    delete p;
+}
+
+extern "C" im_status im_sample_rr(const im_graph *g, im_model model, uint64_t n_sets, uint64_t stream_key,
+                                  im_pool *pool) {
+    clear_error();
+    if (!g || !pool) return IM_E_ARG;
+    if (pool->g != g) {
+        set_error("im_sample_rr: pool belongs to another graph");
+        return IM_E_ARG;
+    }
+    if (pool->key != stream_key || pool->model != model) {
+        set_error("im_sample_rr: pool stream (key %llu, model %d) differs from the call's (key %llu, model %d)",
+                  static_cast<unsigned long long>(pool->key), int(pool->model),
+                  static_cast<unsigned long long>(stream_key), int(model));
+        return IM_E_STREAM_MISMATCH;
+    }
+    return pool_extend_to(pool, pool->count + n_sets, nullptr);
+}
+
+extern "C" im_status im_pool_info(const im_pool *p, uint64_t *count, uint64_t *total_nodes) {
+    clear_error();
+    if (!p) return IM_E_ARG;
+    if (count) *count = p->count;
+    if (total_nodes) *total_nodes = p->total;
+    return IM_OK;
+}
+
+extern "C" im_status im_pool_read(const im_pool *p, uint64_t begin, uint64_t end, uint64_t *off_out,
+                                  uint32_t *nodes_out) {
+    clear_error();
+    if (!p || !off_out || begin > end || end > p->count) {
+        set_error("im_pool_read: bad range");
+        return IM_E_ARG;
+    }
+    hipStream_t st = p->ctx->stream;
+    const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);
+    IM_HIP(hipMemcpyAsync(off_out, poff + begin, (end - begin + 1) * 8, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipStreamSynchronize(st));
+    const uint64_t first = off_out[0];
+    const uint64_t len = off_out[end - begin] - first;
+    for (uint64_t i = 0; i <= end - begin; ++i) off_out[i] -= first;
+    if (nodes_out && len) {
+        IM_HIP(hipMemcpyAsync(nodes_out, static_cast<const uint32_t *>(p->pnodes.ptr) + first, len * 4,
+                              hipMemcpyDeviceToHost, st));
+        IM_HIP(hipStreamSynchronize(st));
+    }
+    return IM_OK;
+}
+
+extern "C" im_status im_pool_device(const im_pool *p, const uint64_t **poff_dev, const uint32_t **pnodes_dev) {
+    clear_error();
+    if (!p) return IM_E_ARG;
+    if (poff_dev) *poff_dev = static_cast<const uint64_t *>(p->poff.ptr);
+    if (pnodes_dev) *pnodes_dev = static_cast<const uint32_t *>(p->pnodes.ptr);
+    return IM_OK;
+}
+
+// ------------------------------------------------------------ coverage ----
+
+extern "C" im_status im_max_coverage_range(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k,
+                                           uint32_t *seeds_out, uint64_t *cov_out) {
+    clear_error();
+    if (!p || !seeds_out || !cov_out || begin > end || end > p->count || k == 0 || k > p->g->n) {
+        set_error("im_max_coverage: bad arguments (k must be in [1, n], range within the pool)");
+        return IM_E_ARG;
+    }
+    return max_coverage(p, begin, end, k, seeds_out, cov_out);
+}
+
+extern "C" im_status im_max_coverage(const im_pool *p, uint32_t k, uint32_t *seeds_out, uint64_t *cov_out) {
+    if (!p) return IM_E_ARG;
+    return im_max_coverage_range(p, 0, p->count, k, seeds_out, cov_out);
+}
+
+extern "C" im_status im_coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds,
+                                       uint32_t k, uint64_t *cov_out) {
+    clear_error();
+    if (!p || !cov_out || begin > end || end > p->count || (k && !seeds)) {
+        set_error("im_coverage_range: bad arguments");
+        return IM_E_ARG;
+    }
+    return coverage_range(p, begin, end, seeds, k, cov_out);
+}
+
+extern "C" im_status im_estimate_inf(const im_graph *g, im_model model, const uint32_t *seeds, uint32_t k,
+                                     double eps_p, double delta_p, double t_max, uint64_t stream_key, double *ic_out,
+                                     uint64_t *t_out) {
+    clear_error();
+    if (!g || !ic_out || !t_out || (k && !seeds) || !(eps_p > 0 && eps_p < 1) || !(delta_p > 0 && delta_p < 1) ||
+        !(t_max >= 0)) {
+        set_error("im_estimate_inf: bad arguments");
+        return IM_E_ARG;
+    }
+    if ((model != IM_IC && model != IM_LT) || !(g->models & (model == IM_IC ? 1u : 2u))) {
+        set_error("im_estimate_inf: graph has no weights for model %d", int(model));
+        return IM_E_ARG;
+    }
+    return estimate_inf(g, model, seeds, k, eps_p, delta_p, t_max, stream_key, 0.0, ic_out, t_out, nullptr);
+}
+
+extern "C" uint64_t im_derived_key(uint64_t key, uint64_t i) { return derived_key(key, i); }
+
+extern "C" const char *im_last_error(void) { return g_err; }
+
+// ------------------------------------------------------- SSA / D-SSA ----
+
+extern "C" im_status im_ssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                            uint32_t *seeds_out, im_stats *st) {
+    clear_error();
+    IM_TRY(check_query(g, model, k, eps, delta));
+    if (!seeds_out || !st) return IM_E_ARG;
+    const double t_start = now_ms();
+    std::memset(st, 0, sizeof(*st));
+    st->i_c = -1.0;
+    const double one_m = 1.0 - std::exp(-1.0);
+    // Eq. 15 defaults
+    const double eps2 = eps / (2.0 * one_m);
+    const double eps3 = eps2;
+    const double eps1 = (1.0 + eps / (2.0 * (one_m - eps))) / (1.0 + eps2) - 1.0;
+    const Caps c = caps(g->n, k, eps, delta);
+    const double lambda1 = (1.0 + eps1) * (1.0 + eps2) * upsilon(eps3, delta / (3.0 * c.i_max));
+    const double delta2p = delta / (3.0 * c.i_max);
+    const double lambda2 = 1.0 + (1.0 + eps2) * upsilon(eps2, delta2p);
+    const double n = double(g->n);
+
+    im_pool *pool = nullptr;
+    IM_TRY(im_pool_create(g->ctx, g, model, key, &pool));
+    std::vector<uint32_t> seeds(k);
+    const uint64_t n1 = uint64_t(std::ceil(c.lambda));
+    im_status rc = IM_OK;
+    for (uint32_t t = 1;; ++t) {
+        const uint64_t size = n1 << (t - 1);
+        if ((rc = pool_extend_to(pool, size, &st->ms_sample))) break;
+        uint64_t cov = 0;
+        double t0 = now_ms();
+        if ((rc = max_coverage(pool, 0, size, k, seeds.data(), &cov))) break;
+        st->ms_cover += now_ms() - t0;
+        const double i_hat = n * double(cov) / double(size);
+        st->iterations = t;
+        st->n_sets = size;
+        st->cov = cov;
+        st->i_hat = i_hat;
+        if (t <= IM_MAX_ITERS) {
+            st->it_sets[t - 1] = size;
+            st->it_cov[t - 1] = cov;
+            st->it_eps_t[t - 1] = -1.0;
+        }
+        bool done = false;
+        if (double(cov) >= lambda1) {  // C1
+            const double t_max = 2.0 * double(size) * (1.0 + eps2) / (1.0 - eps2) * (eps3 * eps3) / (eps2 * eps2);
+            double ic = -1.0;
+            uint64_t T = 0, ex = 0;
+            t0 = now_ms();
+            const double hint = lambda2 * double(size) / double(cov > 0 ? cov : 1);
+            if ((rc = estimate_inf(g, model, seeds.data(), k, eps2, delta2p, t_max, derived_key(key, t), hint, &ic, &T,
+                                   &ex)))
+                break;
+            st->ms_verify += now_ms() - t0;
+            st->n_verify += T;
+            st->edges += ex;
+            st->cov_c = T;
+            st->i_c = ic;
+            if (t <= IM_MAX_ITERS) {
+                st->it_cov_c[t - 1] = T;
+                st->it_eps_t[t - 1] = ic;
+            }
+            if (i_hat <= (1.0 + eps1) * ic) done = true;  // C2
+        }
+        if (done) break;
+        if (double(size) >= c.n_max) {
+            st->stopped_by_cap = 1;
+            break;
+        }
+    }
+    if (rc == IM_OK) {
+        st->eps1 = eps1;
+        st->eps2 = eps2;
+        st->eps3 = eps3;
+        st->edges += pool->edges;
+        std::memcpy(seeds_out, seeds.data(), 4ull * k);
+    }
+    im_pool_free(pool);
+    st->ms_total = now_ms() - t_start;
+    return rc;
+}
+
+extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                             uint32_t *seeds_out, im_stats *st) {
+    clear_error();
+    IM_TRY(check_query(g, model, k, eps, delta));
+    if (!seeds_out || !st) return IM_E_ARG;
+    const double t_start = now_ms();
+    std::memset(st, 0, sizeof(*st));
+    st->i_c = -1.0;
+    const double one_m = 1.0 - std::exp(-1.0);
+    const Caps c = caps(g->n, k, eps, delta);  // t_max = i_max
+    const double lambda1 = 1.0 + (1.0 + eps) * upsilon(eps, delta / (3.0 * c.i_max));
+    const double n = double(g->n);
+
+    im_pool *pool = nullptr;
+    IM_TRY(im_pool_create(g->ctx, g, model, key, &pool));
+    std::vector<uint32_t> seeds(k);
+    const uint64_t n1 = uint64_t(std::ceil(c.lambda));
+    im_status rc = IM_OK;
+    for (uint32_t t = 1;; ++t) {
+        const uint64_t nt = n1 << (t - 1);
+        if ((rc = pool_extend_to(pool, 2 * nt, &st->ms_sample))) break;
+        uint64_t cov = 0, cov_c = 0;
+        double t0 = now_ms();
+        if ((rc = max_coverage(pool, 0, nt, k, seeds.data(), &cov))) break;
+        st->ms_cover += now_ms() - t0;
+        t0 = now_ms();
+        if ((rc = coverage_range(pool, nt, 2 * nt, seeds.data(), k, &cov_c))) break;
+        st->ms_verify += now_ms() - t0;
+        const double i_hat = n * double(cov) / double(nt);
+        st->iterations = t;
+        st->n_sets = 2 * nt;
+        st->cov = cov;
+        st->cov_c = cov_c;
+        st->i_hat = i_hat;
+        if (t <= IM_MAX_ITERS) {
+            st->it_sets[t - 1] = nt;
+            st->it_cov[t - 1] = cov;
+            st->it_cov_c[t - 1] = cov_c;
+            st->it_eps_t[t - 1] = -1.0;
+        }
+        bool done = false;
+        if (double(cov_c) >= lambda1) {  // D1
+            const double two_t1 = std::ldexp(1.0, int(t) - 1);
+            const double i_c = double(cov_c) * n / double(nt);
+            const double e1 = i_hat / i_c - 1.0;
+            const double e2 = eps * std::sqrt(n * (1.0 + eps) / (two_t1 * i_c));
+            const double e3 = eps * std::sqrt(n * (1.0 + eps) * (one_m - eps) / ((1.0 + eps / 3.0) * two_t1 * i_c));
+            const double e_t = (e1 + e2 + e1 * e2) * (one_m - eps) + one_m * e3;
+            st->i_c = i_c;
+            st->eps1 = e1;
+            st->eps2 = e2;
+            st->eps3 = e3;
+            st->eps_t = e_t;
+            if (t <= IM_MAX_ITERS) st->it_eps_t[t - 1] = e_t;
+            if (e_t <= eps) done = true;  // D2
+        }
+        if (done) break;
+        if (double(nt) >= c.n_max) {
+            st->stopped_by_cap = 1;
+            break;
+        }
+    }
+    if (rc == IM_OK) {
+        st->edges = pool->edges;
+        std::memcpy(seeds_out, seeds.data(), 4ull * k);
+    }
+    im_pool_free(pool);
+    st->ms_total = now_ms() - t_start;
+    return rc;
+}

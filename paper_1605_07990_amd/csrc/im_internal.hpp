@@ -1,0 +1,150 @@
+// Host-side internals of libim: handles, device buffers, error reporting,
+// and the launch entry points each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/im.h"
+
+namespace im {
+
+// Per-thread message behind im_last_error().
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define IM_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t err__ = (call);                                                           \
+        if (err__ != hipSuccess) {                                                           \
+            ::im::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(err__), __FILE__, \
+                            __LINE__);                                                       \
+            return IM_E_DEVICE;                                                              \
+        }                                                                                    \
+    } while (0)
+
+#define IM_TRY(expr)                          \
+    do {                                      \
+        im_status st__ = (expr);              \
+        if (st__ != IM_OK) return st__;       \
+    } while (0)
+
+}  // namespace im
+
+// A device allocation owned by a context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct im_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    im_alloc_fn alloc = nullptr;
+    im_free_fn free_ = nullptr;
+    void *user = nullptr;
+    int cu_count = 0;
+    size_t total_mem = 0;
+
+    // Reusable work buffers, grown on demand and kept for the context's life.
+    DevBuf stage;        // sampler staging: RR sets before compaction
+    DevBuf sample_meta;  // per-sample size / staging offset / hit flags
+    DevBuf counters;     // small device counters (tickets, cursors, flags)
+    DevBuf scan_tmp;     // scan partials
+    DevBuf slots;        // long-path visited stamps + queues
+    uint32_t slot_n = 0;      // n the slot arrays are laid out for
+    uint32_t slot_count = 0;  // number of long-path slots
+    uint64_t slot_epoch = 0;  // stamps handed out so far (host mirror)
+    DevBuf cover;        // incidence / greedy working arrays
+    DevBuf seedbits;     // seed-set bitmap (n bits)
+    DevBuf zflags;       // Estimate-Inf per-sample hit flags
+    void *host_pinned = nullptr;  // small pinned staging for read-backs
+};
+
+struct im_graph {
+    im_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t m = 0;
+    uint32_t models = 0;         // bit 0: IC weights present, bit 1: LT weights present
+    uint32_t max_in = 0;         // largest in-degree
+    DevBuf off;                  // u64[n+1]
+    DevBuf edges_ic;             // uint2[m] {src, thr}
+    DevBuf edges_lt;             // uint2[m] {src, cumulative thr}
+    DevBuf src_cum;              // u64[n+1] cumulative integer source weights, or empty
+};
+
+struct im_pool {
+    im_ctx *ctx = nullptr;
+    const im_graph *g = nullptr;
+    im_model model = IM_IC;
+    uint64_t key = 0;
+    uint64_t count = 0;      // sets held
+    uint64_t total = 0;      // node entries held
+    uint64_t edges = 0;      // edges traversed while drawing the held sets
+    size_t cap_sets = 0;     // poff capacity (sets)
+    size_t cap_nodes = 0;    // pnodes capacity
+    DevBuf poff;             // u64[cap_sets+1]
+    DevBuf pnodes;           // u32[cap_nodes]
+    double mean_size = 0.0;  // running mean set size (staging estimate)
+};
+
+namespace im {
+
+// Device memory through the context's allocator (or hipMalloc).
+im_status dev_alloc(im_ctx *ctx, DevBuf &b, size_t bytes);
+void dev_free(im_ctx *ctx, DevBuf &b);
+// Grow b to at least `bytes` (contents not preserved).
+im_status dev_reserve(im_ctx *ctx, DevBuf &b, size_t bytes);
+im_status to_host_sync(im_ctx *ctx, void *dst, const void *src_dev, size_t bytes);
+
+// What a sampling pass produces.
+enum class SampleMode : int {
+    Pool = 0,  // store RR sets into the context's staging buffer
+    Hits = 1,  // only decide whether each RR set meets the seed bitmap
+};
+
+struct SampleResult {
+    uint64_t total_nodes = 0;  // Pool mode: sum of set sizes of the batch
+    uint64_t edges = 0;        // edges traversed
+    uint64_t deferred = 0;     // samples that took the long path
+};
+
+// Draw samples [s0, s0+count) of stream `key` for `model`. Pool mode leaves
+// the sets in ctx->stage with per-sample (offset, size) in ctx->sample_meta;
+// Hits mode leaves one u8 flag per sample in ctx->zflags (1 = meets seeds in
+// ctx->seedbits).
+im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t key, uint64_t s0,
+                       uint64_t count, SampleMode mode, double size_hint, SampleResult *res);
+
+// Append the staged batch (`count` samples) to the pool, in sample order.
+im_status pool_append_staged(im_pool *p, uint64_t count, uint64_t total_nodes);
+
+// Max-Coverage (Algorithm 2) over pool sets [begin, end); seeds stay on
+// device in ctx->cover too; seeds_host[k] and *cov are written.
+im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k, uint32_t *seeds_host,
+                       uint64_t *cov);
+// Cov of seeds over [begin, end).
+im_status coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host,
+                         uint32_t k, uint64_t *cov);
+// Build ctx->seedbits from host seeds.
+im_status set_seed_bits(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k);
+// First index in zflags[0..count) where the running hit count reaches
+// `need` (or -1), plus the number of hits in the range.
+im_status first_crossing(im_ctx *ctx, uint64_t count, uint64_t need, int64_t *index, uint64_t *hits);
+
+// Estimate-Inf (Algorithm 3) with an optional expected-T hint for chunking.
+im_status estimate_inf(const im_graph *g, im_model model, const uint32_t *seeds, uint32_t k, double eps_p,
+                       double delta_p, double t_max, uint64_t key, double t_hint, double *ic_out,
+                       uint64_t *t_out, uint64_t *edges_out);
+
+// Graph construction kernels.
+im_status graph_build(im_graph *g, const uint32_t *src, const uint32_t *dst, const float *w_ic,
+                      const float *w_lt);
+im_status graph_source_weights(im_graph *g, const uint32_t *node_w);
+
+double now_ms();
+
+}  // namespace im

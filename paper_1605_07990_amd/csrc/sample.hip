@@ -1,0 +1,890 @@
+// RR-set sampling (Definition 2) on gfx950.
+//
+// Every RR set is a pure function of (key, sample index): the source and
+// every coin are Philox words at counters naming (sample, edge group) or
+// (sample, node). So samples can run in any order, on any lane, and be
+// re-run, and the pool is identical to a sequential draw.
+//
+// IC  — one wave per sample: reverse breadth-first search whose frontier
+//       (up to 64 queued nodes at a time) is expanded as one flat list of
+//       aligned 4-edge groups spread over the wave's lanes; one Philox call
+//       per group gives the four edge coins. Visited set: an LDS bitmap
+//       (n <= 65536) or an LDS open-addressing hash; the queue lives in LDS.
+// LT  — one lane per sample: the reverse walk keeps at most one in-edge per
+//       node (binary search of the node's cumulative thresholds, then one
+//       vectorised window); revisits are caught by a per-lane 1024-bit LDS
+//       Bloom filter confirmed against the walk written so far.
+// Long path — samples that outgrow LDS (IC) or the per-sample staging
+//       region (LT) are deferred and re-run from scratch by whole waves on
+//       global epoch-stamped visited arrays and queues.
+// Pool append — sizes are scanned into the CSR offsets in sample order and
+//       each set is copied from staging into the flat pool.
+#include <algorithm>
+#include <cmath>
+
+#include "im_device.hpp"
+#include "im_internal.hpp"
+
+namespace {
+
+using namespace imd;
+
+constexpr int kIcWaves = 4;                  // waves per IC block
+constexpr uint32_t kIcQcap = 1024;           // LDS queue entries per wave
+constexpr uint32_t kIcHcap = 2048;           // LDS hash slots / bitmap words per wave
+constexpr uint32_t kIcHbits = 11;            // log2(kIcHcap)
+constexpr uint32_t kBitmapMaxN = kIcHcap * 32;
+constexpr int kLtWaves = 4;
+constexpr int kBloomWords = 32;              // 1024-bit Bloom filter per lane
+constexpr uint32_t kLtCap = 512;             // per-sample staging region (LT)
+constexpr int kLongWaves = 4;
+
+struct Counters {
+    uint32_t ticket;        // next sample of the main pass
+    uint32_t defer_count;   // samples handed to the long path
+    uint32_t defer_ticket;  // next deferred sample of the long path
+    uint32_t overflow;      // staging too small: the batch must be re-run
+    unsigned long long stage_cursor;
+    unsigned long long edges;
+    unsigned long long total_nodes;
+};
+
+struct Params {
+    const uint64_t *off;
+    const uint2 *edges;
+    const uint64_t *src_cum;  // weighted sources, or null
+    uint32_t n;
+    uint32_t count;
+    uint64_t key;
+    uint64_t s0;
+    Counters *cnt;
+    uint32_t *defer_list;
+    uint32_t *stage;
+    uint64_t stage_cap;
+    uint64_t *stage_off;  // per sample
+    uint32_t *sizes;      // per sample
+    uint8_t *z;           // per sample (hits mode)
+    const uint32_t *seedbits;
+    uint32_t lt_cap;
+};
+
+__global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
+    c->ticket = 0;
+    c->defer_count = 0;
+    c->defer_ticket = 0;
+    c->overflow = 0;
+    c->stage_cursor = cursor0;
+    c->edges = 0;
+    c->total_nodes = 0;
+}
+
+// ---------------------------------------------------------------- IC ----
+
+template <bool kBitmap>
+__device__ __forceinline__ bool vis_insert(uint32_t *vis, uint32_t u, bool &full) {
+    if constexpr (kBitmap) {
+        const uint32_t bit = 1u << (u & 31u);
+        const uint32_t old = atomicOr(&vis[u >> 5], bit);
+        return !(old & bit);
+    } else {
+        const uint32_t key = u + 1u;
+        uint32_t h = (u * 2654435761u) >> (32 - kIcHbits);
+        for (uint32_t probe = 0; probe < kIcHcap; ++probe) {
+            const uint32_t old = atomicCAS(&vis[h], 0u, key);
+            if (old == 0u) return true;
+            if (old == key) return false;
+            h = (h + 1u) & (kIcHcap - 1u);
+        }
+        full = true;
+        return false;
+    }
+}
+
+template <bool kBitmap>
+__device__ __forceinline__ uint32_t vis_slot(const uint32_t *vis, uint32_t u) {
+    if constexpr (kBitmap) {
+        return u >> 5;
+    } else {
+        const uint32_t key = u + 1u;
+        uint32_t h = (u * 2654435761u) >> (32 - kIcHbits);
+        for (uint32_t probe = 0; probe < kIcHcap; ++probe) {
+            if (vis[h] == key) return h;
+            h = (h + 1u) & (kIcHcap - 1u);
+        }
+        return kIcHcap;  // not found (cannot happen for an inserted node)
+    }
+}
+
+// Clear the visited structure after a sample whose queued nodes are
+// queue[0..tail) (every inserted node is queued unless `dirty`).
+template <bool kBitmap>
+__device__ __forceinline__ void vis_clear(uint32_t *vis, const uint32_t *queue, uint32_t tail, bool dirty,
+                                          uint32_t lane) {
+    if (dirty || tail > kWave) {
+        for (uint32_t i = lane; i < kIcHcap; i += kWave) vis[i] = 0u;
+    } else {
+        uint32_t slot = kIcHcap;
+        if (lane < tail) slot = vis_slot<kBitmap>(vis, queue[lane]);
+        wave_sync();
+        if (slot < kIcHcap) vis[slot] = 0u;
+    }
+    wave_sync();
+}
+
+template <int kMode, bool kBitmap>
+__global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
+    __shared__ uint32_t s_queue[kIcWaves][kIcQcap];
+    __shared__ uint32_t s_vis[kIcWaves][kIcHcap];
+    __shared__ uint32_t s_pre[kIcWaves][kWave];
+    __shared__ uint64_t s_a[kIcWaves][kWave];
+    __shared__ uint64_t s_b[kIcWaves][kWave];
+
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint32_t *queue = s_queue[wave];
+    uint32_t *vis = s_vis[wave];
+    uint32_t *pre = s_pre[wave];
+    uint64_t *fa = s_a[wave];
+    uint64_t *fb = s_b[wave];
+    const Stream st(p.key);
+
+    for (uint32_t i = lane; i < kIcHcap; i += kWave) vis[i] = 0u;
+    wave_sync();
+    uint64_t edges_acc = 0, nodes_acc = 0;
+
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&p.cnt->ticket, 1u);
+        t = __shfl(t, 0, kWave);
+        if (t >= p.count) break;
+        const uint64_t s = p.s0 + t;
+        const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
+        bool full = false;
+        if (lane == 0) {
+            vis_insert<kBitmap>(vis, v0, full);
+            queue[0] = v0;
+        }
+        uint32_t head = 0, tail = 1;
+        bool hit = (kMode == 1) && test_bit(p.seedbits, v0);
+        uint64_t sample_edges = 0;
+        wave_sync();
+
+        while (head < tail && !hit) {
+            const uint32_t nb = min(tail - head, static_cast<uint32_t>(kWave));
+            uint32_t cg = 0;
+            uint64_t a = 0, b = 0;
+            if (lane < nb) {
+                const uint32_t v = queue[head + lane];
+                a = p.off[v];
+                b = p.off[v + 1];
+                if (b > a) cg = static_cast<uint32_t>(((b - 1) >> 2) - (a >> 2) + 1);
+            }
+            const uint32_t inc = wave_inclusive_scan(cg);
+            const uint32_t groups = __shfl(inc, kWave - 1, kWave);
+            sample_edges += wave_sum_u64(b - a);
+            pre[lane] = inc - cg;
+            fa[lane] = a;
+            fb[lane] = b;
+            head += nb;
+            wave_sync();
+
+            bool stop = false;
+            for (uint32_t base = 0; base < groups; base += kWave) {
+                const uint32_t w = base + lane;
+                uint32_t f0 = 0xFFFFFFFFu, f1 = 0xFFFFFFFFu, f2 = 0xFFFFFFFFu, f3 = 0xFFFFFFFFu;
+                if (w < groups) {
+                    // owner: last frontier slot whose first group index <= w
+                    uint32_t lo = 0, hi = nb - 1;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (pre[mid] <= w) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const uint64_t ea = fa[lo], eb = fb[lo];
+                    const uint64_t g = (ea >> 2) + (w - pre[lo]);
+                    const uint4 coins = ic_coins(st, s, g);
+                    const uint64_t e0 = g << 2;
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) {
+                        const uint64_t e = e0 + q;
+                        if (e >= ea && e < eb) {
+                            const uint2 rec = p.edges[e];
+                            if (ic_live(word_of(coins, q), rec.y) && vis_insert<kBitmap>(vis, rec.x, full)) {
+                                if (q == 0) f0 = rec.x;
+                                else if (q == 1) f1 = rec.x;
+                                else if (q == 2) f2 = rec.x;
+                                else f3 = rec.x;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) {
+                    const uint32_t f = (q == 0) ? f0 : (q == 1) ? f1 : (q == 2) ? f2 : f3;
+                    const bool has = f != 0xFFFFFFFFu;
+                    const uint64_t mask = __ballot(has);
+                    if (mask) {
+                        const uint32_t pos = tail + lanes_below(mask);
+                        if (has) {
+                            if (pos < kIcQcap) queue[pos] = f;
+                            if (kMode == 1 && test_bit(p.seedbits, f)) hit = true;
+                        }
+                        tail += static_cast<uint32_t>(__popcll(mask));
+                    }
+                }
+                if (kMode == 1) hit = __ballot(hit) != 0;
+                if (tail > kIcQcap || __ballot(full) != 0 || hit) {
+                    stop = true;
+                    break;
+                }
+            }
+            wave_sync();
+            if (stop) break;
+        }
+
+        const bool overflow = (tail > kIcQcap) || (__ballot(full) != 0);
+        if (overflow && !hit) {
+            if (lane == 0) {
+                const uint32_t d = atomicAdd(&p.cnt->defer_count, 1u);
+                p.defer_list[d] = t;
+            }
+        } else if (kMode == 1) {
+            if (lane == 0) p.z[t] = hit ? 1 : 0;
+            edges_acc += sample_edges;
+        } else {
+            unsigned long long base = 0;
+            if (lane == 0) {
+                base = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(tail));
+                if (base + tail > p.stage_cap) {
+                    atomicOr(&p.cnt->overflow, 1u);
+                    p.sizes[t] = 0;
+                    p.stage_off[t] = 0;
+                } else {
+                    p.sizes[t] = tail;
+                    p.stage_off[t] = base;
+                }
+            }
+            base = __shfl(base, 0, kWave);
+            if (base + tail <= p.stage_cap)
+                for (uint32_t i = lane; i < tail; i += kWave) p.stage[base + i] = queue[i];
+            edges_acc += sample_edges;
+            nodes_acc += tail;
+        }
+        vis_clear<kBitmap>(vis, queue, min(tail, kIcQcap), overflow || hit, lane);
+    }
+    if (lane == 0) {
+        if (edges_acc) atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(edges_acc));
+        if (nodes_acc) atomicAdd(&p.cnt->total_nodes, static_cast<unsigned long long>(nodes_acc));
+    }
+}
+
+// ---------------------------------------------------------------- LT ----
+
+__device__ __forceinline__ uint32_t bloom_h1(uint32_t u) { return (u * 0x9E3779B1u) >> 22; }
+__device__ __forceinline__ uint32_t bloom_h2(uint32_t u) { return (u * 0x85EBCA77u + 0x165667B1u) >> 22; }
+
+__device__ __forceinline__ void bloom_insert(uint32_t *bl, uint32_t u) {
+    const uint32_t h1 = bloom_h1(u), h2 = bloom_h2(u);
+    bl[(h1 >> 5) * kWave] |= 1u << (h1 & 31u);
+    bl[(h2 >> 5) * kWave] |= 1u << (h2 & 31u);
+}
+
+__device__ __forceinline__ bool bloom_maybe(const uint32_t *bl, uint32_t u) {
+    const uint32_t h1 = bloom_h1(u), h2 = bloom_h2(u);
+    return ((bl[(h1 >> 5) * kWave] >> (h1 & 31u)) & 1u) && ((bl[(h2 >> 5) * kWave] >> (h2 & 31u)) & 1u);
+}
+
+// The in-edge kept by node v's LT coin c: the first e in [a, b) whose
+// cumulative threshold exceeds c, or b if none.
+__device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint64_t b, uint32_t c,
+                                            uint32_t &u) {
+    uint64_t lo = a, hi = b;  // answer in [lo, hi]; thr[hi] > c unless hi == b
+    while (hi - lo >= 8) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if (edges[mid].y > c) hi = mid;
+        else lo = mid + 1;
+    }
+    uint2 r[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint64_t e = lo + i;
+        r[i] = (e < b && e <= hi) ? edges[e] : make_uint2(0u, 0u);
+    }
+    uint64_t pick = b;
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+        if (r[i].y > c) {
+            pick = lo + i;
+            u = r[i].x;
+        }
+    }
+    return pick;
+}
+
+template <int kMode>
+__global__ __launch_bounds__(kLtWaves *kWave) void lt_main_kernel(Params p) {
+    __shared__ uint32_t s_bloom[kLtWaves][kBloomWords][kWave];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint32_t *bl = &s_bloom[wave][0][lane];
+    const Stream st(p.key);
+
+    bool active = false, finished = false;
+    uint32_t t = 0, v = 0, len = 0;
+    uint64_t s = 0;
+    uint32_t *region = nullptr;
+    uint64_t edges_acc = 0, nodes_acc = 0;
+
+    for (;;) {
+        const bool need = !active && !finished;
+        const uint64_t mask = __ballot(need);
+        if (mask) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&p.cnt->ticket, static_cast<uint32_t>(__popcll(mask)));
+            base = __shfl(base, 0, kWave);
+            if (need) {
+                const uint32_t mine = base + lanes_below(mask);
+                if (mine < p.count) {
+                    t = mine;
+                    s = p.s0 + t;
+                    v = pick_source(st, s, p.src_cum, p.n);
+                    region = p.stage + static_cast<uint64_t>(t) * p.lt_cap;
+                    region[0] = v;
+                    len = 1;
+#pragma unroll
+                    for (int w = 0; w < kBloomWords; ++w) bl[w * kWave] = 0u;
+                    bloom_insert(bl, v);
+                    active = true;
+                    if (kMode == 1 && test_bit(p.seedbits, v)) {
+                        p.z[t] = 1;
+                        edges_acc += 1;
+                        active = false;
+                    }
+                } else {
+                    finished = true;
+                }
+            }
+        }
+        // every lane without a sample just tried to take one: done when
+        // all lanes found the batch exhausted
+        if (__ballot(!finished) == 0) break;
+        if (!active) continue;
+
+        bool stop = false;
+        uint32_t u = 0;
+        const uint64_t a = p.off[v], b = p.off[v + 1];
+        if (a == b) {
+            stop = true;
+        } else {
+            const uint32_t c = lt_coin(st, s, v);
+            if (lt_pick(p.edges, a, b, c, u) == b) stop = true;
+        }
+        if (!stop && bloom_maybe(bl, u)) {
+            for (uint32_t i = 0; i < len; ++i) {
+                if (region[i] == u) {
+                    stop = true;
+                    break;
+                }
+            }
+        }
+        if (stop) {
+            if (kMode == 1) {
+                p.z[t] = 0;
+            } else {
+                p.sizes[t] = len;
+                p.stage_off[t] = static_cast<uint64_t>(t) * p.lt_cap;
+                nodes_acc += len;
+            }
+            edges_acc += len;
+            active = false;
+            continue;
+        }
+        if (len == p.lt_cap) {  // longer than the staging region: long path
+            const uint32_t d = atomicAdd(&p.cnt->defer_count, 1u);
+            p.defer_list[d] = t;
+            active = false;
+            continue;
+        }
+        region[len++] = u;
+        bloom_insert(bl, u);
+        v = u;
+        if (kMode == 1 && test_bit(p.seedbits, u)) {
+            p.z[t] = 1;
+            edges_acc += len;
+            active = false;
+        }
+    }
+    const uint64_t e_sum = wave_sum_u64(edges_acc);
+    const uint64_t n_sum = wave_sum_u64(nodes_acc);
+    if (lane == 0) {
+        if (e_sum) atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(e_sum));
+        if (n_sum) atomicAdd(&p.cnt->total_nodes, static_cast<unsigned long long>(n_sum));
+    }
+}
+
+// ----------------------------------------------------------- long path ----
+
+// One wave per slot; each slot owns vis[n] (epoch stamps) and queue[n].
+template <int kModel, int kMode>
+__global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint32_t *slot_mem, uint64_t n_stride,
+                                                                 uint32_t nslots, uint32_t *slot_epoch) {
+    __shared__ uint32_t s_pre[kLongWaves][kWave];
+    __shared__ uint64_t s_a[kLongWaves][kWave];
+    __shared__ uint64_t s_b[kLongWaves][kWave];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t slot = blockIdx.x * kLongWaves + wave;
+    if (slot >= nslots) return;
+    uint32_t *vis = slot_mem + static_cast<uint64_t>(slot) * 2 * n_stride;
+    uint32_t *queue = vis + n_stride;
+    uint32_t *pre = s_pre[wave];
+    uint64_t *fa = s_a[wave];
+    uint64_t *fb = s_b[wave];
+    const Stream st(p.key);
+    uint64_t edges_acc = 0, nodes_acc = 0;
+
+    for (;;) {
+        uint32_t d = 0;
+        if (lane == 0) d = atomicAdd(&p.cnt->defer_ticket, 1u);
+        d = __shfl(d, 0, kWave);
+        if (d >= p.cnt->defer_count) break;
+        const uint32_t t = p.defer_list[d];
+        const uint64_t s = p.s0 + t;
+        uint32_t stamp = 0;
+        if (lane == 0) stamp = ++slot_epoch[slot];
+        stamp = __shfl(stamp, 0, kWave);
+        const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
+        bool hit = (kMode == 1) && test_bit(p.seedbits, v0);
+        uint32_t tail = 1;
+        uint64_t sample_edges = 0;
+        if (lane == 0) {
+            queue[0] = v0;
+            vis[v0] = stamp;
+        }
+        wave_sync();
+        if (kModel == IM_LT) {
+            // the walk runs on lane 0; the other lanes wait
+            if (lane == 0 && !hit) {
+                uint32_t v = v0;
+                for (;;) {
+                    sample_edges += 1;
+                    const uint64_t a = p.off[v], b = p.off[v + 1];
+                    if (a == b) break;
+                    uint32_t u = 0;
+                    if (lt_pick(p.edges, a, b, lt_coin(st, s, v), u) == b) break;
+                    if (vis[u] == stamp) break;
+                    vis[u] = stamp;
+                    queue[tail++] = u;
+                    v = u;
+                    if (kMode == 1 && test_bit(p.seedbits, u)) {
+                        hit = true;
+                        break;
+                    }
+                }
+            }
+            tail = __shfl(tail, 0, kWave);
+            hit = __shfl(static_cast<int>(hit), 0, kWave) != 0;
+            sample_edges = __shfl(sample_edges, 0, kWave);
+        } else {
+            uint32_t head = 0;
+            while (head < tail && !hit) {
+                const uint32_t nb = min(tail - head, static_cast<uint32_t>(kWave));
+                uint32_t cg = 0;
+                uint64_t a = 0, b = 0;
+                if (lane < nb) {
+                    const uint32_t v = queue[head + lane];
+                    a = p.off[v];
+                    b = p.off[v + 1];
+                    if (b > a) cg = static_cast<uint32_t>(((b - 1) >> 2) - (a >> 2) + 1);
+                }
+                const uint32_t inc = wave_inclusive_scan(cg);
+                const uint32_t groups = __shfl(inc, kWave - 1, kWave);
+                sample_edges += wave_sum_u64(b - a);
+                pre[lane] = inc - cg;
+                fa[lane] = a;
+                fb[lane] = b;
+                head += nb;
+                wave_sync();
+                for (uint32_t base = 0; base < groups; base += kWave) {
+                    const uint32_t w = base + lane;
+                    uint32_t f[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+                    if (w < groups) {
+                        uint32_t lo = 0, hi = nb - 1;
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi + 1) >> 1;
+                            if (pre[mid] <= w) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const uint64_t ea = fa[lo], eb = fb[lo];
+                        const uint64_t g = (ea >> 2) + (w - pre[lo]);
+                        const uint4 coins = ic_coins(st, s, g);
+#pragma unroll
+                        for (uint32_t q = 0; q < 4; ++q) {
+                            const uint64_t e = (g << 2) + q;
+                            if (e >= ea && e < eb) {
+                                const uint2 rec = p.edges[e];
+                                if (ic_live(word_of(coins, q), rec.y) && atomicExch(&vis[rec.x], stamp) != stamp)
+                                    f[q] = rec.x;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) {
+                        const bool has = f[q] != 0xFFFFFFFFu;
+                        const uint64_t mask = __ballot(has);
+                        if (mask) {
+                            if (has) {
+                                queue[tail + lanes_below(mask)] = f[q];
+                                if (kMode == 1 && test_bit(p.seedbits, f[q])) hit = true;
+                            }
+                            tail += static_cast<uint32_t>(__popcll(mask));
+                        }
+                    }
+                    if (kMode == 1) hit = __ballot(hit) != 0;
+                    if (hit) break;
+                }
+                __threadfence_block();
+                wave_sync();
+            }
+        }
+        if (kMode == 1) {
+            if (lane == 0) p.z[t] = hit ? 1 : 0;
+            edges_acc += sample_edges;
+        } else {
+            unsigned long long base = 0;
+            if (lane == 0) {
+                base = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(tail));
+                if (base + tail > p.stage_cap) {
+                    atomicOr(&p.cnt->overflow, 1u);
+                    p.sizes[t] = 0;
+                    p.stage_off[t] = 0;
+                } else {
+                    p.sizes[t] = tail;
+                    p.stage_off[t] = base;
+                }
+            }
+            base = __shfl(base, 0, kWave);
+            __threadfence_block();
+            wave_sync();
+            if (base + tail <= p.stage_cap)
+                for (uint32_t i = lane; i < tail; i += kWave) p.stage[base + i] = queue[i];
+            edges_acc += sample_edges;
+            nodes_acc += tail;
+        }
+        wave_sync();
+    }
+    if (lane == 0) {
+        if (edges_acc) atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(edges_acc));
+        if (nodes_acc) atomicAdd(&p.cnt->total_nodes, static_cast<unsigned long long>(nodes_acc));
+    }
+}
+
+// ---------------------------------------------------------- pool append ----
+
+constexpr int kScanThreads = 256;
+constexpr int kScanTile = 1024;  // 4 items per thread
+
+__device__ __forceinline__ uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t *smem, uint64_t &total) {
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint64_t inc = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d, kWave);
+        if (lane >= static_cast<uint32_t>(d)) inc += y;
+    }
+    if (lane == kWave - 1) smem[wave] = inc;
+    __syncthreads();
+    uint64_t wave_off = 0, tot = 0;
+    const uint32_t nw = blockDim.x / kWave;
+    for (uint32_t w = 0; w < nw; ++w) {
+        if (w < wave) wave_off += smem[w];
+        tot += smem[w];
+    }
+    __syncthreads();
+    total = tot;
+    return wave_off + inc - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t *in, uint64_t count, uint64_t *tile_sum) {
+    __shared__ uint64_t smem[kScanThreads / kWave];
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 4;
+    uint64_t x = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (base + i < count) x += in[base + i];
+    uint64_t total = 0;
+    block_exclusive_scan_u64(x, smem, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of tile sums in place (any length).
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t *tile_sum, uint64_t tiles) {
+    __shared__ uint64_t smem[1024 / kWave];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t b0 = 0; b0 < tiles; b0 += blockDim.x) {
+        const uint64_t i = b0 + threadIdx.x;
+        const uint64_t x = i < tiles ? tile_sum[i] : 0;
+        uint64_t total = 0;
+        const uint64_t ex = block_exclusive_scan_u64(x, smem, total);
+        if (i < tiles) tile_sum[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+}
+
+// out[i+1] = base + sum(in[0..i]) ; out[0] written by the caller's layout.
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t *in, uint64_t count,
+                                                                   const uint64_t *tile_off, uint64_t base,
+                                                                   uint64_t *out) {
+    __shared__ uint64_t smem[kScanThreads / kWave];
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 4;
+    uint64_t v[4];
+    uint64_t x = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (b0 + i < count) ? in[b0 + i] : 0;
+        x += v[i];
+    }
+    uint64_t total = 0;
+    uint64_t run = base + tile_off[blockIdx.x] + block_exclusive_scan_u64(x, smem, total);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        run += v[i];
+        if (b0 + i < count) out[b0 + i + 1] = run;
+    }
+}
+
+__global__ void set_first_kernel(uint64_t *out, uint64_t value) { out[0] = value; }
+
+// 16 lanes per sample copy its set from staging into the pool.
+__global__ __launch_bounds__(256) void compact_kernel(const uint32_t *stage, const uint64_t *stage_off,
+                                                      const uint64_t *poff, uint32_t *pnodes, uint64_t count) {
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t group = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+    const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (uint64_t i = group; i < count; i += groups) {
+        const uint64_t dst = poff[i];
+        const uint64_t len = poff[i + 1] - dst;
+        const uint32_t *src = stage + stage_off[i];
+        for (uint64_t j = sub; j < len; j += 16) pnodes[dst + j] = src[j];
+    }
+}
+
+__global__ void copy_u64_kernel(const uint64_t *src, uint64_t *dst, uint64_t count) {
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void copy_u32_kernel(const uint32_t *src, uint32_t *dst, uint64_t count) {
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
+uint32_t blocks_for(uint64_t items, uint32_t per_block, uint32_t cap) {
+    uint64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return static_cast<uint32_t>(b);
+}
+
+// Per-sample metadata layout inside ctx->sample_meta for `count` samples.
+struct Meta {
+    uint64_t *stage_off;
+    uint32_t *sizes;
+    uint32_t *defer_list;
+    uint8_t *z;
+};
+
+size_t meta_bytes(uint64_t count) { return count * (8 + 4 + 4 + 1) + 256; }
+
+Meta meta_view(im_ctx *ctx, uint64_t count) {
+    Meta m;
+    char *base = static_cast<char *>(ctx->sample_meta.ptr);
+    m.stage_off = reinterpret_cast<uint64_t *>(base);
+    m.sizes = reinterpret_cast<uint32_t *>(base + count * 8);
+    m.defer_list = reinterpret_cast<uint32_t *>(base + count * 12);
+    m.z = reinterpret_cast<uint8_t *>(base + count * 16);
+    return m;
+}
+
+}  // namespace
+
+namespace im {
+
+// Long-path slot arrays for a graph of n nodes: each slot holds vis[n]
+// (epoch stamps, zeroed once) and queue[n].
+static im_status ensure_slots(im_ctx *ctx, uint32_t n) {
+    const uint64_t per_slot = 2ull * n * 4;
+    const uint64_t budget = std::min<uint64_t>(8ull << 30, ctx->total_mem / 16);
+    uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>(1024, budget / std::max<uint64_t>(per_slot, 1)));
+    if (ctx->slots.ptr && ctx->slot_n == n && ctx->slot_count == want && ctx->slot_epoch < 0xF0000000ull)
+        return IM_OK;
+    dev_free(ctx, ctx->slots);
+    IM_TRY(dev_alloc(ctx, ctx->slots, want * per_slot + want * 4 + 256));
+    IM_HIP(hipMemsetAsync(ctx->slots.ptr, 0, want * per_slot + want * 4 + 256, ctx->stream));
+    ctx->slot_n = n;
+    ctx->slot_count = static_cast<uint32_t>(want);
+    ctx->slot_epoch = 0;
+    return IM_OK;
+}
+
+im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t key, uint64_t s0,
+                       uint64_t count, SampleMode mode, double size_hint, SampleResult *res) {
+    *res = SampleResult{};
+    if (count == 0) return IM_OK;
+    if (count > 0xFFFFFFF0ull) {
+        set_error("sample batch of %llu samples is too large", static_cast<unsigned long long>(count));
+        return IM_E_ARG;
+    }
+    const DevBuf &edges = (model == IM_IC) ? g->edges_ic : g->edges_lt;
+    hipStream_t st = ctx->stream;
+    IM_TRY(dev_reserve(ctx, ctx->sample_meta, meta_bytes(count)));
+    IM_TRY(dev_reserve(ctx, ctx->counters, 256));
+    if (mode == SampleMode::Hits) IM_TRY(dev_reserve(ctx, ctx->zflags, count + 64));
+    IM_TRY(ensure_slots(ctx, g->n));
+    Meta meta = meta_view(ctx, count);
+    auto *cnt = static_cast<Counters *>(ctx->counters.ptr);
+
+    // staging capacity: LT reserves a region per sample, then a bump area
+    // for long walks; IC bump-allocates every set.
+    const double hint = size_hint > 0 ? size_hint : (model == IM_IC ? 16.0 : 64.0);
+    uint64_t lt_regions = (model == IM_LT) ? count * kLtCap : 0;
+    uint64_t cap = lt_regions + static_cast<uint64_t>(std::ceil(hint * 1.5 * count)) + (1u << 20);
+    if (mode == SampleMode::Hits && model == IM_IC) cap = 0;
+
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        if (cap) IM_TRY(dev_reserve(ctx, ctx->stage, cap * 4));
+        Params p{};
+        p.off = static_cast<const uint64_t *>(g->off.ptr);
+        p.edges = static_cast<const uint2 *>(edges.ptr);
+        p.src_cum = static_cast<const uint64_t *>(g->src_cum.ptr);
+        p.n = g->n;
+        p.count = static_cast<uint32_t>(count);
+        p.key = key;
+        p.s0 = s0;
+        p.cnt = cnt;
+        p.defer_list = meta.defer_list;
+        p.stage = static_cast<uint32_t *>(ctx->stage.ptr);
+        p.stage_cap = cap;
+        p.stage_off = meta.stage_off;
+        p.sizes = meta.sizes;
+        p.z = (mode == SampleMode::Hits) ? static_cast<uint8_t *>(ctx->zflags.ptr) : meta.z;
+        p.seedbits = static_cast<const uint32_t *>(ctx->seedbits.ptr);
+        p.lt_cap = kLtCap;
+
+        init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
+        const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+        if (model == IM_IC) {
+            const uint32_t grid = blocks_for(count, kIcWaves, cu * 8);
+            const bool bitmap = g->n <= kBitmapMaxN;
+            if (mode == SampleMode::Pool) {
+                if (bitmap) ic_main_kernel<0, true><<<grid, kIcWaves * kWave, 0, st>>>(p);
+                else ic_main_kernel<0, false><<<grid, kIcWaves * kWave, 0, st>>>(p);
+            } else {
+                if (bitmap) ic_main_kernel<1, true><<<grid, kIcWaves * kWave, 0, st>>>(p);
+                else ic_main_kernel<1, false><<<grid, kIcWaves * kWave, 0, st>>>(p);
+            }
+        } else {
+            const uint32_t grid = blocks_for(count, kLtWaves * kWave, cu * 8);
+            if (mode == SampleMode::Pool) lt_main_kernel<0><<<grid, kLtWaves * kWave, 0, st>>>(p);
+            else lt_main_kernel<1><<<grid, kLtWaves * kWave, 0, st>>>(p);
+        }
+        {
+            const uint32_t nslots = ctx->slot_count;
+            const uint32_t grid = (nslots + kLongWaves - 1) / kLongWaves;
+            auto *slot_mem = static_cast<uint32_t *>(ctx->slots.ptr);
+            auto *epochs = slot_mem + 2ull * g->n * nslots;
+            if (model == IM_IC) {
+                if (mode == SampleMode::Pool) long_kernel<IM_IC, 0><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
+                else long_kernel<IM_IC, 1><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
+            } else {
+                if (mode == SampleMode::Pool) long_kernel<IM_LT, 0><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
+                else long_kernel<IM_LT, 1><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
+            }
+        }
+        IM_HIP(hipGetLastError());
+        Counters hc{};
+        IM_TRY(to_host_sync(ctx, &hc, cnt, sizeof(hc)));
+        ctx->slot_epoch += hc.defer_count;
+        if (hc.overflow) {
+            cap = std::max<uint64_t>(cap * 2, hc.stage_cursor + (1u << 20));
+            continue;
+        }
+        res->total_nodes = hc.total_nodes;
+        res->edges = hc.edges;
+        res->deferred = hc.defer_count;
+        return IM_OK;
+    }
+    set_error("sampler staging kept overflowing");
+    return IM_E_OOM;
+}
+
+static im_status grow_pool(im_pool *p, uint64_t need_sets, uint64_t need_nodes) {
+    im_ctx *ctx = p->ctx;
+    hipStream_t st = ctx->stream;
+    if (need_sets > p->cap_sets) {
+        size_t cap = std::max<size_t>(need_sets, p->cap_sets * 2);
+        DevBuf nb;
+        IM_TRY(dev_alloc(ctx, nb, (cap + 1) * 8));
+        if (p->poff.ptr) {
+            copy_u64_kernel<<<blocks_for(p->count + 1, 256, 4096), 256, 0, st>>>(
+                static_cast<const uint64_t *>(p->poff.ptr), static_cast<uint64_t *>(nb.ptr), p->count + 1);
+        } else {
+            set_first_kernel<<<1, 1, 0, st>>>(static_cast<uint64_t *>(nb.ptr), 0);
+        }
+        IM_HIP(hipStreamSynchronize(st));
+        dev_free(ctx, p->poff);
+        p->poff = nb;
+        p->cap_sets = cap;
+    }
+    if (need_nodes > p->cap_nodes) {
+        size_t cap = std::max<size_t>(need_nodes, p->cap_nodes * 2);
+        DevBuf nb;
+        IM_TRY(dev_alloc(ctx, nb, cap * 4));
+        if (p->pnodes.ptr && p->total)
+            copy_u32_kernel<<<blocks_for(p->total, 256, 4096), 256, 0, st>>>(
+                static_cast<const uint32_t *>(p->pnodes.ptr), static_cast<uint32_t *>(nb.ptr), p->total);
+        IM_HIP(hipStreamSynchronize(st));
+        dev_free(ctx, p->pnodes);
+        p->pnodes = nb;
+        p->cap_nodes = cap;
+    }
+    return IM_OK;
+}
+
+im_status pool_append_staged(im_pool *p, uint64_t count, uint64_t total_nodes) {
+    if (count == 0) return IM_OK;
+    im_ctx *ctx = p->ctx;
+    hipStream_t st = ctx->stream;
+    IM_TRY(grow_pool(p, p->count + count, p->total + total_nodes + 1));
+    Meta meta = meta_view(ctx, count);
+    const uint64_t tiles = (count + kScanTile - 1) / kScanTile;
+    IM_TRY(dev_reserve(ctx, ctx->scan_tmp, (tiles + 1) * 8));
+    auto *tsum = static_cast<uint64_t *>(ctx->scan_tmp.ptr);
+    auto *poff = static_cast<uint64_t *>(p->poff.ptr) + p->count;  // poff[count] already holds p->total
+    scan_tiles_kernel<<<static_cast<uint32_t>(tiles), kScanThreads, 0, st>>>(meta.sizes, count, tsum);
+    scan_sums_kernel<<<1, 1024, 0, st>>>(tsum, tiles);
+    scan_apply_kernel<<<static_cast<uint32_t>(tiles), kScanThreads, 0, st>>>(meta.sizes, count, tsum, p->total, poff);
+    compact_kernel<<<blocks_for(count * 16, 256, static_cast<uint32_t>(ctx->cu_count) * 16), 256, 0, st>>>(
+        static_cast<const uint32_t *>(ctx->stage.ptr), meta.stage_off, poff, static_cast<uint32_t *>(p->pnodes.ptr),
+        count);
+    IM_HIP(hipGetLastError());
+    uint64_t end = 0;
+    IM_TRY(to_host_sync(ctx, &end, poff + count, 8));
+    if (end != p->total + total_nodes) {
+        set_error("pool append: offsets end at %llu, expected %llu", static_cast<unsigned long long>(end),
+                  static_cast<unsigned long long>(p->total + total_nodes));
+        return IM_E_DEVICE;
+    }
+    p->count += count;
+    p->total = end;
+    return IM_OK;
+}
+
+}  // namespace im

@@ -141,6 +141,7 @@ RECIPES = {
     "rmat16": dict(kind="rmat", scale=16, draws=16 << 16, abc=(0.57, 0.19, 0.19), seed=13,
                    ic="wc", lt="uniform"),
     "cl_mid": dict(kind="chung_lu", n=200_000, m=2_000_000, gamma=2.0, seed=14, ic="wc", lt="uniform"),
+    "cl_20k": dict(kind="chung_lu", n=20_000, m=120_000, gamma=2.1, seed=15, ic="wc", lt="uniform"),
 }
 
 

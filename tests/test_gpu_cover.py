@@ -1,0 +1,110 @@
+"""GPU parity of Max-Coverage (Algorithm 2), coverage counts (Eq. 1) and
+Estimate-Inf (Algorithm 3) against the oracle: identical seeds (ties to the
+lowest id), identical integer coverage, identical stopping index T."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def im():
+    from paper_1605_07990_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(im):
+    return im.Context(0)
+
+
+@pytest.fixture(scope="module")
+def pools(im, ctx, oracle_lib):
+    out = {}
+    for name, model, count, key in (("nethept", 0, 40000, 1), ("rmat16", 1, 30000, 2), ("cl_small", 1, 8000, 3)):
+        g = synth.make(name)
+        w = g.w_ic if model == 0 else g.w_lt
+        dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
+        og = oracle_lib.Graph(model, g.n, g.src, g.dst, w)
+        p = im.Pool(dg, model, key)
+        p.sample(count)
+        op = oracle_lib.Pool(og, key)
+        op.extend(count)
+        out[name] = (g, dg, og, p, op)
+    return out
+
+
+@pytest.mark.parametrize("name", ["nethept", "rmat16", "cl_small"])
+@pytest.mark.parametrize("k", [1, 7, 50, 200])
+def test_max_coverage_matches_oracle(pools, name, k):
+    g, dg, og, p, op = pools[name]
+    note(f"max coverage {name} k={k}")
+    seeds, cov = p.max_coverage(k)
+    oseeds, ocov = op.max_coverage(k)
+    assert cov == ocov
+    assert seeds.tolist() == oseeds.tolist()
+
+
+@pytest.mark.parametrize("name", ["nethept", "rmat16"])
+def test_ranges_and_coverage(pools, name):
+    g, dg, og, p, op = pools[name]
+    c = p.count
+    note(f"coverage ranges {name}")
+    for begin, end, k in ((0, c // 2, 20), (c // 2, c, 20), (1234, 1234 + 4097, 5), (7, 8, 3), (100, 100, 2)):
+        seeds, cov = p.max_coverage(k, begin, end)
+        oseeds, ocov = op.max_coverage(k, begin, end)
+        assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (begin, end, k)
+        assert p.coverage(seeds, 0, c) == op.coverage(seeds, 0, c)
+        assert p.coverage(seeds, end, c) == op.coverage(seeds, end, c)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        S = rng.choice(g.n, size=int(rng.integers(1, 40)), replace=False)
+        assert p.coverage(S, 0, c) == op.coverage(S, 0, c)
+    assert p.coverage(np.arange(g.n), 0, c) == c
+
+
+def test_k_equals_n_and_errors(im, ctx, oracle_lib):
+    note("k = n and bad k")
+    n = 40
+    e = np.array([], np.uint32)
+    dg = im.Graph(ctx, n, e, e, w_ic=np.array([], np.float32))
+    og = oracle_lib.Graph(0, n, e, e, np.array([], np.float32))
+    p = im.Pool(dg, 0, 5)
+    p.sample(300)
+    op = oracle_lib.Pool(og, 5)
+    op.extend(300)
+    seeds, cov = p.max_coverage(n)
+    oseeds, ocov = op.max_coverage(n)
+    assert seeds.tolist() == oseeds.tolist() and cov == ocov == 300
+    with pytest.raises(im.ImError):
+        p.max_coverage(n + 1)
+    with pytest.raises(im.ImError):
+        p.max_coverage(0)
+
+
+@pytest.mark.parametrize("name,model", [("nethept", 0), ("rmat16", 1), ("cl_small", 0), ("cl_small", 1)])
+def test_estimate_inf_matches_oracle(im, ctx, oracle_lib, name, model):
+    g = synth.make(name)
+    w = g.w_ic if model == 0 else g.w_lt
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
+    og = oracle_lib.Graph(model, g.n, g.src, g.dst, w)
+    rng = np.random.default_rng(1)
+    note(f"estimate-inf {name} model={model}")
+    cases = [(rng.choice(g.n, size=10, replace=False), 0.1, 1e-3, 1e9, 31),
+             (rng.choice(g.n, size=3, replace=False), 0.2, 0.01, 1e9, 32),
+             (np.arange(g.n), 0.15, 1e-4, 1e9, 33),
+             (rng.choice(g.n, size=5, replace=False), 0.1, 1e-3, 5000.7, 34)]
+    for S, e, d, tmax, key in cases:
+        ic, T = dg.estimate_inf(model, S, e, d, tmax, key)
+        oic, oT = og.estimate_inf(S, e, d, tmax, key)
+        assert T == oT, (S[:5], e, d, tmax, T, oT)
+        assert ic == oic
+    # all nodes: the count is reached exactly at ceil(Lambda2)
+    ic, T = dg.estimate_inf(model, np.arange(g.n), 0.2, 0.01, 1e9, 40)
+    lam2 = 1 + 1.2 * oracle_lib.upsilon(0.2, 0.01)
+    assert T == math.ceil(lam2)

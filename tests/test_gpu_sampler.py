@@ -1,0 +1,181 @@
+"""GPU parity of RR-set sampling (Definition 2): pools from the HIP sampler
+must equal the oracle's bit for bit (offsets exactly, every set as a sorted
+list), across graph shapes, both models, the LDS bitmap / LDS hash / long
+paths, ragged batches and appends."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import assert_pool_equal, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def im():
+    from paper_1605_07990_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(im):
+    return im.Context(0)
+
+
+def _graphs(im, ctx, oracle_lib, name, w_ic=None, w_lt=None):
+    g = synth.make(name)
+    w_ic = g.w_ic if w_ic is None else w_ic
+    w_lt = g.w_lt if w_lt is None else w_lt
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w_ic, w_lt=w_lt)
+    ogs = {}
+    if w_ic is not None:
+        ogs[0] = oracle_lib.Graph(0, g.n, g.src, g.dst, w_ic)
+    if w_lt is not None:
+        ogs[1] = oracle_lib.Graph(1, g.n, g.src, g.dst, w_lt)
+    return g, dg, ogs
+
+
+@pytest.mark.parametrize("name,model,count,key", [
+    ("cl_small", 0, 20000, 1),
+    ("cl_small", 1, 20000, 2),
+    ("nethept", 0, 30000, 0),
+    ("nethept", 1, 30000, 5),
+    ("rmat12", 0, 20000, 3),
+    ("rmat12", 1, 20000, 4),
+    ("rmat16", 1, 20000, 6),
+    ("rmat16", 0, 3000, 7),
+])
+def test_pool_matches_oracle(im, ctx, oracle_lib, name, model, count, key):
+    note(f"pool parity {name} model={model} count={count} key={key}")
+    g, dg, ogs = _graphs(im, ctx, oracle_lib, name)
+    pool = im.Pool(dg, model, key)
+    pool.sample(count)
+    op = oracle_lib.Pool(ogs[model], key)
+    op.extend(count)
+    assert pool.count == count
+    assert_pool_equal(pool, op, 0, count)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_appends_and_ragged_batches(im, ctx, oracle_lib, model):
+    note(f"ragged appends model={model}")
+    g, dg, ogs = _graphs(im, ctx, oracle_lib, "cl_small")
+    pool = im.Pool(dg, model, 11)
+    op = oracle_lib.Pool(ogs[model], 11)
+    total = 0
+    for c in (1, 0, 63, 64, 65, 255, 1023, 1025, 4097, 3):
+        pool.sample(c)
+        total += c
+    op.extend(total)
+    assert pool.count == total
+    assert_pool_equal(pool, op, 0, total)
+    assert_pool_equal(pool, op, 100, 2000)
+
+
+def test_long_path_ic_ancestors(im, ctx, oracle_lib):
+    # p = 1 everywhere: RR sets are whole ancestor sets, far above the LDS
+    # queue, so every non-trivial sample takes the global long path.
+    g = synth.make("cl_20k")
+    w = np.ones(g.m, np.float32)
+    note("long path IC p=1 cl_20k")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w)
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, w)
+    pool = im.Pool(dg, 0, 21)
+    pool.sample(300)
+    op = oracle_lib.Pool(og, 21)
+    op.extend(300)
+    assert_pool_equal(pool, op, 0, 300)
+    assert int(np.diff(op.offsets()).max()) > 4 * 1024  # sets far above the LDS queue
+
+
+def test_long_path_lt_walks(im, ctx, oracle_lib):
+    # a path 0 -> 1 -> ... -> n-1 with w = 1: the walk from v has v+1 nodes,
+    # so most walks outgrow the per-sample staging region.
+    n = 3000
+    src = np.arange(0, n - 1, dtype=np.uint32)
+    dst = np.arange(1, n, dtype=np.uint32)
+    w = np.ones(n - 1, np.float32)
+    note("long path LT path graph")
+    dg = im.Graph(ctx, n, src, dst, w_lt=w)
+    og = oracle_lib.Graph(1, n, src, dst, w)
+    pool = im.Pool(dg, 1, 22)
+    pool.sample(700)
+    op = oracle_lib.Pool(og, 22)
+    op.extend(700)
+    assert_pool_equal(pool, op, 0, 700)
+
+
+def test_hash_visited_large_n(im, ctx, oracle_lib):
+    # n > 65536 uses the LDS hash; IC on an R-MAT-20 graph
+    g, dg, ogs = _graphs(im, ctx, oracle_lib, "rmat20")
+    note("rmat20 IC hash path")
+    pool = im.Pool(dg, 0, 9)
+    pool.sample(2000)
+    op = oracle_lib.Pool(ogs[0], 9)
+    op.extend(2000)
+    assert_pool_equal(pool, op, 0, 2000)
+
+
+def test_edge_cases(im, ctx, oracle_lib):
+    note("edge cases: edgeless graph, single node, zero-weight edges")
+    # no edges: every set is its source
+    n = 50
+    e = np.array([], np.uint32)
+    dg = im.Graph(ctx, n, e, e, w_ic=np.array([], np.float32), w_lt=np.array([], np.float32))
+    for model in (0, 1):
+        og = oracle_lib.Graph(model, n, e, e, np.array([], np.float32))
+        pool = im.Pool(dg, model, 3)
+        pool.sample(500)
+        op = oracle_lib.Pool(og, 3)
+        op.extend(500)
+        assert_pool_equal(pool, op, 0, 500)
+    # one node
+    d1 = im.Graph(ctx, 1, e, e, w_ic=np.array([], np.float32))
+    p1 = im.Pool(d1, 0, 0)
+    p1.sample(10)
+    off, nodes = p1.read()
+    assert off.tolist() == list(range(11)) and nodes.tolist() == [0] * 10
+    # zero weights: singletons
+    g = synth.make("cl_small")
+    z = np.zeros(g.m, np.float32)
+    dz = im.Graph(ctx, g.n, g.src, g.dst, w_ic=z, w_lt=z)
+    for model in (0, 1):
+        pool = im.Pool(dz, model, 4)
+        pool.sample(1000)
+        off, _ = pool.read()
+        assert np.all(np.diff(off) == 1)
+
+
+def test_weighted_sources(im, ctx, oracle_lib):
+    g = synth.make("cl_small")
+    wts = synth.node_weights(g.n, 0.2, 2.1, 5)
+    note("weighted sources (WRIS)")
+    for model, w in ((0, g.w_ic), (1, g.w_lt)):
+        dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
+        dg.set_source_weights(wts)
+        og = oracle_lib.Graph(model, g.n, g.src, g.dst, w, node_weights=wts)
+        pool = im.Pool(dg, model, 8)
+        pool.sample(5000)
+        op = oracle_lib.Pool(og, 8)
+        op.extend(5000)
+        assert_pool_equal(pool, op, 0, 5000)
+
+
+def test_stream_mismatch_and_bad_graphs(im, ctx):
+    note("error paths")
+    g = synth.make("cl_small")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    pool = im.Pool(dg, 0, 1)
+    with pytest.raises(im.ImError) as e:
+        pool.sample(10, key=2)
+    assert e.value.status == -5
+    with pytest.raises(im.ImError):
+        im.Pool(dg, 1, 1)  # no LT weights
+    with pytest.raises(im.ImError) as e:
+        im.Graph(ctx, 3, np.array([1, 2], np.uint32), np.array([0, 0], np.uint32),
+                 w_lt=np.array([0.7, 0.7], np.float32))
+    assert e.value.status == -3
+    with pytest.raises(im.ImError) as e:
+        im.Graph(ctx, 3, np.array([2, 1], np.uint32), np.array([0, 0], np.uint32),
+                 w_ic=np.array([0.5, 0.5], np.float32))
+    assert e.value.status == -1
