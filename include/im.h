@@ -205,6 +205,33 @@ im_status im_ssa(const im_graph *g, im_model model, uint32_t k, double eps, doub
 im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
                   uint32_t *seeds_out, im_stats *st);
 
+/*
+ * Kernel timing for measurement. When enabled on a context, every launch of
+ * the main RR-set sampler kernel (the pass that draws the RR sets of
+ * Definition 2 into staging) is bracketed by HIP events on the context's
+ * stream; im_ctx_read_timing returns the totals since the last reset.
+ *   sample_launches  number of timed sampler launches
+ *   sample_ms        sum of their event-measured durations
+ *   sample_sets      RR sets those launches completed (deferred ones excluded)
+ *   sample_steps     their edges traversed: IC in-edges examined, LT nodes
+ *                    whose in-list was consulted (walk steps)
+ *   sample_nodes     node entries of the sets they completed
+ *   model            model of the last timed launch (IM_IC or IM_LT)
+ * Errors: IM_E_ARG (null handle), IM_E_DEVICE.
+ */
+typedef struct im_kernel_times {
+    uint64_t sample_launches;
+    double sample_ms;
+    uint64_t sample_sets;
+    uint64_t sample_steps;
+    uint64_t sample_nodes;
+    int32_t model;
+    int32_t reserved;
+} im_kernel_times;
+
+im_status im_ctx_set_timing(im_ctx *ctx, int enable);
+im_status im_ctx_read_timing(im_ctx *ctx, im_kernel_times *out, int reset);
+
 /* The stream key of SSA iteration i's verification pool, derived from key. */
 uint64_t im_derived_key(uint64_t key, uint64_t i);
 

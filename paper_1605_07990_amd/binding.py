@@ -8,6 +8,7 @@ it on a machine without the built library raises at once.
 from __future__ import annotations
 
 import ctypes
+import sys
 from dataclasses import dataclass
 from pathlib import Path
 
@@ -27,7 +28,7 @@ STATUS = {0: "IM_OK", -1: "IM_E_ARG", -2: "IM_E_OOM", -3: "IM_E_LT_WEIGHTS", -4:
 EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source_weights", "im_graph_free",
            "im_graph_info", "im_pool_create", "im_pool_free", "im_sample_rr", "im_pool_info", "im_pool_read",
            "im_pool_device", "im_max_coverage", "im_max_coverage_range", "im_coverage_range", "im_estimate_inf",
-           "im_ssa", "im_dssa", "im_derived_key", "im_last_error"]
+           "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing"]
 
 
 class ImError(RuntimeError):
@@ -59,10 +60,24 @@ class Stats(ctypes.Structure):
                     ms_total=self.ms_total)
 
 
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("sample_launches", ctypes.c_uint64), ("sample_ms", ctypes.c_double),
+                ("sample_sets", ctypes.c_uint64), ("sample_steps", ctypes.c_uint64),
+                ("sample_nodes", ctypes.c_uint64), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 _lib = None
+
+
+def _no_torch() -> bool:
+    import os
+    return os.environ.get("IM_NO_TORCH", "") == "1"
 
 
 def load_library(path: Path | str | None = None):
@@ -76,10 +91,13 @@ def load_library(path: Path | str | None = None):
     # torch ships its own HIP runtime (SONAME libamdhip64.so.7) and asks for
     # it under an unversioned name; loading torch first lets libim's
     # dependency resolve to that same runtime instead of a second copy.
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    # IM_NO_TORCH=1 keeps torch out of the process (the library then uses
+    # the system HIP runtime, hipMalloc and the null stream).
+    if not _no_torch():
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     lib = ctypes.CDLL(str(p))
     vp, u32p, u64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
     f32p, f64p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
@@ -108,6 +126,8 @@ def load_library(path: Path | str | None = None):
                          u32p, ctypes.POINTER(Stats)]),
         "im_derived_key": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
         "im_last_error": (ctypes.c_char_p, []),
+        "im_ctx_set_timing": (st, [vp, ctypes.c_int]),
+        "im_ctx_read_timing": (st, [vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -140,8 +160,10 @@ class Context:
     """im_ctx on one HIP device, queued on torch's current stream, allocating
     through torch's caching allocator."""
 
-    def __init__(self, device: int = 0, use_torch: bool = True):
+    def __init__(self, device: int = 0, use_torch: bool | None = None):
         lib = load_library()
+        if use_torch is None:
+            use_torch = not _no_torch()
         self.device = device
         stream = None
         self._alloc = ALLOC_FN()
@@ -167,12 +189,24 @@ class Context:
         _check(lib.im_ctx_create(device, stream, self._alloc, self._free, None, ctypes.byref(h)))
         self.h = h
 
+    def set_timing(self, enable: bool = True):
+        _check(load_library().im_ctx_set_timing(self.h, 1 if enable else 0))
+
+    def read_timing(self, reset: bool = False) -> dict:
+        t = KernelTimes()
+        _check(load_library().im_ctx_read_timing(self.h, ctypes.byref(t), 1 if reset else 0))
+        return t.as_dict()
+
     def close(self):
         if getattr(self, "h", None):
             load_library().im_ctx_free(self.h)
             self.h = None
 
     def __del__(self):
+        # at interpreter exit torch may already be gone: the allocator hooks
+        # must not be called then, so the memory is left to the process exit
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -210,6 +244,8 @@ class Graph:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -251,6 +287,8 @@ class Pool:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -254,11 +254,32 @@ extern "C" im_status im_ctx_create(int device, void *stream, im_alloc_fn alloc, 
     return IM_OK;
 }
 
+extern "C" im_status im_ctx_set_timing(im_ctx *c, int enable) {
+    clear_error();
+    if (!c) return IM_E_ARG;
+    if (enable && !c->ev_begin) {
+        IM_HIP(hipEventCreate(&c->ev_begin));
+        IM_HIP(hipEventCreate(&c->ev_end));
+    }
+    c->timing = enable != 0;
+    return IM_OK;
+}
+
+extern "C" im_status im_ctx_read_timing(im_ctx *c, im_kernel_times *out, int reset) {
+    clear_error();
+    if (!c || !out) return IM_E_ARG;
+    *out = c->times;
+    if (reset) c->times = im_kernel_times{};
+    return IM_OK;
+}
+
 extern "C" void im_ctx_free(im_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
+    if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits,
-                      &c->zflags})
+                      &c->zflags, &c->lt_tables})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     delete c;

@@ -7,7 +7,10 @@
 //   argmax over unchosen v of (gain[v] << 32 | ~v)   (max gain, lowest id)
 //   for each not-yet-covered set of the winner: mark covered, decrement the
 //   gain of every member
-// which is linear in the total size of the sets, as the paper notes.
+// which is linear in the total size of the sets, as the paper notes. The
+// argmax reads a two-level maximum index that each round patches only where
+// the previous round's decrements landed; the first rounds (the largest
+// covers) run as grid-wide kernels, the rest in one persistent workgroup.
 #include <algorithm>
 
 #include "im_device.hpp"
@@ -133,48 +136,209 @@ __global__ __launch_bounds__(kThreads) void scatter_kernel(const uint64_t *poff,
     }
 }
 
-// ---- greedy rounds ----
+// ---- greedy: two-level maximum index over node gains ----
+//
+// gain[v] = uncovered sets of the range holding v, bit 31 = v already chosen.
+// key(v) = chosen ? 0 : gain << 32 | ~v, so the largest key is the largest
+// gain with the lowest id, and keys are unique. m1[c] caches the largest key
+// of nodes [64c, 64c+64), m2[d] the largest m1 of chunks [64d, 64d+64).
+// Keys only fall, so a cached maximum is still right exactly when the node
+// holding it still has that key; each round re-derives only the entries
+// whose holder changed.
+
+constexpr uint32_t kChosen = 0x80000000u;
+constexpr uint32_t kL1Shift = 6;  // 64 nodes per m1 entry (one 256-byte line of gains)
+constexpr uint32_t kL2Shift = 6;  // 64 m1 entries per m2 entry
+constexpr int kPersistThreads = 1024;
+constexpr uint64_t kPersistEntries = 1u << 16;  // ranges this small run all rounds in one workgroup
 
 struct GreedyState {
-    uint32_t *gain;     // uncovered sets holding v
-    uint8_t *chosen;    // 1 once v is a seed
-    uint32_t *covbits;  // covered flag per set (bit)
+    uint32_t *gain;
+    unsigned long long *m1;
+    unsigned long long *m2;
+    uint32_t *covbits;  // covered flag per set of the range
     const uint64_t *ioff;
     const uint32_t *isets;
     const uint64_t *poff;
     const uint32_t *pnodes;
     uint64_t begin;
-    uint32_t n;
-    unsigned long long *best;  // per round: packed argmax key
-    uint32_t *seeds;           // per round
-    unsigned long long *cov;   // covered sets so far
+    uint32_t n, n1, n2, k;
+    uint32_t *seeds;
+    uint32_t *pick;  // the current round's seed
+    uint32_t *done;  // blocks of the current refresh that finished
+    unsigned long long *cov;
 };
 
-__global__ __launch_bounds__(kThreads) void argmax_kernel(GreedyState g, uint32_t round) {
-    __shared__ unsigned long long smem[kThreads / kWave];
+// Load flavours. State written by earlier kernels is read with plain loads.
+// State that other waves of the same workgroup change inside the kernel (the
+// persistent rounds) is read with workgroup-scope atomic loads, which skip
+// the CU's L1 and hit the XCD's L2 (where the atomics landed); an L1 line
+// could still hold the old value.
+template <bool kWg, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (kWg) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else return *p;
+}
+
+template <bool kWg>
+__device__ __forceinline__ unsigned long long node_key(const uint32_t *gain, uint32_t v) {
+    const uint32_t gv = ld<kWg>(gain + v);
+    return (gv & kChosen) ? 0ull : ((static_cast<unsigned long long>(gv) << 32) | static_cast<unsigned long long>(~v));
+}
+
+// Lane-local recompute of m1[c]: the chunk's 64 gains as 16 vector loads.
+template <bool kWg>
+__device__ __forceinline__ unsigned long long m1_lane(const GreedyState &g, uint32_t c) {
+    const uint32_t a = c << kL1Shift;
     unsigned long long best = 0;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
-        const unsigned long long key =
-            g.chosen[v] ? 0ull : ((static_cast<unsigned long long>(g.gain[v]) << 32) | static_cast<unsigned long long>(~v));
-        best = key > best ? key : best;
+    if (a + (1u << kL1Shift) <= g.n) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(g.gain + a);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            uint4 q;
+            if constexpr (kWg) {
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(p + i);
+                q = make_uint4(ld<true>(w), ld<true>(w + 1), ld<true>(w + 2), ld<true>(w + 3));
+            } else {
+                q = p[i];
+            }
+            const uint32_t gv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t v = a + 4 * i + j;
+                const unsigned long long key =
+                    (gv[j] & kChosen) ? 0ull
+                                      : ((static_cast<unsigned long long>(gv[j]) << 32) | static_cast<unsigned long long>(~v));
+                best = key > best ? key : best;
+            }
+        }
+    } else {
+        for (uint32_t v = a; v < g.n; ++v) {
+            const unsigned long long key = node_key<kWg>(g.gain, v);
+            best = key > best ? key : best;
+        }
     }
-    best = wave_max_u64(best);
-    if (lane_id() == 0) smem[threadIdx.x / kWave] = best;
+    return best;
+}
+
+template <bool kWg>
+__device__ __forceinline__ unsigned long long m2_lane(const GreedyState &g, uint32_t d) {
+    const uint32_t a = d << kL2Shift;
+    unsigned long long best = 0;
+    if (!kWg && a + (1u << kL2Shift) <= g.n1) {
+        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(g.m1 + a);
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const ulonglong2 q = p[i];
+            best = q.x > best ? q.x : best;
+            best = q.y > best ? q.y : best;
+        }
+        return best;
+    }
+    const uint32_t b = min(a + (1u << kL2Shift), g.n1);
+    for (uint32_t c = a; c < b; ++c) {
+        const unsigned long long m = ld<kWg>(g.m1 + c);
+        best = m > best ? m : best;
+    }
+    return best;
+}
+
+// Re-validate m1[c]: right as long as its holder still has that key.
+template <bool kWg>
+__device__ __forceinline__ void refresh_m1_one(const GreedyState &g, uint32_t c) {
+    const unsigned long long m = ld<kWg>(g.m1 + c);
+    if (m != 0ull && node_key<kWg>(g.gain, ~static_cast<uint32_t>(m)) != m) g.m1[c] = m1_lane<kWg>(g, c);
+}
+
+template <bool kWg>
+__device__ __forceinline__ void refresh_m2_one(const GreedyState &g, uint32_t d) {
+    const unsigned long long m = ld<kWg>(g.m2 + d);
+    if (m != 0ull && ld<kWg>(g.m1 + ((~static_cast<uint32_t>(m)) >> kL1Shift)) != m) g.m2[d] = m2_lane<kWg>(g, d);
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x, unsigned long long *smem) {
+    x = wave_max_u64(x);
+    if (lane_id() == 0) smem[threadIdx.x / kWave] = x;
+    __syncthreads();
+    unsigned long long m = 0;
+    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) m = smem[w] > m ? smem[w] : m;
+    __syncthreads();
+    return m;
+}
+
+__global__ __launch_bounds__(kThreads) void init_m1_kernel(GreedyState g) {
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n1; c += gridDim.x * blockDim.x)
+        g.m1[c] = m1_lane<false>(g, c);
+}
+
+__global__ __launch_bounds__(kThreads) void init_m2_kernel(GreedyState g) {
+    for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < g.n2; d += gridDim.x * blockDim.x)
+        g.m2[d] = m2_lane<false>(g, d);
+}
+
+// The seed of round r from m2 (all threads of one block): the argmax key's
+// node, or, when every remaining gain is zero, the lowest id not yet chosen
+// (at most r, since only r nodes are chosen).
+template <bool kWg>
+__device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long *smem, uint32_t *s_pick) {
+    unsigned long long best = 0;
+    for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) {
+        const unsigned long long m = ld<true>(g.m2 + d);
+        best = m > best ? m : best;
+    }
+    best = block_max_u64(best, smem);
+    if ((best >> 32) == 0) {
+        if (threadIdx.x == 0) *s_pick = 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t v = threadIdx.x; v <= r; v += blockDim.x) {
+            bool taken = false;
+            for (uint32_t q = 0; q < r; ++q) taken |= (ld<true>(g.seeds + q) == v);
+            if (!taken) atomicMin(s_pick, v);
+        }
+    } else if (threadIdx.x == 0) {
+        *s_pick = ~static_cast<uint32_t>(best & 0xFFFFFFFFull);
+    }
+    __syncthreads();
+    const uint32_t v = *s_pick;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kThreads / kWave; ++w) best = smem[w] > best ? smem[w] : best;
-        atomicMax(&g.best[round], best);
+        g.seeds[r] = v;
+        atomicOr(&g.gain[v], kChosen);
+    }
+    return v;
+}
+
+// Round step 1 (grid-wide): re-validate m1; the last block to finish then
+// re-validates m2 and chooses the round's seed (release fence + counter on
+// the writers' side, acquire fence on the last block's side).
+__global__ __launch_bounds__(kThreads) void refresh_choose_kernel(GreedyState g, uint32_t r) {
+    __shared__ unsigned long long smem[kThreads / kWave];
+    __shared__ uint32_t s_pick;
+    __shared__ bool s_last;
+    if (r > 0) {
+        for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n1; c += gridDim.x * blockDim.x)
+            refresh_m1_one<false>(g, c);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(g.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (r > 0) {
+        for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) refresh_m2_one<false>(g, d);
+        __syncthreads();
+    }
+    const uint32_t v = choose<true>(g, r, smem, &s_pick);
+    if (threadIdx.x == 0) {
+        *g.pick = v;
+        *g.done = 0u;
     }
 }
 
-// Cover the winner's sets. 16 lanes per incidence entry.
-__global__ __launch_bounds__(kThreads) void apply_kernel(GreedyState g, uint32_t round) {
-    __shared__ unsigned long long smem[kThreads / kWave];
-    const uint32_t v = ~static_cast<uint32_t>(g.best[round] & 0xFFFFFFFFull);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        g.seeds[round] = v;
-        g.chosen[v] = 1;
-    }
+// Round step 3 (grid-wide): cover the seed's sets, 16 lanes per incidence entry.
+__global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g) {
+    const uint32_t v = *g.pick;
     const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
     const uint32_t sub = threadIdx.x & 15u;
     const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
@@ -195,13 +359,68 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(GreedyState g, uint32_t
         }
     }
     newly = wave_sum_u64(newly);
-    if (lane_id() == 0) smem[threadIdx.x / kWave] = newly;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long tot = 0;
-        for (int w = 0; w < kThreads / kWave; ++w) tot += smem[w];
-        if (tot) atomicAdd(g.cov, tot);
+    if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+}
+
+// Rounds [r0, k) in one workgroup. The cover step is flattened: first the
+// winner's incidence entries (1024 at a time) yield the newly covered sets,
+// then their members are decremented 1024 at a time.
+__global__ __launch_bounds__(kPersistThreads) void persist_kernel(GreedyState g, uint32_t r0) {
+    __shared__ unsigned long long smem[kPersistThreads / kWave];
+    __shared__ uint32_t s_pick;
+    __shared__ uint32_t s_nfresh;
+    __shared__ uint64_t s_start[kPersistThreads];
+    __shared__ uint32_t s_pre[kPersistThreads + 1];
+    const uint32_t tid = threadIdx.x;
+    unsigned long long newly = 0;
+    for (uint32_t r = r0; r < g.k; ++r) {
+        if (r > r0) {
+            for (uint32_t c = tid; c < g.n1; c += blockDim.x) refresh_m1_one<true>(g, c);
+            __syncthreads();
+            for (uint32_t d = tid; d < g.n2; d += blockDim.x) refresh_m2_one<true>(g, d);
+            __syncthreads();
+        }
+        const uint32_t v = choose<true>(g, r, smem, &s_pick);
+        const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
+        for (uint64_t base = a; base < b; base += blockDim.x) {
+            if (tid == 0) s_nfresh = 0;
+            __syncthreads();
+            const uint64_t i = base + tid;
+            if (i < b) {
+                const uint32_t j = g.isets[i];
+                const uint32_t bit = 1u << (j & 31u);
+                if (!(atomicOr(&g.covbits[j >> 5], bit) & bit)) {
+                    const uint32_t slot = atomicAdd(&s_nfresh, 1u);
+                    const uint64_t sa = g.poff[g.begin + j];
+                    s_start[slot] = sa;
+                    s_pre[slot + 1] = static_cast<uint32_t>(g.poff[g.begin + j + 1] - sa);
+                }
+            }
+            __syncthreads();
+            const uint32_t nf = s_nfresh;
+            newly += (tid == 0) ? nf : 0;
+            if (tid == 0) {  // prefix sums of the fresh sets' sizes
+                s_pre[0] = 0;
+                for (uint32_t q = 0; q < nf; ++q) s_pre[q + 1] += s_pre[q];
+            }
+            __syncthreads();
+            const uint32_t members = s_pre[nf];
+            for (uint32_t mb = 0; mb < members; mb += blockDim.x) {
+                const uint32_t idx = mb + tid;
+                if (idx < members) {
+                    uint32_t lo = 0, hi = nf - 1;  // last set whose prefix <= idx
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= idx) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    atomicSub(&g.gain[g.pnodes[s_start[lo] + (idx - s_pre[lo])]], 1u);
+                }
+            }
+            __syncthreads();
+        }
     }
+    if (tid == 0 && newly) atomicAdd(g.cov, newly);
 }
 
 // Sets in [begin, end) that contain a node of the seed bitmap.
@@ -361,47 +580,64 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const uint64_t nsets = end - begin;
     const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);
     const auto *pnodes = static_cast<const uint32_t *>(p->pnodes.ptr);
-    uint64_t ebegin = 0, eend = 0;
-    IM_TRY(to_host_sync(ctx, &ebegin, poff + begin, 8));
-    IM_TRY(to_host_sync(ctx, &eend, poff + end, 8));
+    uint64_t ends[2] = {0, 0};
+    IM_TRY(to_host_sync(ctx, &ends[0], poff + begin, 8));
+    IM_TRY(to_host_sync(ctx, &ends[1], poff + end, 8));
+    const uint64_t ebegin = ends[0], eend = ends[1];
     const uint64_t entries = eend - ebegin;
 
     // layout of the working arrays in ctx->cover
     const uint64_t tiles = (uint64_t(n) + kTile - 1) / kTile;
+    const uint32_t n1 = (n + (1u << kL1Shift) - 1) >> kL1Shift;
+    const uint32_t n2 = (n1 + (1u << kL2Shift) - 1) >> kL2Shift;
     const uint64_t covwords = (nsets + 31) / 32 + 1;
-    size_t off_gain = 0;
-    size_t off_fill = off_gain + 4ull * n;
-    size_t off_ioff = (off_fill + 4ull * n + 7) & ~size_t(7);
-    size_t off_tsum = off_ioff + 8ull * (n + 1);
-    size_t off_best = off_tsum + 8ull * (tiles + 1);
-    size_t off_cov = off_best + 8ull * k;
-    size_t off_seeds = off_cov + 8;
-    size_t off_chosen = off_seeds + 4ull * k;
-    size_t off_covbits = (off_chosen + n + 3) & ~size_t(3);
-    size_t off_isets = off_covbits + 4ull * covwords;
-    size_t bytes = off_isets + 4ull * (entries + 1);
-    IM_TRY(dev_reserve(ctx, ctx->cover, bytes));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return at;
+    };
+    const size_t o_gain = take(4ull * n), o_fill = take(4ull * n), o_ioff = take(8ull * (n + 1)),
+                 o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
+                 o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
+                 o_m2 = take(8ull * n2), o_cnt = take(16);
+    IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
-    auto *gain = reinterpret_cast<uint32_t *>(base + off_gain);
-    auto *fill = reinterpret_cast<uint32_t *>(base + off_fill);
-    auto *ioff = reinterpret_cast<uint64_t *>(base + off_ioff);
-    auto *tsum = reinterpret_cast<uint64_t *>(base + off_tsum);
-    auto *best = reinterpret_cast<unsigned long long *>(base + off_best);
-    auto *dcov = reinterpret_cast<unsigned long long *>(base + off_cov);
-    auto *dseeds = reinterpret_cast<uint32_t *>(base + off_seeds);
-    auto *chosen = reinterpret_cast<uint8_t *>(base + off_chosen);
-    auto *covbits = reinterpret_cast<uint32_t *>(base + off_covbits);
-    auto *isets = reinterpret_cast<uint32_t *>(base + off_isets);
+    auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
+    auto *gain = at32(o_gain);
+    auto *fill = at32(o_fill);
+    auto *ioff = reinterpret_cast<uint64_t *>(base + o_ioff);
+    auto *tsum = reinterpret_cast<uint64_t *>(base + o_tsum);
+    auto *dcov = reinterpret_cast<unsigned long long *>(base + o_cov);
+    auto *covbits = at32(o_covbits);
+    auto *isets = at32(o_isets);
+
+    GreedyState g{};
+    g.gain = gain;
+    g.m1 = reinterpret_cast<unsigned long long *>(base + o_m1);
+    g.m2 = reinterpret_cast<unsigned long long *>(base + o_m2);
+    g.pick = at32(o_cnt);
+    g.done = at32(o_cnt) + 1;
+    g.covbits = covbits;
+    g.ioff = ioff;
+    g.isets = isets;
+    g.poff = poff;
+    g.pnodes = pnodes;
+    g.begin = begin;
+    g.n = n;
+    g.n1 = n1;
+    g.n2 = n2;
+    g.k = k;
+    g.seeds = at32(o_seeds);
+    g.cov = dcov;
 
     hipStream_t st = ctx->stream;
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
     fill_u32_kernel<<<grid_of(n, kThreads, cu * 8), kThreads, 0, st>>>(gain, n, 0u);
     fill_u32_kernel<<<grid_of(n, kThreads, cu * 8), kThreads, 0, st>>>(fill, n, 0u);
-    fill_u32_kernel<<<grid_of(n / 4 + 1, kThreads, cu * 8), kThreads, 0, st>>>(reinterpret_cast<uint32_t *>(chosen),
-                                                                               (uint64_t(n) + 3) / 4, 0u);
     fill_u32_kernel<<<grid_of(covwords, kThreads, cu * 8), kThreads, 0, st>>>(covbits, covwords, 0u);
-    fill_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(best), k, 0);
     fill_u64_kernel<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t *>(dcov), 1, 0);
+    // incidence: counts, offsets, set ids per node
     if (entries)
         histogram_kernel<<<grid_of(entries, kThreads, cu * 16), kThreads, 0, st>>>(pnodes, ebegin, eend, gain);
     tile_sums_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gain, n, tsum);
@@ -410,15 +646,23 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     if (nsets)
         scatter_kernel<<<grid_of(nsets * 16, kThreads, cu * 16), kThreads, 0, st>>>(poff, pnodes, begin, nsets, ioff,
                                                                                      fill, isets);
-    GreedyState gs{gain, chosen, covbits, ioff, isets, poff, pnodes, begin, n, best, dseeds, dcov};
-    const uint32_t agrid = grid_of(n, kThreads, cu * 4);
-    const uint32_t pgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, static_cast<uint32_t>((nsets * 16 + kThreads - 1) / kThreads)));
-    for (uint32_t r = 0; r < k; ++r) {
-        argmax_kernel<<<agrid, kThreads, 0, st>>>(gs, r);
-        apply_kernel<<<pgrid, kThreads, 0, st>>>(gs, r);
+    // maximum index, then the rounds
+    init_m1_kernel<<<grid_of(n1, kThreads, cu * 8), kThreads, 0, st>>>(g);
+    init_m2_kernel<<<grid_of(n2, kThreads, cu * 8), kThreads, 0, st>>>(g);
+    // per-round launches pay for themselves once the cover work per round is
+    // large; tiny problems keep every round in one workgroup
+    const bool small = entries <= kPersistEntries;
+    const uint32_t big = small ? 0u : k;
+    const uint32_t cgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
+    const uint32_t rgrid = grid_of(uint64_t(n1), kThreads, cu * 4);
+    fill_u32_kernel<<<1, 64, 0, st>>>(g.done, 1, 0u);
+    for (uint32_t r = 0; r < big; ++r) {
+        refresh_choose_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
+        cover_kernel<<<cgrid, kThreads, 0, st>>>(g);
     }
+    if (big < k) persist_kernel<<<1, kPersistThreads, 0, st>>>(g, big);
     IM_HIP(hipGetLastError());
-    IM_HIP(hipMemcpyAsync(seeds_host, dseeds, 4ull * k, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipMemcpyAsync(seeds_host, g.seeds, 4ull * k, hipMemcpyDeviceToHost, st));
     IM_TRY(to_host_sync(ctx, cov, dcov, 8));
     return IM_OK;
 }

@@ -58,10 +58,18 @@ struct im_ctx {
     uint32_t slot_n = 0;      // n the slot arrays are laid out for
     uint32_t slot_count = 0;  // number of long-path slots
     uint64_t slot_epoch = 0;  // stamps handed out so far (host mirror)
+    DevBuf lt_tables;    // LT per-lane visited tables
+    uint32_t lt_lanes = 0;    // lanes the tables cover
+    uint64_t lt_stamp = 1;    // next LT walk stamp (never 0: zeroed entries are free)
     DevBuf cover;        // incidence / greedy working arrays
     DevBuf seedbits;     // seed-set bitmap (n bits)
     DevBuf zflags;       // Estimate-Inf per-sample hit flags
     void *host_pinned = nullptr;  // small pinned staging for read-backs
+
+    // optional event timing of the main sampler launches
+    bool timing = false;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    im_kernel_times times{};
 };
 
 struct im_graph {

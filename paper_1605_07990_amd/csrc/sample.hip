@@ -11,9 +11,9 @@
 //       per group gives the four edge coins. Visited set: an LDS bitmap
 //       (n <= 65536) or an LDS open-addressing hash; the queue lives in LDS.
 // LT  — one lane per sample: the reverse walk keeps at most one in-edge per
-//       node (binary search of the node's cumulative thresholds, then one
-//       vectorised window); revisits are caught by a per-lane 1024-bit LDS
-//       Bloom filter confirmed against the walk written so far.
+//       node (interpolation search of the node's cumulative thresholds in
+//       8-record windows); revisits are caught exactly by a per-lane bucketed
+//       hash table in global memory whose entries carry the walk's stamp.
 // Long path — samples that outgrow LDS (IC) or the per-sample staging
 //       region (LT) are deferred and re-run from scratch by whole waves on
 //       global epoch-stamped visited arrays and queues.
@@ -34,8 +34,6 @@ constexpr uint32_t kIcQcap = 1024;           // LDS queue entries per wave
 constexpr uint32_t kIcHcap = 2048;           // LDS hash slots / bitmap words per wave
 constexpr uint32_t kIcHbits = 11;            // log2(kIcHcap)
 constexpr uint32_t kBitmapMaxN = kIcHcap * 32;
-constexpr int kLtWaves = 4;
-constexpr int kBloomWords = 32;              // 1024-bit Bloom filter per lane
 constexpr uint32_t kLtCap = 512;             // per-sample staging region (LT)
 constexpr int kLongWaves = 4;
 
@@ -45,8 +43,10 @@ struct Counters {
     uint32_t defer_ticket;  // next deferred sample of the long path
     uint32_t overflow;      // staging too small: the batch must be re-run
     unsigned long long stage_cursor;
-    unsigned long long edges;
-    unsigned long long total_nodes;
+    unsigned long long edges;        // main pass
+    unsigned long long total_nodes;  // main pass
+    unsigned long long edges_long;   // long path
+    unsigned long long nodes_long;   // long path
 };
 
 struct Params {
@@ -76,6 +76,8 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
     c->stage_cursor = cursor0;
     c->edges = 0;
     c->total_nodes = 0;
+    c->edges_long = 0;
+    c->nodes_long = 0;
 }
 
 // ---------------------------------------------------------------- IC ----
@@ -280,60 +282,92 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
 
 // ---------------------------------------------------------------- LT ----
 
-__device__ __forceinline__ uint32_t bloom_h1(uint32_t u) { return (u * 0x9E3779B1u) >> 22; }
-__device__ __forceinline__ uint32_t bloom_h2(uint32_t u) { return (u * 0x85EBCA77u + 0x165667B1u) >> 22; }
+// Per-lane visited set: an open-addressed table of 64-byte buckets (8 u64
+// entries: walk stamp << 32 | node) in global memory. Entries of earlier
+// walks carry older stamps and count as free, so a table is never cleared.
+// A lookup's bucket load is issued together with the next node's offsets.
+constexpr uint32_t kLtBucketSlots = 8;
+constexpr uint32_t kLtBuckets = 128;  // 1024 entries = 8 KiB per lane
+constexpr uint32_t kLtTableSlots = kLtBuckets * kLtBucketSlots;
+constexpr uint32_t kLtMaxWalk = 640;  // longer walks take the long path (load <= 5/8)
 
-__device__ __forceinline__ void bloom_insert(uint32_t *bl, uint32_t u) {
-    const uint32_t h1 = bloom_h1(u), h2 = bloom_h2(u);
-    bl[(h1 >> 5) * kWave] |= 1u << (h1 & 31u);
-    bl[(h2 >> 5) * kWave] |= 1u << (h2 & 31u);
-}
+__device__ __forceinline__ uint32_t lt_bucket(uint32_t u) { return (u * 0x9E3779B1u) >> (32 - 7); }
 
-__device__ __forceinline__ bool bloom_maybe(const uint32_t *bl, uint32_t u) {
-    const uint32_t h1 = bloom_h1(u), h2 = bloom_h2(u);
-    return ((bl[(h1 >> 5) * kWave] >> (h1 & 31u)) & 1u) && ((bl[(h2 >> 5) * kWave] >> (h2 & 31u)) & 1u);
+__device__ __forceinline__ uint64_t lt_entry(uint32_t stamp, uint32_t u) {
+    return (static_cast<uint64_t>(stamp) << 32) | u;
 }
 
 // The in-edge kept by node v's LT coin c: the first e in [a, b) whose
-// cumulative threshold exceeds c, or b if none.
-__device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint64_t b, uint32_t c,
-                                            uint32_t &u) {
-    uint64_t lo = a, hi = b;  // answer in [lo, hi]; thr[hi] > c unless hi == b
-    while (hi - lo >= 8) {
-        const uint64_t mid = lo + ((hi - lo) >> 1);
-        if (edges[mid].y > c) hi = mid;
-        else lo = mid + 1;
+// cumulative threshold exceeds c, or b if none. Interpolation on the
+// thresholds picks an 8-record window (one round trip); a probe that does not
+// halve the interval makes the next probe a bisection.
+__device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint64_t b, uint32_t c, uint32_t &u) {
+    uint64_t lo = a, hi = b;             // answer in [lo, hi]
+    uint64_t tlo = 0, thi = 1ull << 32;  // threshold of record lo-1 (0 at a); of record hi (2^32 past the end)
+    uint32_t hi_src = 0;
+    bool bisect = false;
+    while (hi - lo > 8) {
+        const uint64_t len = hi - lo;
+        const uint64_t g = bisect ? lo + len / 2 : lo + (static_cast<uint64_t>(c) - tlo) * len / (thi - tlo);
+        uint64_t ws = (g >= lo + 3) ? g - 3 : lo;
+        if (ws + 8 > hi) ws = hi - 8;
+        uint2 r[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) r[i] = edges[ws + i];
+        if (r[0].y > c) {
+            hi = ws;
+            thi = r[0].y;
+            hi_src = r[0].x;
+        } else if (r[7].y <= c) {
+            lo = ws + 8;
+            tlo = r[7].y;
+        } else {
+            uint64_t pick = ws + 7;
+            uint32_t pu = r[7].x;
+#pragma unroll
+            for (int i = 6; i >= 1; --i) {
+                if (r[i].y > c) {
+                    pick = ws + i;
+                    pu = r[i].x;
+                }
+            }
+            u = pu;
+            return pick;
+        }
+        bisect = (hi - lo) * 2 > len;
     }
     uint2 r[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint64_t e = lo + i;
-        r[i] = (e < b && e <= hi) ? edges[e] : make_uint2(0u, 0u);
+        r[i] = (e < hi) ? edges[e] : make_uint2(0u, 0u);
     }
-    uint64_t pick = b;
+    uint64_t pick = hi;
+    uint32_t pu = hi_src;
 #pragma unroll
     for (int i = 7; i >= 0; --i) {
         if (r[i].y > c) {
             pick = lo + i;
-            u = r[i].x;
+            pu = r[i].x;
         }
     }
+    if (pick == b) return b;
+    u = pu;
     return pick;
 }
 
 template <int kMode>
-__global__ __launch_bounds__(kLtWaves *kWave) void lt_main_kernel(Params p) {
-    __shared__ uint32_t s_bloom[kLtWaves][kBloomWords][kWave];
+__global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tables, uint32_t stamp_base) {
     const uint32_t lane = lane_id();
-    const uint32_t wave = threadIdx.x / kWave;
-    uint32_t *bl = &s_bloom[wave][0][lane];
+    uint64_t *table = tables + (static_cast<uint64_t>(blockIdx.x) * kWave + lane) * kLtTableSlots;
     const Stream st(p.key);
 
     bool active = false, finished = false;
-    uint32_t t = 0, v = 0, len = 0;
-    uint64_t s = 0;
+    uint32_t t = 0, v = 0, len = 0, stamp = 0;
+    uint64_t s = 0, a = 0, b = 0;
     uint32_t *region = nullptr;
     uint64_t edges_acc = 0, nodes_acc = 0;
+    const uint32_t max_walk = min(kLtMaxWalk, p.lt_cap);
 
     for (;;) {
         const bool need = !active && !finished;
@@ -347,13 +381,15 @@ __global__ __launch_bounds__(kLtWaves *kWave) void lt_main_kernel(Params p) {
                 if (mine < p.count) {
                     t = mine;
                     s = p.s0 + t;
+                    stamp = stamp_base + t;
                     v = pick_source(st, s, p.src_cum, p.n);
                     region = p.stage + static_cast<uint64_t>(t) * p.lt_cap;
                     region[0] = v;
                     len = 1;
-#pragma unroll
-                    for (int w = 0; w < kBloomWords; ++w) bl[w * kWave] = 0u;
-                    bloom_insert(bl, v);
+                    // every entry is stale for a new stamp: the first slot is free
+                    table[lt_bucket(v) * kLtBucketSlots] = lt_entry(stamp, v);
+                    a = p.off[v];
+                    b = p.off[v + 1];
                     active = true;
                     if (kMode == 1 && test_bit(p.seedbits, v)) {
                         p.z[t] = 1;
@@ -370,21 +406,38 @@ __global__ __launch_bounds__(kLtWaves *kWave) void lt_main_kernel(Params p) {
         if (__ballot(!finished) == 0) break;
         if (!active) continue;
 
-        bool stop = false;
+        bool stop = (a == b);
         uint32_t u = 0;
-        const uint64_t a = p.off[v], b = p.off[v + 1];
-        if (a == b) {
-            stop = true;
-        } else {
+        uint64_t na = 0, nb = 0;
+        if (!stop) {
             const uint32_t c = lt_coin(st, s, v);
             if (lt_pick(p.edges, a, b, c, u) == b) stop = true;
         }
-        if (!stop && bloom_maybe(bl, u)) {
-            for (uint32_t i = 0; i < len; ++i) {
-                if (region[i] == u) {
-                    stop = true;
+        if (!stop) {
+            na = p.off[u];
+            nb = p.off[u + 1];
+            const uint64_t want = lt_entry(stamp, u);
+            uint32_t bi = lt_bucket(u);
+            for (uint32_t probe = 0; probe < kLtBuckets; ++probe) {
+                const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+                const ulonglong2 q0 = bucket[0], q1 = bucket[1], q2 = bucket[2], q3 = bucket[3];
+                const uint64_t ent[8] = {q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
+                int free_slot = -1;
+                bool found = false;
+#pragma unroll
+                for (int i = 7; i >= 0; --i) {
+                    if (ent[i] == want) found = true;
+                    if (static_cast<uint32_t>(ent[i] >> 32) != stamp) free_slot = i;
+                }
+                if (found) {
+                    stop = true;  // the walk closed a cycle
                     break;
                 }
+                if (free_slot >= 0) {
+                    table[bi * kLtBucketSlots + free_slot] = want;
+                    break;
+                }
+                bi = (bi + 1) & (kLtBuckets - 1);
             }
         }
         if (stop) {
@@ -399,15 +452,16 @@ __global__ __launch_bounds__(kLtWaves *kWave) void lt_main_kernel(Params p) {
             active = false;
             continue;
         }
-        if (len == p.lt_cap) {  // longer than the staging region: long path
+        if (len == max_walk) {  // longer than the staging region / table budget: long path
             const uint32_t d = atomicAdd(&p.cnt->defer_count, 1u);
             p.defer_list[d] = t;
             active = false;
             continue;
         }
         region[len++] = u;
-        bloom_insert(bl, u);
         v = u;
+        a = na;
+        b = nb;
         if (kMode == 1 && test_bit(p.seedbits, u)) {
             p.z[t] = 1;
             edges_acc += len;
@@ -574,8 +628,8 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
         wave_sync();
     }
     if (lane == 0) {
-        if (edges_acc) atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(edges_acc));
-        if (nodes_acc) atomicAdd(&p.cnt->total_nodes, static_cast<unsigned long long>(nodes_acc));
+        if (edges_acc) atomicAdd(&p.cnt->edges_long, static_cast<unsigned long long>(edges_acc));
+        if (nodes_acc) atomicAdd(&p.cnt->nodes_long, static_cast<unsigned long long>(nodes_acc));
     }
 }
 
@@ -674,6 +728,12 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint32_t *stage, con
     }
 }
 
+__global__ void zero_u64_kernel(uint64_t *p, uint64_t count) {
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
 __global__ void copy_u64_kernel(const uint64_t *src, uint64_t *dst, uint64_t count) {
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
          i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -748,6 +808,15 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
     IM_TRY(dev_reserve(ctx, ctx->counters, 256));
     if (mode == SampleMode::Hits) IM_TRY(dev_reserve(ctx, ctx->zflags, count + 64));
     IM_TRY(ensure_slots(ctx, g->n));
+    if (model == IM_LT && !ctx->lt_tables.ptr) {
+        const uint32_t lanes = static_cast<uint32_t>(ctx->cu_count) * 16 * kWave;
+        const uint64_t words = uint64_t(lanes) * kLtTableSlots;
+        IM_TRY(dev_alloc(ctx, ctx->lt_tables, words * 8));
+        zero_u64_kernel<<<blocks_for(words, 256, ctx->cu_count * 16), 256, 0, st>>>(
+            static_cast<uint64_t *>(ctx->lt_tables.ptr), words);
+        ctx->lt_lanes = lanes;
+        ctx->lt_stamp = 1;
+    }
     Meta meta = meta_view(ctx, count);
     auto *cnt = static_cast<Counters *>(ctx->counters.ptr);
 
@@ -780,6 +849,7 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
         const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+        if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_begin, st));
         if (model == IM_IC) {
             const uint32_t grid = blocks_for(count, kIcWaves, cu * 8);
             const bool bitmap = g->n <= kBitmapMaxN;
@@ -791,10 +861,19 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
                 else ic_main_kernel<1, false><<<grid, kIcWaves * kWave, 0, st>>>(p);
             }
         } else {
-            const uint32_t grid = blocks_for(count, kLtWaves * kWave, cu * 8);
-            if (mode == SampleMode::Pool) lt_main_kernel<0><<<grid, kLtWaves * kWave, 0, st>>>(p);
-            else lt_main_kernel<1><<<grid, kLtWaves * kWave, 0, st>>>(p);
+            const uint32_t grid = blocks_for(count, kWave, std::min<uint32_t>(cu * 16, ctx->lt_lanes / kWave));
+            if (ctx->lt_stamp + count >= 0xFFFFFFF0ull) {
+                zero_u64_kernel<<<blocks_for(uint64_t(ctx->lt_lanes) * kLtTableSlots, 256, cu * 16), 256, 0, st>>>(
+                    static_cast<uint64_t *>(ctx->lt_tables.ptr), uint64_t(ctx->lt_lanes) * kLtTableSlots);
+                ctx->lt_stamp = 1;
+            }
+            const uint32_t stamp_base = static_cast<uint32_t>(ctx->lt_stamp);
+            ctx->lt_stamp += count;
+            auto *tables = static_cast<uint64_t *>(ctx->lt_tables.ptr);
+            if (mode == SampleMode::Pool) lt_main_kernel<0><<<grid, kWave, 0, st>>>(p, tables, stamp_base);
+            else lt_main_kernel<1><<<grid, kWave, 0, st>>>(p, tables, stamp_base);
         }
+        if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_end, st));
         {
             const uint32_t nslots = ctx->slot_count;
             const uint32_t grid = (nslots + kLongWaves - 1) / kLongWaves;
@@ -816,9 +895,19 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
             cap = std::max<uint64_t>(cap * 2, hc.stage_cursor + (1u << 20));
             continue;
         }
-        res->total_nodes = hc.total_nodes;
-        res->edges = hc.edges;
+        res->total_nodes = hc.total_nodes + hc.nodes_long;
+        res->edges = hc.edges + hc.edges_long;
         res->deferred = hc.defer_count;
+        if (ctx->timing && mode == SampleMode::Pool) {
+            float ms = 0.f;
+            IM_HIP(hipEventElapsedTime(&ms, ctx->ev_begin, ctx->ev_end));
+            ctx->times.sample_launches += 1;
+            ctx->times.sample_ms += ms;
+            ctx->times.sample_sets += count - hc.defer_count;
+            ctx->times.sample_steps += hc.edges;
+            ctx->times.sample_nodes += hc.total_nodes;
+            ctx->times.model = model;
+        }
         return IM_OK;
     }
     set_error("sampler staging kept overflowing");
