@@ -1,16 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the Stop-and-Stare hot path on one MI355X.
 
-Workload: the R-MAT scale-20 graph (1,048,576 nodes, 16M draws with
-a,b,c = 0.57, 0.19, 0.19, self-loops and repeats dropped), LT model with
-uniform(0,1) in-weights normalised to sum 1 per node; each step is one full
-D-SSA query (Algorithm 4: RR-set sampling, incidence, greedy max-coverage,
-stare step, FP64 checkpoint logic) with k = 100, eps = 0.1, delta = 1/n and a
-fresh stream key. Inputs are resident in HBM before the timed region.
+Default workload (--workload rmat20-lt-dssa): the R-MAT scale-20 graph
+(1,048,576 nodes, 16M draws with a,b,c = 0.57, 0.19, 0.19, self-loops and
+repeats dropped), LT model with uniform(0,1) in-weights normalised to sum 1
+per node; each step is one full D-SSA query (Algorithm 4: RR-set sampling,
+incidence, greedy max-coverage, stare step, FP64 checkpoint logic) with
+k = 100, eps = 0.1, delta = 1/n and a fresh stream key.
 
-Prints one JSON line: RR sets/s over the timed steps (whole job), edges
-traversed/s, query latency p50/p99, the sampler kernel's roofline (event-
-timed live on the library's stream) and the oracle timed on the host.
+Other workloads (one JSON line each, same fields):
+  pokec-ic-ssa64  Pokec-shaped Chung-Lu graph (4.8M nodes, 69M edges,
+                  exponent 2.3), IC trivalency; each step is 64 concurrent
+                  SSA queries (k log-uniform in [1, 500], eps in
+                  {0.05, 0.1, 0.2}, delta = 1/n, key = query index) through
+                  the multi-query engine, all sampling fused per pass.
+  serving         Poisson stream of queries over the resident NetHEPT-,
+                  R-MAT-20- and Pokec-shaped graphs through the request loop
+                  (continuous batching, admission by RR-pool bytes).
+
+Inputs are resident in HBM before the timed region. Prints one JSON line:
+RR sets/s over the timed steps (whole job), edges traversed/s, query latency
+p50/p99, the sampler kernel's roofline (event-timed live on the library's
+stream) and the oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -51,60 +62,54 @@ def percentile(xs, q):
     return xs[i]
 
 
-def cpu_baseline(g, k, eps, delta, budget_s):
-    import oracle
+def roofline(kt: dict, model: int) -> dict:
+    """Roofline of the main sampler kernel from its event timing: algorithmic
+    bytes per launch over the mean launch duration, against HBM peak."""
+    launches = max(kt["sample_launches"], 1)
+    if model == 1:
+        total = lt_bytes(kt["sample_steps"], kt["sample_sets"])
+        name = "lt_main_kernel (LT RR-set sampler)"
+    else:
+        total = ic_bytes(kt["sample_steps"], kt["sample_nodes"], kt["sample_sets"])
+        name = "ic_main_kernel (IC RR-set sampler)"
+    bytes_per_launch = total / launches
+    ms_per_launch = kt["sample_ms"] / launches
+    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
+    sec = kt["sample_ms"] * 1e-3
+    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "launches": kt["sample_launches"],
+            "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
+            "sampler_sets_per_s": round(kt["sample_sets"] / sec) if sec else None,
+            "sampler_steps_per_s": round(kt["sample_steps"] / sec) if sec else None}
 
-    og = oracle.Graph(oracle.LT, g.n, g.src, g.dst, g.w_lt)
-    sets = edges = 0
-    q = 0
-    t0 = time.perf_counter()
-    while True:
-        _, st = og.dssa(k, eps, delta, q)
-        sets += st["n_sets"]
-        edges += st["edges"]
-        q += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": sets / dt, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
-            "edges_per_s": edges / dt,
-            "sample": f"{q} sequential oracle D-SSA queries (k={k}, eps={eps}, delta=1/n, keys 0..{q - 1}) "
-                      f"on the same graph, {dt:.1f} s on one host core",
-            "host_cpus": os.cpu_count()}
+
+def log_uniform_k(rng, hi: int, n: int) -> int:
+    return int(min(n, max(1, round(math.exp(rng.uniform(0.0, math.log(hi)))))))
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=100)
-    ap.add_argument("--eps", type=float, default=0.1)
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
-              "note, not an implemented path.", file=sys.stderr)
-        return 2
+def pokec_queries(n: int, count: int = 64, seed: int = 64):
+    """The 64-query mix: k = round(exp(U(0, ln 500))), eps uniform over
+    {0.05, 0.1, 0.2}, key = query index."""
+    import numpy as np
 
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        k = log_uniform_k(rng, 500, n)
+        eps = float((0.05, 0.1, 0.2)[int(rng.integers(3))])
+        out.append((k, eps, q))
+    return out
+
+
+# ----------------------------------------------------------- workloads ----
+
+def run_rmat20(args, im, ctx, sync):
     import synth
-    from paper_1605_07990_amd import binding as im
-
-    torch = None
-    if os.environ.get("IM_NO_TORCH", "") != "1":
-        import torch
-
-    def sync():
-        if torch is not None:
-            torch.cuda.synchronize()
 
     g = synth.make("rmat20")
     n, k, eps = g.n, args.k, args.eps
     delta = 1.0 / n
-    ctx = im.Context(0)
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_lt=g.w_lt)
-
     for i in range(args.warmup):
         dg.dssa(im.IM_LT, k, eps, delta, 1_000_000 + i)
     ctx.set_timing(True)
@@ -126,31 +131,203 @@ def main() -> int:
     dt = time.perf_counter() - t0
     kt = ctx.read_timing(reset=True)
     ctx.set_timing(False)
-
-    launches = max(kt["sample_launches"], 1)
-    bytes_per_launch = lt_bytes(kt["sample_steps"], kt["sample_sets"]) / launches
-    ms_per_launch = kt["sample_ms"] / launches
-    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": "lt_main_kernel (LT RR-set sampler)", "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "launches": kt["sample_launches"], "avg_launch_ms": round(ms_per_launch, 5),
-            "algorithmic_bytes_per_launch": round(bytes_per_launch),
-            "sampler_sets_per_s": round(kt["sample_sets"] / (kt["sample_ms"] * 1e-3)) if kt["sample_ms"] else None,
-            "sampler_steps_per_s": round(kt["sample_steps"] / (kt["sample_ms"] * 1e-3)) if kt["sample_ms"] else None}
-
-    out = {"metric": METRIC, "value": round(sets / dt, 1), "unit": "RR sets/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+    dg.close()
+    out = {"value": round(sets / dt, 1), "ms_per_step": round(dt * 1e3 / args.steps, 4),
            "config": {"workload": "R-MAT-20 LT D-SSA", "n": n, "m": g.m, "k": k, "eps": eps, "delta": "1/n",
                       "queries_per_step": 1},
            "edges_per_s": round(edges / dt, 1), "p50_ms": round(percentile(lat, 50), 3),
            "p99_ms": round(percentile(lat, 99), 3), "rr_sets_per_query": sets // max(args.steps, 1),
            "iterations_per_query": sorted(set(iters)),
            "stage_ms_per_query": {k_: round(v_ / args.steps, 3) for k_, v_ in stage.items()},
-           "roofline": roof}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, k, eps, delta, args.cpu_budget)
+           "roofline": roofline(kt, 1)}
+
+    def cpu(budget_s):
+        import oracle
+
+        og = oracle.Graph(oracle.LT, g.n, g.src, g.dst, g.w_lt)
+        s_ = e_ = q = 0
+        t = time.perf_counter()
+        while True:
+            _, ost = og.dssa(k, eps, delta, q)
+            s_ += ost["n_sets"]
+            e_ += ost["edges"]
+            q += 1
+            if time.perf_counter() - t >= budget_s:
+                break
+        d = time.perf_counter() - t
+        return {"value": s_ / d, "unit": "RR sets/s", "cores": 1, "kind": "oracle", "edges_per_s": e_ / d,
+                "sample": f"{q} sequential oracle D-SSA queries (k={k}, eps={eps}, delta=1/n, keys 0..{q - 1}) "
+                          f"on the same graph, {d:.1f} s on one host core"}
+
+    return out, cpu
+
+
+def run_pokec64(args, im, ctx, sync):
+    import synth
+
+    g = synth.make("pokec")
+    n = g.n
+    delta = 1.0 / n
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    qs = pokec_queries(n)
+    budget = int(args.pool_budget_gb * (1 << 30))
+
+    def one_batch(key_base):
+        eng = im.Engine(ctx, pool_budget_bytes=budget, max_active=64)
+        t_sub = time.perf_counter()
+        tickets = [eng.submit(dg, im.IM_IC, "ssa", k, eps, delta, key_base + key) for k, eps, key in qs]
+        done = {}
+        while len(done) < len(tickets):
+            eng.step()
+            now = time.perf_counter()
+            for t in tickets:
+                if t not in done and eng.poll(t) != 0:
+                    done[t] = (now - t_sub) * 1e3
+        res = [eng.result(t) for t in tickets]
+        eng.close()
+        return res, [done[t] for t in tickets]
+
+    for i in range(args.warmup):
+        one_batch(1_000_000 * (i + 1))
+    ctx.set_timing(True)
+    ctx.read_timing(reset=True)
+    sync()
+    lat, sets, edges = [], 0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, l_ = one_batch(0)
+        lat += l_
+        for _, st in res:
+            sets += st["n_sets"] + st["n_verify"]
+            edges += st["edges"]
+    sync()
+    dt = time.perf_counter() - t0
+    kt = ctx.read_timing(reset=True)
+    ctx.set_timing(False)
+    out = {"value": round(sets / dt, 1), "ms_per_step": round(dt * 1e3 / args.steps, 4),
+           "config": {"workload": "Pokec-shaped IC trivalency, 64 concurrent SSA queries", "n": n, "m": g.m,
+                      "k": "log-uniform [1,500]", "eps": [0.05, 0.1, 0.2], "delta": "1/n", "queries_per_step": 64},
+           "edges_per_s": round(edges / dt, 1), "p50_ms": round(percentile(lat, 50), 3),
+           "p99_ms": round(percentile(lat, 99), 3), "rr_sets_per_step": sets // max(args.steps, 1),
+           "roofline": roofline(kt, 0)}
+    if args.compare_plain:
+        # the same 64 queries one after another through im_ssa
+        sync()
+        p0 = time.perf_counter()
+        psets = 0
+        for k, eps, key in qs:
+            _, st = dg.ssa(im.IM_IC, k, eps, delta, key)
+            psets += st["n_sets"] + st["n_verify"]
+        sync()
+        pdt = time.perf_counter() - p0
+        out["one_query_at_a_time"] = {"ms": round(pdt * 1e3, 3), "rr_sets_per_s": round(psets / pdt, 1),
+                                      "engine_speedup": round(pdt / (dt / args.steps), 3)}
     dg.close()
+
+    def cpu(budget_s):
+        import oracle
+
+        og = oracle.Graph(oracle.IC, g.n, g.src, g.dst, g.w_ic)
+        pool = oracle.Pool(og, 0)
+        c = 0
+        t = time.perf_counter()
+        chunk = 20000
+        while time.perf_counter() - t < budget_s:
+            c += chunk
+            pool.extend(c)
+        d = time.perf_counter() - t
+        return {"value": c / d, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
+                "sample": f"oracle RR-set sampling of samples 0..{c - 1} of query 0's stream on the same graph "
+                          f"({d:.1f} s, one host core); sampling only, no greedy"}
+
+    return out, cpu
+
+
+def run_serving(args, im, ctx, sync):
+    import synth
+    from paper_1605_07990_amd import serve
+
+    graphs, shapes = {}, {}
+    for name in ("nethept", "rmat20", "pokec"):
+        g = synth.make(name)
+        graphs[name] = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic, w_lt=g.w_lt)
+        shapes[name] = (g.n, g.w_ic is not None, g.w_lt is not None)
+    budget = int(args.pool_budget_gb * (1 << 30))
+    if args.warmup:
+        eng = im.Engine(ctx, pool_budget_bytes=budget, max_active=args.max_active)
+        serve.serve(eng, graphs, serve.poisson_requests(shapes, args.qps, max(8, args.warmup), seed=999,
+                                                        algo=None, key_base=1 << 40))
+        eng.close()
+    reqs = serve.poisson_requests(shapes, args.qps, args.queries, seed=args.seed, algo=None)
+    eng = im.Engine(ctx, pool_budget_bytes=budget, max_active=args.max_active)
+    ctx.set_timing(True)
+    ctx.read_timing(reset=True)
+    sync()
+    r = serve.serve(eng, graphs, reqs)
+    sync()
+    kt = ctx.read_timing(reset=True)
+    ctx.set_timing(False)
+    eng.close()
+    for dg in graphs.values():
+        dg.close()
+    out = {"value": round(r["rr_sets_per_s"], 1), "ms_per_step": round(r["wall_s"] * 1e3, 3),
+           "config": {"workload": "serving: Poisson stream over NetHEPT-, R-MAT-20-, Pokec-shaped graphs",
+                      "qps": args.qps, "queries": args.queries, "k": "log-uniform [1,1000]",
+                      "eps": [0.05, 0.1, 0.2], "model": "IC or LT 50/50", "algo": "SSA or D-SSA 50/50",
+                      "pool_budget_gb": args.pool_budget_gb, "max_active": args.max_active},
+           "edges_per_s": round(r["edges_per_s"], 1), "p50_ms": round(r["p50_ms"], 3),
+           "p99_ms": round(r["p99_ms"], 3), "achieved_qps": round(r["achieved_qps"], 3),
+           "offered_qps": round(r["offered_qps"], 3), "engine_steps": r["engine_steps"],
+           "max_active": r["max_active"], "roofline": roofline(kt, kt.get("model", 0))}
+    return out, None
+
+
+WORKLOADS = {"rmat20-lt-dssa": run_rmat20, "pokec-ic-ssa64": run_pokec64, "serving": run_serving}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="rmat20-lt-dssa")
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--pool-budget-gb", type=float, default=64.0)
+    ap.add_argument("--max-active", type=int, default=64)
+    ap.add_argument("--qps", type=float, default=20.0)
+    ap.add_argument("--queries", type=int, default=1000)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--compare-plain", action="store_true", help="also time the queries one at a time")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
+              "note, not an implemented path.", file=sys.stderr)
+        return 2
+
+    from paper_1605_07990_amd import binding as im
+
+    torch = None
+    if os.environ.get("IM_NO_TORCH", "") != "1":
+        import torch
+
+    def sync():
+        if torch is not None:
+            torch.cuda.synchronize()
+
+    ctx = im.Context(0)
+    body, cpu = WORKLOADS[args.workload](args, im, ctx, sync)
+    steps = args.steps if args.workload != "serving" else 1
+    out = {"metric": METRIC, "value": body.pop("value"), "unit": "RR sets/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": body.pop("ms_per_step"), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
+    out.update(body)
+    if cpu is not None and not args.no_cpu_baseline:
+        cb = cpu(args.cpu_budget)
+        cb["host_cpus"] = os.cpu_count()
+        out["cpu_baseline"] = cb
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0

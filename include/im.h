@@ -58,6 +58,8 @@ typedef void (*im_free_fn)(void *ptr, void *user);
  */
 im_status im_ctx_create(int device, void *stream, im_alloc_fn alloc, im_free_fn free_, void *user,
                         im_ctx **out);
+/* Free the context's own buffers. Every engine, pool and graph made on it
+ * must be freed before (they use its allocator and stream). */
 void im_ctx_free(im_ctx *ctx);
 
 /*
@@ -231,6 +233,81 @@ typedef struct im_kernel_times {
 
 im_status im_ctx_set_timing(im_ctx *ctx, int enable);
 im_status im_ctx_read_timing(im_ctx *ctx, im_kernel_times *out, int reset);
+
+/*
+ * Multi-query engine. Many SSA (Algorithm 1) and D-SSA (Algorithm 4)
+ * queries advance together: each engine step issues one fused sampler
+ * launch per (graph, model) holding every active query's next RR sets
+ * (Definition 2) on its own stream, one fused Estimate-Inf pass
+ * (Algorithm 3) for the SSA queries that passed condition C1, and one
+ * batched Max-Coverage (Algorithm 2, one workgroup per query) plus stare
+ * step for the queries whose pool reached their checkpoint; the FP64
+ * checkpoint conditions run per query on the host exactly as in im_ssa /
+ * im_dssa. A query's seeds and statistics (except the ms_* wall times,
+ * which here are the query's share of shared passes) equal those of im_ssa /
+ * im_dssa with the same arguments, whatever else runs beside it.
+ *
+ * im_query: graph (loaded on the engine's context), model, algo, k, eps,
+ * delta, key: the arguments of im_ssa / im_dssa.
+ */
+typedef enum { IM_ALGO_SSA = 0, IM_ALGO_DSSA = 1 } im_algo;
+
+typedef struct im_query {
+    const im_graph *graph;
+    im_model model;
+    im_algo algo;
+    uint32_t k;
+    double eps, delta;
+    uint64_t key;
+} im_query;
+
+typedef struct im_engine im_engine;
+
+/*
+ * Create an engine on ctx. Queued queries are admitted at the start of a
+ * step while fewer than max_active are active and the device bytes of the
+ * active queries' RR pools are below pool_budget_bytes (one query is always
+ * admitted when none is active). The engine borrows ctx, which must outlive
+ * it. Errors: IM_E_ARG (null ctx/out, max_active 0), IM_E_OOM.
+ */
+im_status im_engine_create(im_ctx *ctx, uint64_t pool_budget_bytes, uint32_t max_active, im_engine **out);
+
+/* Free the engine and every query it still holds (finished or not). */
+void im_engine_free(im_engine *e);
+
+/*
+ * Queue a query (copied; the graph must stay loaded until its result is
+ * taken). *ticket receives its id (> 0). No device work happens here.
+ * Errors: those of im_ssa / im_dssa's argument checks; IM_E_ARG for a graph
+ * of another context or an unknown algo.
+ */
+im_status im_engine_submit(im_engine *e, const im_query *q, uint64_t *ticket);
+
+/*
+ * One engine step: admission, then the fused sampling, verification and
+ * coverage passes and every active query's checkpoint. Synchronises the
+ * context's stream. *n_active / *n_pending (either may be NULL) receive the
+ * queries still active / queued after the step. On a device error every
+ * active query is marked failed with that status, which is also returned.
+ */
+im_status im_engine_step(im_engine *e, uint32_t *n_active, uint32_t *n_pending);
+
+/* Step until no query is active or queued. */
+im_status im_engine_run(im_engine *e);
+
+/*
+ * *state = 0 while the query is queued or running, 1 once its result is
+ * ready, a negative im_status if it failed. Errors: IM_E_ARG (unknown
+ * ticket: never issued or result already taken).
+ */
+im_status im_engine_poll(im_engine *e, uint64_t ticket, int *state);
+
+/*
+ * Take a finished query's result: seeds_out[k] and *st (either may be NULL),
+ * then forget the ticket. A failed query returns its error status (and is
+ * forgotten). Errors: IM_E_ARG (unknown ticket), IM_E_STATE (not finished).
+ */
+im_status im_engine_result(im_engine *e, uint64_t ticket, uint32_t *seeds_out, im_stats *st);
 
 /* The stream key of SSA iteration i's verification pool, derived from key. */
 uint64_t im_derived_key(uint64_t key, uint64_t i);

@@ -28,7 +28,12 @@ STATUS = {0: "IM_OK", -1: "IM_E_ARG", -2: "IM_E_OOM", -3: "IM_E_LT_WEIGHTS", -4:
 EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source_weights", "im_graph_free",
            "im_graph_info", "im_pool_create", "im_pool_free", "im_sample_rr", "im_pool_info", "im_pool_read",
            "im_pool_device", "im_max_coverage", "im_max_coverage_range", "im_coverage_range", "im_estimate_inf",
-           "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing"]
+           "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing",
+           "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
+           "im_engine_poll", "im_engine_result"]
+
+IM_ALGO_SSA, IM_ALGO_DSSA = 0, 1
+ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}
 
 
 class ImError(RuntimeError):
@@ -58,6 +63,12 @@ class Stats(ctypes.Structure):
                     it_cov_c=list(self.it_cov_c[:t]), it_eps_t=list(self.it_eps_t[:t]),
                     ms_sample=self.ms_sample, ms_cover=self.ms_cover, ms_verify=self.ms_verify,
                     ms_total=self.ms_total)
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("model", ctypes.c_int), ("algo", ctypes.c_int),
+                ("k", ctypes.c_uint32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+                ("key", ctypes.c_uint64)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -128,6 +139,13 @@ def load_library(path: Path | str | None = None):
         "im_last_error": (ctypes.c_char_p, []),
         "im_ctx_set_timing": (st, [vp, ctypes.c_int]),
         "im_ctx_read_timing": (st, [vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
+        "im_engine_create": (st, [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(vp)]),
+        "im_engine_free": (None, [vp]),
+        "im_engine_submit": (st, [vp, ctypes.POINTER(Query), u64p]),
+        "im_engine_step": (st, [vp, u32p, u32p]),
+        "im_engine_run": (st, [vp]),
+        "im_engine_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+        "im_engine_result": (st, [vp, ctypes.c_uint64, u32p, ctypes.POINTER(Stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -185,9 +203,27 @@ class Context:
 
             self._alloc = ALLOC_FN(_a)
             self._free = FREE_FN(_f)
+        # live handles made on this context: raw pointer -> name of the C call
+        # that frees it, in creation order (engines and pools come after the
+        # graphs they use, so freeing in reverse order is always safe)
+        self._live: dict[int, str] = {}
         h = ctypes.c_void_p()
         _check(lib.im_ctx_create(device, stream, self._alloc, self._free, None, ctypes.byref(h)))
         self.h = h
+
+    def _adopt(self, h: ctypes.c_void_p, free_fn: str):
+        self._live[h.value] = free_fn
+
+    def _release(self, child) -> None:
+        """Free a child's handle unless this context already freed it (the
+        garbage collector may finalize a context before its children)."""
+        h = getattr(child, "h", None)
+        if h is None:
+            return
+        child.h = None
+        fn = self._live.pop(h.value, None)
+        if fn is not None and self.h is not None:
+            getattr(load_library(), fn)(h)
 
     def set_timing(self, enable: bool = True):
         _check(load_library().im_ctx_set_timing(self.h, 1 if enable else 0))
@@ -199,7 +235,11 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            load_library().im_ctx_free(self.h)
+            lib = load_library()
+            for ptr, fn in reversed(list(self._live.items())):
+                getattr(lib, fn)(ctypes.c_void_p(ptr))
+            self._live.clear()
+            lib.im_ctx_free(self.h)
             self.h = None
 
     def __del__(self):
@@ -224,6 +264,7 @@ class Graph:
         wl, wlp = _f32(w_lt)
         h = ctypes.c_void_p()
         _check(lib.im_graph_load(ctx.h, n, s.shape[0], sp, dp, wip, wlp, ctypes.byref(h)))
+        ctx._adopt(h, "im_graph_free")
         self.ctx, self.h, self.n, self.m = ctx, h, n, int(s.shape[0])
 
     def set_source_weights(self, node_w):
@@ -240,8 +281,7 @@ class Graph:
 
     def close(self):
         if getattr(self, "h", None):
-            load_library().im_graph_free(self.h)
-            self.h = None
+            self.ctx._release(self)
 
     def __del__(self):
         if sys.is_finalizing():
@@ -279,12 +319,12 @@ class Pool:
         lib = load_library()
         h = ctypes.c_void_p()
         _check(lib.im_pool_create(graph.ctx.h, graph.h, MODELS[model], key, ctypes.byref(h)))
+        graph.ctx._adopt(h, "im_pool_free")
         self.graph, self.model, self.key, self.h = graph, MODELS[model], key, h
 
     def close(self):
         if getattr(self, "h", None):
-            load_library().im_pool_free(self.h)
-            self.h = None
+            self.graph.ctx._release(self)
 
     def __del__(self):
         if sys.is_finalizing():
@@ -338,6 +378,63 @@ class Pool:
         cov = ctypes.c_uint64()
         _check(load_library().im_coverage_range(self.h, begin, end, sp, s.shape[0], ctypes.byref(cov)))
         return int(cov.value)
+
+
+class Engine:
+    """im_engine: many SSA / D-SSA queries advanced together in fused passes."""
+
+    def __init__(self, ctx: Context, pool_budget_bytes: int = 16 << 30, max_active: int = 64):
+        h = ctypes.c_void_p()
+        _check(load_library().im_engine_create(ctx.h, pool_budget_bytes, max_active, ctypes.byref(h)))
+        ctx._adopt(h, "im_engine_free")
+        self.ctx, self.h = ctx, h
+        self._k = {}
+        self._graphs = {}
+
+    def submit(self, graph: Graph, model, algo, k: int, eps: float, delta: float, key: int) -> int:
+        q = Query(graph.h, MODELS[model], ALGOS[algo], k, eps, delta, key)
+        t = ctypes.c_uint64()
+        _check(load_library().im_engine_submit(self.h, ctypes.byref(q), ctypes.byref(t)))
+        self._k[int(t.value)] = k
+        self._graphs[int(t.value)] = graph  # keep the graph alive while the query is held
+        return int(t.value)
+
+    def step(self):
+        a, p = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load_library().im_engine_step(self.h, ctypes.byref(a), ctypes.byref(p)))
+        return int(a.value), int(p.value)
+
+    def run(self):
+        _check(load_library().im_engine_run(self.h))
+
+    def poll(self, ticket: int) -> int:
+        s = ctypes.c_int()
+        _check(load_library().im_engine_poll(self.h, ticket, ctypes.byref(s)))
+        return int(s.value)
+
+    def result(self, ticket: int):
+        seeds = np.zeros(max(self._k.get(ticket, 1), 1), dtype=np.uint32)
+        st = Stats()
+        rc = load_library().im_engine_result(self.h, ticket, seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                             ctypes.byref(st))
+        if rc != -6:  # everything but "not finished" forgets the ticket
+            self._k.pop(ticket, None)
+            self._graphs.pop(ticket, None)
+        _check(rc)
+        return seeds, st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx._release(self)
+            self._graphs.clear()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def derived_key(key: int, i: int) -> int:

@@ -9,7 +9,7 @@ from pathlib import Path
 HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libim.so"
-SOURCES = ["api.hip", "graph.hip", "sample.hip", "cover.hip"]
+SOURCES = ["api.hip", "graph.hip", "sample.hip", "cover.hip", "engine.hip"]
 ARCH = os.environ.get("IM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -102,7 +102,7 @@ uint64_t derived_key(uint64_t key, uint64_t i) {
 
 // ---- constants (Table 1, Algorithms 1, 3, 4, Eq. 15) ----
 
-static double ups_ln(double eps, double ln_inv_delta) {
+double ups_ln(double eps, double ln_inv_delta) {
     return (2.0 + 2.0 * eps / 3.0) * ln_inv_delta / (eps * eps);
 }
 
@@ -114,14 +114,10 @@ double ln_choose(uint32_t n, uint32_t k) {
     return s;
 }
 
-struct Caps {
-    double n_max, i_max, lambda;
-};
-
 // N_max = 8 (1-1/e)/(2+2eps/3) Upsilon(eps, delta/6/C(n,k)) n/k ;
 // i_max = ceil(log2(2 N_max / Upsilon(eps, delta/3))) ;
 // Lambda = Upsilon(eps, delta/(3 i_max)).
-static Caps caps(uint32_t n, uint32_t k, double eps, double delta) {
+Caps caps(uint32_t n, uint32_t k, double eps, double delta) {
     const double one_m = 1.0 - std::exp(-1.0);
     Caps c;
     c.n_max = 8.0 * one_m / (2.0 + 2.0 * eps / 3.0) * ups_ln(eps, std::log(6.0 / delta) + ln_choose(n, k)) * double(n) /
@@ -131,7 +127,7 @@ static Caps caps(uint32_t n, uint32_t k, double eps, double delta) {
     return c;
 }
 
-static im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps, double delta) {
+im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps, double delta) {
     const double one_m = 1.0 - std::exp(-1.0);
     if (!g) {
         set_error("null graph");
@@ -161,18 +157,19 @@ static im_status check_query(const im_graph *g, im_model model, uint32_t k, doub
 }
 
 // Largest batch drawn at once: LT reserves a staging region per sample.
-static uint64_t max_batch(im_model model) { return model == IM_LT ? (1ull << 20) : (1ull << 24); }
+uint64_t max_batch(im_model model) { return model == IM_LT ? (1ull << 20) : (1ull << 24); }
 
 static im_status pool_extend_to(im_pool *p, uint64_t target, double *ms) {
     const double t0 = now_ms();
     while (p->count < target) {
         const uint64_t count = std::min<uint64_t>(target - p->count, max_batch(p->model));
         SampleResult r;
-        IM_TRY(sample_batch(p->ctx, p->g, p->model, p->key, p->count, count, SampleMode::Pool,
-                            p->mean_size > 0 ? p->mean_size : 0.0, &r));
-        IM_TRY(pool_append_staged(p, count, r.total_nodes));
-        p->edges += r.edges;
-        p->mean_size = double(p->total) / double(p->count);
+        SampleItem it{p->key, p->count, count, nullptr};
+        ItemTotals tot;
+        IM_TRY(sample_items(p->ctx, p->g, p->model, &it, 1, SampleMode::Pool, p->mean_size > 0 ? p->mean_size : 0.0,
+                            &r, &tot));
+        AppendItem ap{p, count, tot.nodes, tot.edges};
+        IM_TRY(pool_append_items(p->ctx, &ap, 1));
     }
     if (ms) *ms += now_ms() - t0;
     return IM_OK;
@@ -279,7 +276,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits,
-                      &c->zflags, &c->lt_tables})
+                      &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     delete c;

@@ -12,6 +12,7 @@
 // the previous round's decrements landed; the first rounds (the largest
 // covers) run as grid-wide kernels, the rest in one persistent workgroup.
 #include <algorithm>
+#include <vector>
 
 #include "im_device.hpp"
 #include "im_internal.hpp"
@@ -362,10 +363,12 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g) {
     if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
 }
 
-// Rounds [r0, k) in one workgroup. The cover step is flattened: first the
+// Rounds [r0, k) of job blockIdx.x in one workgroup. The cover step is
+// flattened: first the
 // winner's incidence entries (1024 at a time) yield the newly covered sets,
 // then their members are decremented 1024 at a time.
-__global__ __launch_bounds__(kPersistThreads) void persist_kernel(GreedyState g, uint32_t r0) {
+__global__ __launch_bounds__(kPersistThreads) void persist_kernel(const GreedyState *jobs, uint32_t r0) {
+    const GreedyState g = jobs[blockIdx.x];
     __shared__ unsigned long long smem[kPersistThreads / kWave];
     __shared__ uint32_t s_pick;
     __shared__ uint32_t s_nfresh;
@@ -529,14 +532,153 @@ __global__ __launch_bounds__(1024) void crossing_kernel(const uint8_t *z, uint64
     }
 }
 
+
+// ---- batched jobs: many pool ranges of one graph ----
+
+struct JobTable {
+    const uint64_t *poff;
+    const uint32_t *pnodes;
+    uint64_t begin;        // first set of the greedy range
+    uint64_t ebegin;       // pnodes index of its first entry
+    uint64_t set_start;    // flattened: sets of earlier jobs
+    uint64_t entry_start;  // flattened: entries of earlier jobs
+    uint64_t stare_begin;  // first set of the stare range
+    uint64_t stare_start;  // flattened: stare sets of earlier jobs
+    uint64_t seed_start;   // flattened: seeds of earlier jobs
+    uint32_t *gain;
+    uint32_t *fill;
+    uint32_t *stare_bits;  // seed bitmap for the stare step
+    unsigned long long *cov_c;
+};
+
+__device__ __forceinline__ uint32_t job_of(const JobTable *jt, uint32_t nj, uint64_t x, uint64_t JobTable::*field) {
+    uint32_t lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (jt[mid].*field <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// poff at the range ends of each job: out[4j..4j+3] = poff[begin], poff[end],
+// poff[stare_begin], poff[stare_end].
+__global__ void job_bounds_kernel(const uint64_t *const *poffs, const uint64_t *bounds, uint32_t nj, uint64_t *out) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * nj; i += gridDim.x * blockDim.x)
+        out[i] = poffs[i / 4][bounds[i]];
+}
+
+__global__ __launch_bounds__(kThreads) void batch_histogram_kernel(const JobTable *jt, uint32_t nj, uint64_t total) {
+    for (uint64_t x = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; x < total;
+         x += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const JobTable &j = jt[job_of(jt, nj, x, &JobTable::entry_start)];
+        atomicAdd(&j.gain[j.pnodes[j.ebegin + (x - j.entry_start)]], 1u);
+    }
+}
+
+// 16 lanes per set; isets positions come from the global prefix over all
+// jobs' counts (job j's counts occupy [j*n, j*n+n)).
+__global__ __launch_bounds__(kThreads) void batch_scatter_kernel(const JobTable *jt, uint32_t nj, uint64_t total_sets,
+                                                                 const uint64_t *prefix, uint32_t n, uint32_t *isets) {
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+    const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (uint64_t x = grp; x < total_sets; x += ngrp) {
+        const uint32_t ji = job_of(jt, nj, x, &JobTable::set_start);
+        const JobTable &j = jt[ji];
+        const uint64_t js = x - j.set_start;
+        const uint64_t a = j.poff[j.begin + js], b = j.poff[j.begin + js + 1];
+        for (uint64_t q = a + sub; q < b; q += 16) {
+            const uint32_t v = j.pnodes[q];
+            const uint32_t pos = atomicAdd(&j.fill[v], 1u);
+            isets[prefix[uint64_t(ji) * n + v] + pos] = static_cast<uint32_t>(js);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void batch_init_m1_kernel(const GreedyState *gs, uint32_t nj, uint32_t n1) {
+    const uint64_t total = uint64_t(nj) * n1;
+    for (uint64_t x = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; x < total;
+         x += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const GreedyState &g = gs[x / n1];
+        const uint32_t c = static_cast<uint32_t>(x % n1);
+        g.m1[c] = m1_lane<false>(g, c);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void batch_init_m2_kernel(const GreedyState *gs, uint32_t nj, uint32_t n2) {
+    const uint64_t total = uint64_t(nj) * n2;
+    for (uint64_t x = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; x < total;
+         x += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const GreedyState &g = gs[x / n2];
+        const uint32_t d = static_cast<uint32_t>(x % n2);
+        g.m2[d] = m2_lane<false>(g, d);
+    }
+}
+
+__global__ void batch_seed_bits_kernel(const JobTable *jt, uint32_t nj, const uint32_t *seeds, uint64_t total) {
+    for (uint64_t x = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; x < total;
+         x += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const JobTable &j = jt[job_of(jt, nj, x, &JobTable::seed_start)];
+        const uint32_t v = seeds[x];
+        atomicOr(&j.stare_bits[v >> 5], 1u << (v & 31u));
+    }
+}
+
+// Stare step of every job: its stare-range sets that meet its seed bitmap.
+__global__ __launch_bounds__(kThreads) void batch_coverage_kernel(const JobTable *jt, uint32_t nj, uint64_t total_sets) {
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+    const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (uint64_t x = grp; x < total_sets; x += ngrp) {
+        const JobTable &j = jt[job_of(jt, nj, x, &JobTable::stare_start)];
+        const uint64_t js = x - j.stare_start;
+        const uint64_t a = j.poff[j.stare_begin + js], b = j.poff[j.stare_begin + js + 1];
+        bool any = false;
+        for (uint64_t q = a + sub; q < b && !any; q += 16) any = test_bit(j.stare_bits, j.pnodes[q]);
+        const uint64_t mask = __ballot(any);
+        if (sub == 0 && ((mask >> (lane_id() & ~15u)) & 0xFFFFull)) atomicAdd(j.cov_c, 1ull);
+    }
+}
+
+// Estimate-Inf crossing for many items: block i walks flags [start, start+count)
+// in order, 1024 at a time, to the first index where the running count of
+// ones reaches need[i]. out[2i] = that index (relative) or -1; out[2i+1] =
+// ones in the whole segment.
+__global__ __launch_bounds__(1024) void crossing_items_kernel(const uint8_t *z, const uint64_t *seg, long long *out) {
+    __shared__ uint64_t smem[1024 / kWave];
+    __shared__ long long s_idx;
+    const uint64_t start = seg[3 * blockIdx.x], count = seg[3 * blockIdx.x + 1], need = seg[3 * blockIdx.x + 2];
+    if (threadIdx.x == 0) s_idx = -1;
+    __syncthreads();
+    uint64_t run = 0;
+    for (uint64_t b0 = 0; b0 < count; b0 += blockDim.x) {
+        const uint64_t i = b0 + threadIdx.x;
+        const uint64_t x = (i < count) ? z[start + i] : 0;
+        uint64_t total = 0;
+        const uint64_t ex = block_scan_excl(x, smem, total);
+        if (s_idx < 0 && x && run + ex + 1 == need) s_idx = static_cast<long long>(i);
+        run += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = s_idx;
+        out[2 * blockIdx.x + 1] = static_cast<long long>(run);
+    }
+}
+
 }  // namespace
 
 namespace im {
 
 im_status set_seed_bits(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k) {
+    return seed_bits_into(ctx, n, seeds_host, k, ctx->seedbits);
+}
+
+im_status seed_bits_into(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k, DevBuf &out) {
     const uint64_t words = (uint64_t(n) + 31) / 32;
-    IM_TRY(dev_reserve(ctx, ctx->seedbits, words * 4 + 4 * uint64_t(k) + 64));
-    auto *bits = static_cast<uint32_t *>(ctx->seedbits.ptr);
+    IM_TRY(dev_reserve(ctx, out, words * 4 + 4 * uint64_t(k) + 64));
+    auto *bits = static_cast<uint32_t *>(out.ptr);
     auto *dseeds = bits + words;
     auto *bad = dseeds + k;
     hipStream_t st = ctx->stream;
@@ -600,7 +742,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const size_t o_gain = take(4ull * n), o_fill = take(4ull * n), o_ioff = take(8ull * (n + 1)),
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
                  o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
-                 o_m2 = take(8ull * n2), o_cnt = take(16);
+                 o_m2 = take(8ull * n2), o_cnt = take(16), o_job = take(sizeof(GreedyState));
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
@@ -660,7 +802,11 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         refresh_choose_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
         cover_kernel<<<cgrid, kThreads, 0, st>>>(g);
     }
-    if (big < k) persist_kernel<<<1, kPersistThreads, 0, st>>>(g, big);
+    if (big < k) {
+        auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
+        IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
+        persist_kernel<<<1, kPersistThreads, 0, st>>>(dg, big);
+    }
     IM_HIP(hipGetLastError());
     IM_HIP(hipMemcpyAsync(seeds_host, g.seeds, 4ull * k, hipMemcpyDeviceToHost, st));
     IM_TRY(to_host_sync(ctx, cov, dcov, 8));
@@ -685,4 +831,169 @@ im_status first_crossing(im_ctx *ctx, uint64_t count, uint64_t need, int64_t *in
     return IM_OK;
 }
 
+
+im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, uint32_t nj) {
+    if (nj == 0) return IM_OK;
+    const uint32_t n = gr->n;
+    hipStream_t st = ctx->stream;
+    const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+    // range ends of every job in one read-back
+    std::vector<const uint64_t *> hpoffs(nj);
+    std::vector<uint64_t> hb(4ull * nj), he(4ull * nj);
+    for (uint32_t j = 0; j < nj; ++j) {
+        hpoffs[j] = static_cast<const uint64_t *>(jobs[j].pool->poff.ptr);
+        hb[4 * j] = jobs[j].begin;
+        hb[4 * j + 1] = jobs[j].end;
+        hb[4 * j + 2] = jobs[j].stare_begin;
+        hb[4 * j + 3] = jobs[j].stare_end;
+    }
+    IM_TRY(dev_reserve(ctx, ctx->scan_tmp, nj * (8 + 32 + 32) + 1024));
+    auto *d_poffs = static_cast<const uint64_t **>(ctx->scan_tmp.ptr);
+    auto *d_b = reinterpret_cast<uint64_t *>(d_poffs + nj);
+    auto *d_e = d_b + 4ull * nj;
+    IM_HIP(hipMemcpyAsync(d_poffs, hpoffs.data(), 8ull * nj, hipMemcpyHostToDevice, st));
+    IM_HIP(hipMemcpyAsync(d_b, hb.data(), 32ull * nj, hipMemcpyHostToDevice, st));
+    job_bounds_kernel<<<grid_of(4ull * nj, kThreads, 64), kThreads, 0, st>>>(d_poffs, d_b, nj, d_e);
+    IM_HIP(hipMemcpyAsync(he.data(), d_e, 32ull * nj, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipStreamSynchronize(st));
+
+    const uint32_t n1 = (n + (1u << kL1Shift) - 1) >> kL1Shift;
+    const uint32_t n2 = (n1 + (1u << kL2Shift) - 1) >> kL2Shift;
+    const uint64_t words = (uint64_t(n) + 31) / 32;
+    uint64_t tot_entries = 0, tot_sets = 0, tot_stare = 0, tot_seeds = 0, tot_cov = 0;
+    std::vector<JobTable> jt(nj);
+    std::vector<uint64_t> cov_off(nj);
+    for (uint32_t j = 0; j < nj; ++j) {
+        const CoverJob &cj = jobs[j];
+        jt[j].begin = cj.begin;
+        jt[j].ebegin = he[4 * j];
+        jt[j].set_start = tot_sets;
+        jt[j].entry_start = tot_entries;
+        jt[j].stare_begin = cj.stare_begin;
+        jt[j].stare_start = tot_stare;
+        jt[j].seed_start = tot_seeds;
+        cov_off[j] = tot_cov;
+        tot_entries += he[4 * j + 1] - he[4 * j];
+        tot_sets += cj.end - cj.begin;
+        tot_stare += cj.stare_end - cj.stare_begin;
+        tot_seeds += cj.k;
+        tot_cov += (cj.end - cj.begin + 31) / 32 + 1;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return at;
+    };
+    const uint64_t cells = uint64_t(nj) * n;
+    const uint64_t tiles = (cells + kTile - 1) / kTile;
+    const size_t o_gain = take(4 * cells), o_fill = take(4 * cells), o_prefix = take(8 * (cells + 1)),
+                 o_tsum = take(8 * (tiles + 1)), o_isets = take(4 * (tot_entries + 1)), o_covbits = take(4 * tot_cov),
+                 o_m1 = take(8ull * nj * n1), o_m2 = take(8ull * nj * n2), o_seeds = take(4 * (tot_seeds + 1)),
+                 o_cov = take(8ull * nj), o_covc = take(8ull * nj), o_bits = take(4 * words * nj),
+                 o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj);
+    IM_TRY(dev_reserve(ctx, ctx->cover, off));
+    char *base = static_cast<char *>(ctx->cover.ptr);
+    auto *gains = reinterpret_cast<uint32_t *>(base + o_gain);
+    auto *fills = reinterpret_cast<uint32_t *>(base + o_fill);
+    auto *prefix = reinterpret_cast<uint64_t *>(base + o_prefix);
+    auto *tsum = reinterpret_cast<uint64_t *>(base + o_tsum);
+    auto *isets = reinterpret_cast<uint32_t *>(base + o_isets);
+    auto *covbits = reinterpret_cast<uint32_t *>(base + o_covbits);
+    auto *seeds = reinterpret_cast<uint32_t *>(base + o_seeds);
+    auto *covs = reinterpret_cast<unsigned long long *>(base + o_cov);
+    auto *covcs = reinterpret_cast<unsigned long long *>(base + o_covc);
+    auto *bits = reinterpret_cast<uint32_t *>(base + o_bits);
+    auto *djt = reinterpret_cast<JobTable *>(base + o_jt);
+    auto *dgs = reinterpret_cast<GreedyState *>(base + o_gs);
+    std::vector<GreedyState> gs(nj);
+    for (uint32_t j = 0; j < nj; ++j) {
+        const CoverJob &cj = jobs[j];
+        jt[j].poff = static_cast<const uint64_t *>(cj.pool->poff.ptr);
+        jt[j].pnodes = static_cast<const uint32_t *>(cj.pool->pnodes.ptr);
+        jt[j].gain = gains + uint64_t(j) * n;
+        jt[j].fill = fills + uint64_t(j) * n;
+        jt[j].stare_bits = bits + uint64_t(j) * words;
+        jt[j].cov_c = covcs + j;
+        GreedyState &g = gs[j];
+        g.gain = jt[j].gain;
+        g.m1 = reinterpret_cast<unsigned long long *>(base + o_m1) + uint64_t(j) * n1;
+        g.m2 = reinterpret_cast<unsigned long long *>(base + o_m2) + uint64_t(j) * n2;
+        g.covbits = covbits + cov_off[j];
+        g.ioff = prefix + uint64_t(j) * n;
+        g.isets = isets;
+        g.poff = jt[j].poff;
+        g.pnodes = jt[j].pnodes;
+        g.begin = cj.begin;
+        g.n = n;
+        g.n1 = n1;
+        g.n2 = n2;
+        g.k = cj.k;
+        g.seeds = seeds + jt[j].seed_start;
+        g.pick = nullptr;
+        g.done = nullptr;
+        g.cov = covs + j;
+    }
+    IM_HIP(hipMemcpyAsync(djt, jt.data(), sizeof(JobTable) * nj, hipMemcpyHostToDevice, st));
+    IM_HIP(hipMemcpyAsync(dgs, gs.data(), sizeof(GreedyState) * nj, hipMemcpyHostToDevice, st));
+    fill_u32_kernel<<<grid_of(cells, kThreads, cu * 8), kThreads, 0, st>>>(gains, cells, 0u);
+    fill_u32_kernel<<<grid_of(cells, kThreads, cu * 8), kThreads, 0, st>>>(fills, cells, 0u);
+    fill_u32_kernel<<<grid_of(tot_cov, kThreads, cu * 8), kThreads, 0, st>>>(covbits, tot_cov, 0u);
+    fill_u32_kernel<<<grid_of(words * nj, kThreads, cu * 8), kThreads, 0, st>>>(bits, words * nj, 0u);
+    fill_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(covs), nj, 0);
+    fill_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(covcs), nj, 0);
+    if (tot_entries)
+        batch_histogram_kernel<<<grid_of(tot_entries, kThreads, cu * 16), kThreads, 0, st>>>(djt, nj, tot_entries);
+    tile_sums_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gains, cells, tsum);
+    tile_scan_kernel<<<1, 1024, 0, st>>>(tsum, tiles);
+    tile_apply_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gains, cells, tsum, prefix);
+    if (tot_sets)
+        batch_scatter_kernel<<<grid_of(tot_sets * 16, kThreads, cu * 16), kThreads, 0, st>>>(djt, nj, tot_sets, prefix, n,
+                                                                                             isets);
+    batch_init_m1_kernel<<<grid_of(uint64_t(nj) * n1, kThreads, cu * 8), kThreads, 0, st>>>(dgs, nj, n1);
+    batch_init_m2_kernel<<<grid_of(uint64_t(nj) * n2, kThreads, cu * 8), kThreads, 0, st>>>(dgs, nj, n2);
+    persist_kernel<<<nj, kPersistThreads, 0, st>>>(dgs, 0);
+    if (tot_stare) {
+        batch_seed_bits_kernel<<<grid_of(tot_seeds, kThreads, cu * 4), kThreads, 0, st>>>(djt, nj, seeds, tot_seeds);
+        batch_coverage_kernel<<<grid_of(tot_stare * 16, kThreads, cu * 16), kThreads, 0, st>>>(djt, nj, tot_stare);
+    }
+    IM_HIP(hipGetLastError());
+    std::vector<uint32_t> hseeds(tot_seeds);
+    std::vector<unsigned long long> hcov(2ull * nj);
+    IM_HIP(hipMemcpyAsync(hseeds.data(), seeds, 4 * tot_seeds, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipMemcpyAsync(hcov.data(), covs, 8ull * nj, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipMemcpyAsync(hcov.data() + nj, covcs, 8ull * nj, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipStreamSynchronize(st));
+    for (uint32_t j = 0; j < nj; ++j) {
+        std::copy(hseeds.begin() + jt[j].seed_start, hseeds.begin() + jt[j].seed_start + jobs[j].k, jobs[j].seeds);
+        jobs[j].cov = hcov[j];
+        jobs[j].cov_c = hcov[nj + j];
+    }
+    return IM_OK;
+}
+
+im_status first_crossing_items(im_ctx *ctx, const CrossItem *items, uint32_t nitems) {
+    if (nitems == 0) return IM_OK;
+    hipStream_t st = ctx->stream;
+    IM_TRY(dev_reserve(ctx, ctx->scan_tmp, 40ull * nitems + 256));
+    auto *dseg = static_cast<uint64_t *>(ctx->scan_tmp.ptr);
+    auto *dout = reinterpret_cast<long long *>(dseg + 3ull * nitems);
+    std::vector<uint64_t> seg(3ull * nitems);
+    for (uint32_t i = 0; i < nitems; ++i) {
+        seg[3 * i] = items[i].start;
+        seg[3 * i + 1] = items[i].count;
+        seg[3 * i + 2] = items[i].need;
+    }
+    IM_HIP(hipMemcpyAsync(dseg, seg.data(), 24ull * nitems, hipMemcpyHostToDevice, st));
+    crossing_items_kernel<<<nitems, 1024, 0, st>>>(static_cast<const uint8_t *>(ctx->zflags.ptr), dseg, dout);
+    IM_HIP(hipGetLastError());
+    std::vector<long long> out(2ull * nitems);
+    IM_HIP(hipMemcpyAsync(out.data(), dout, 16ull * nitems, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipStreamSynchronize(st));
+    for (uint32_t i = 0; i < nitems; ++i) {
+        items[i].index[0] = out[2 * i];
+        items[i].hits[0] = static_cast<uint64_t>(out[2 * i + 1]);
+    }
+    return IM_OK;
+}
 }  // namespace im

@@ -64,6 +64,8 @@ struct im_ctx {
     DevBuf cover;        // incidence / greedy working arrays
     DevBuf seedbits;     // seed-set bitmap (n bits)
     DevBuf zflags;       // Estimate-Inf per-sample hit flags
+    DevBuf items;        // fused sampler work queue + per-item accumulators
+    DevBuf append_dst;   // per-item pool destinations of a fused append
     void *host_pinned = nullptr;  // small pinned staging for read-backs
 
     // optional event timing of the main sampler launches
@@ -118,7 +120,40 @@ struct SampleResult {
     uint64_t total_nodes = 0;  // Pool mode: sum of set sizes of the batch
     uint64_t edges = 0;        // edges traversed
     uint64_t deferred = 0;     // samples that took the long path
+    uint64_t count = 0;        // samples drawn
 };
+
+// One query's share of a fused sampling launch: samples [s0, s0+count) of
+// stream `key`; hits mode tests them against the device bitmap `seedbits`.
+struct SampleItem {
+    uint64_t key;
+    uint64_t s0;
+    uint64_t count;
+    const uint32_t *seedbits;
+};
+
+struct ItemTotals {
+    uint64_t nodes = 0;  // node entries of the item's sets
+    uint64_t edges = 0;  // edges its samples traversed
+};
+
+// Where a fused batch's item goes: the next `count` staged slots (in item
+// order) are appended to `pool`.
+struct AppendItem {
+    im_pool *pool;
+    uint64_t count;
+    uint64_t nodes;
+    uint64_t edges;
+};
+
+// Draw every item in one launch (slots laid out item after item). Pool mode
+// leaves the sets in ctx->stage with per-slot (offset, size) in
+// ctx->sample_meta; Hits mode leaves one u8 flag per slot in ctx->zflags.
+im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const SampleItem *items, uint32_t nitems,
+                       SampleMode mode, double size_hint, SampleResult *res, ItemTotals *per_item);
+
+// Append a fused batch, item by item, to the items' pools in sample order.
+im_status pool_append_items(im_ctx *ctx, const AppendItem *items, uint32_t nitems);
 
 // Draw samples [s0, s0+count) of stream `key` for `model`. Pool mode leaves
 // the sets in ctx->stage with per-sample (offset, size) in ctx->sample_meta;
@@ -127,8 +162,6 @@ struct SampleResult {
 im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t key, uint64_t s0,
                        uint64_t count, SampleMode mode, double size_hint, SampleResult *res);
 
-// Append the staged batch (`count` samples) to the pool, in sample order.
-im_status pool_append_staged(im_pool *p, uint64_t count, uint64_t total_nodes);
 
 // Max-Coverage (Algorithm 2) over pool sets [begin, end); seeds stay on
 // device in ctx->cover too; seeds_host[k] and *cov are written.
@@ -143,6 +176,31 @@ im_status set_seed_bits(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uin
 // `need` (or -1), plus the number of hits in the range.
 im_status first_crossing(im_ctx *ctx, uint64_t count, uint64_t need, int64_t *index, uint64_t *hits);
 
+// One Max-Coverage job of a batch: greedy over pool sets [begin, end), then
+// (if stare_end > stare_begin) the coverage of its seeds over
+// [stare_begin, stare_end). seeds[k] is host memory.
+struct CoverJob {
+    const im_pool *pool;
+    uint64_t begin, end;
+    uint32_t k;
+    uint64_t stare_begin, stare_end;
+    uint32_t *seeds;
+    uint64_t cov = 0;
+    uint64_t cov_c = 0;
+};
+
+// Every job of one graph in one pass: a flattened incidence build, one
+// workgroup per job for its k rounds, a flattened stare step.
+im_status max_coverage_batch(im_ctx *ctx, const im_graph *g, CoverJob *jobs, uint32_t njobs);
+
+// Estimate-Inf crossing search for many items of one hits-mode launch.
+struct CrossItem {
+    uint64_t start, count, need;
+    int64_t *index;  // out: first index (relative) where the count reaches need, or -1
+    uint64_t *hits;  // out: ones in the segment
+};
+im_status first_crossing_items(im_ctx *ctx, const CrossItem *items, uint32_t nitems);
+
 // Estimate-Inf (Algorithm 3) with an optional expected-T hint for chunking.
 im_status estimate_inf(const im_graph *g, im_model model, const uint32_t *seeds, uint32_t k, double eps_p,
                        double delta_p, double t_max, uint64_t key, double t_hint, double *ic_out,
@@ -154,5 +212,20 @@ im_status graph_build(im_graph *g, const uint32_t *src, const uint32_t *dst, con
 im_status graph_source_weights(im_graph *g, const uint32_t *node_w);
 
 double now_ms();
+
+// Constants of Algorithms 1 and 4 (Table 1's Upsilon; N_max, i_max = t_max,
+// Lambda), computed in the order the paper writes them.
+struct Caps {
+    double n_max, i_max, lambda;
+};
+double ups_ln(double eps, double ln_inv_delta);
+double upsilon(double eps, double delta);
+double ln_choose(uint32_t n, uint32_t k);
+Caps caps(uint32_t n, uint32_t k, double eps, double delta);
+im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps, double delta);
+uint64_t derived_key(uint64_t key, uint64_t i);
+uint64_t max_batch(im_model model);
+// Seed bitmap of n bits in `out` from host seeds.
+im_status seed_bits_into(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k, DevBuf &out);
 
 }  // namespace im

@@ -21,6 +21,7 @@
 //       each set is copied from staging into the flat pool.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "im_device.hpp"
 #include "im_internal.hpp"
@@ -49,14 +50,25 @@ struct Counters {
     unsigned long long nodes_long;   // long path
 };
 
+// One entry of the device work queue: samples [s0, s0+count) of stream
+// `key`, occupying global slots [start, start+count) of the launch.
+struct WorkItem {
+    uint64_t key;
+    uint64_t s0;
+    uint32_t start;
+    uint32_t count;
+    const uint32_t *seedbits;  // hits mode: the query's seed bitmap
+    unsigned long long *acc;   // per item: [0] node entries drawn, [1] edges traversed
+};
+
 struct Params {
     const uint64_t *off;
     const uint2 *edges;
     const uint64_t *src_cum;  // weighted sources, or null
     uint32_t n;
-    uint32_t count;
-    uint64_t key;
-    uint64_t s0;
+    uint32_t count;  // slots over all items
+    const WorkItem *items;
+    uint32_t nitems;
     Counters *cnt;
     uint32_t *defer_list;
     uint32_t *stage;
@@ -64,9 +76,19 @@ struct Params {
     uint64_t *stage_off;  // per sample
     uint32_t *sizes;      // per sample
     uint8_t *z;           // per sample (hits mode)
-    const uint32_t *seedbits;
     uint32_t lt_cap;
 };
+
+// The work item owning global slot t.
+__device__ __forceinline__ const WorkItem &item_of(const Params &p, uint32_t t) {
+    uint32_t lo = 0, hi = p.nitems - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (p.items[mid].start <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return p.items[lo];
+}
 
 __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
     c->ticket = 0;
@@ -148,8 +170,6 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
     uint32_t *pre = s_pre[wave];
     uint64_t *fa = s_a[wave];
     uint64_t *fb = s_b[wave];
-    const Stream st(p.key);
-
     for (uint32_t i = lane; i < kIcHcap; i += kWave) vis[i] = 0u;
     wave_sync();
     uint64_t edges_acc = 0, nodes_acc = 0;
@@ -159,7 +179,10 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
         if (lane == 0) t = atomicAdd(&p.cnt->ticket, 1u);
         t = __shfl(t, 0, kWave);
         if (t >= p.count) break;
-        const uint64_t s = p.s0 + t;
+        const WorkItem &it = item_of(p, t);
+        const Stream st(it.key);
+        const uint32_t *seedbits = it.seedbits;
+        const uint64_t s = it.s0 + (t - it.start);
         const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
         bool full = false;
         if (lane == 0) {
@@ -167,7 +190,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
             queue[0] = v0;
         }
         uint32_t head = 0, tail = 1;
-        bool hit = (kMode == 1) && test_bit(p.seedbits, v0);
+        bool hit = (kMode == 1) && test_bit(seedbits, v0);
         uint64_t sample_edges = 0;
         wave_sync();
 
@@ -229,7 +252,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                         const uint32_t pos = tail + lanes_below(mask);
                         if (has) {
                             if (pos < kIcQcap) queue[pos] = f;
-                            if (kMode == 1 && test_bit(p.seedbits, f)) hit = true;
+                            if (kMode == 1 && test_bit(seedbits, f)) hit = true;
                         }
                         tail += static_cast<uint32_t>(__popcll(mask));
                     }
@@ -251,11 +274,16 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                 p.defer_list[d] = t;
             }
         } else if (kMode == 1) {
-            if (lane == 0) p.z[t] = hit ? 1 : 0;
+            if (lane == 0) {
+                p.z[t] = hit ? 1 : 0;
+                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
+            }
             edges_acc += sample_edges;
         } else {
             unsigned long long base = 0;
             if (lane == 0) {
+                atomicAdd(&it.acc[0], static_cast<unsigned long long>(tail));
+                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
                 base = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(tail));
                 if (base + tail > p.stage_cap) {
                     atomicOr(&p.cnt->overflow, 1u);
@@ -360,7 +388,9 @@ template <int kMode>
 __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tables, uint32_t stamp_base) {
     const uint32_t lane = lane_id();
     uint64_t *table = tables + (static_cast<uint64_t>(blockIdx.x) * kWave + lane) * kLtTableSlots;
-    const Stream st(p.key);
+    Stream st(0);
+    const uint32_t *seedbits = nullptr;
+    unsigned long long *acc = nullptr;
 
     bool active = false, finished = false;
     uint32_t t = 0, v = 0, len = 0, stamp = 0;
@@ -380,7 +410,11 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                 const uint32_t mine = base + lanes_below(mask);
                 if (mine < p.count) {
                     t = mine;
-                    s = p.s0 + t;
+                    const WorkItem &it = item_of(p, t);
+                    st = Stream(it.key);
+                    seedbits = it.seedbits;
+                    acc = it.acc;
+                    s = it.s0 + (t - it.start);
                     stamp = stamp_base + t;
                     v = pick_source(st, s, p.src_cum, p.n);
                     region = p.stage + static_cast<uint64_t>(t) * p.lt_cap;
@@ -391,9 +425,10 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                     a = p.off[v];
                     b = p.off[v + 1];
                     active = true;
-                    if (kMode == 1 && test_bit(p.seedbits, v)) {
+                    if (kMode == 1 && test_bit(seedbits, v)) {
                         p.z[t] = 1;
                         edges_acc += 1;
+                        atomicAdd(&acc[1], 1ull);
                         active = false;
                     }
                 } else {
@@ -447,7 +482,9 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                 p.sizes[t] = len;
                 p.stage_off[t] = static_cast<uint64_t>(t) * p.lt_cap;
                 nodes_acc += len;
+                atomicAdd(&acc[0], static_cast<unsigned long long>(len));
             }
+            atomicAdd(&acc[1], static_cast<unsigned long long>(len));
             edges_acc += len;
             active = false;
             continue;
@@ -462,9 +499,10 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
         v = u;
         a = na;
         b = nb;
-        if (kMode == 1 && test_bit(p.seedbits, u)) {
+        if (kMode == 1 && test_bit(seedbits, u)) {
             p.z[t] = 1;
             edges_acc += len;
+            atomicAdd(&acc[1], static_cast<unsigned long long>(len));
             active = false;
         }
     }
@@ -494,7 +532,6 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
     uint32_t *pre = s_pre[wave];
     uint64_t *fa = s_a[wave];
     uint64_t *fb = s_b[wave];
-    const Stream st(p.key);
     uint64_t edges_acc = 0, nodes_acc = 0;
 
     for (;;) {
@@ -503,12 +540,15 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
         d = __shfl(d, 0, kWave);
         if (d >= p.cnt->defer_count) break;
         const uint32_t t = p.defer_list[d];
-        const uint64_t s = p.s0 + t;
+        const WorkItem &it = item_of(p, t);
+        const Stream st(it.key);
+        const uint32_t *seedbits = it.seedbits;
+        const uint64_t s = it.s0 + (t - it.start);
         uint32_t stamp = 0;
         if (lane == 0) stamp = ++slot_epoch[slot];
         stamp = __shfl(stamp, 0, kWave);
         const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
-        bool hit = (kMode == 1) && test_bit(p.seedbits, v0);
+        bool hit = (kMode == 1) && test_bit(seedbits, v0);
         uint32_t tail = 1;
         uint64_t sample_edges = 0;
         if (lane == 0) {
@@ -530,7 +570,7 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
                     vis[u] = stamp;
                     queue[tail++] = u;
                     v = u;
-                    if (kMode == 1 && test_bit(p.seedbits, u)) {
+                    if (kMode == 1 && test_bit(seedbits, u)) {
                         hit = true;
                         break;
                     }
@@ -589,7 +629,7 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
                         if (mask) {
                             if (has) {
                                 queue[tail + lanes_below(mask)] = f[q];
-                                if (kMode == 1 && test_bit(p.seedbits, f[q])) hit = true;
+                                if (kMode == 1 && test_bit(seedbits, f[q])) hit = true;
                             }
                             tail += static_cast<uint32_t>(__popcll(mask));
                         }
@@ -602,11 +642,16 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
             }
         }
         if (kMode == 1) {
-            if (lane == 0) p.z[t] = hit ? 1 : 0;
+            if (lane == 0) {
+                p.z[t] = hit ? 1 : 0;
+                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
+            }
             edges_acc += sample_edges;
         } else {
             unsigned long long base = 0;
             if (lane == 0) {
+                atomicAdd(&it.acc[0], static_cast<unsigned long long>(tail));
+                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
                 base = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(tail));
                 if (base + tail > p.stage_cap) {
                     atomicOr(&p.cnt->overflow, 1u);
@@ -714,20 +759,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
 
 __global__ void set_first_kernel(uint64_t *out, uint64_t value) { out[0] = value; }
 
-// 16 lanes per sample copy its set from staging into the pool.
-__global__ __launch_bounds__(256) void compact_kernel(const uint32_t *stage, const uint64_t *stage_off,
-                                                      const uint64_t *poff, uint32_t *pnodes, uint64_t count) {
-    const uint32_t sub = threadIdx.x & 15u;
-    const uint64_t group = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
-    const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
-    for (uint64_t i = group; i < count; i += groups) {
-        const uint64_t dst = poff[i];
-        const uint64_t len = poff[i + 1] - dst;
-        const uint32_t *src = stage + stage_off[i];
-        for (uint64_t j = sub; j < len; j += 16) pnodes[dst + j] = src[j];
-    }
-}
-
 __global__ void zero_u64_kernel(uint64_t *p, uint64_t count) {
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
          i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -744,6 +775,38 @@ __global__ void copy_u32_kernel(const uint32_t *src, uint32_t *dst, uint64_t cou
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
          i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
         dst[i] = src[i];
+}
+
+// Destination of one work item's sets in its pool.
+struct AppendDst {
+    uint64_t *poff;    // the pool's offsets at its current count (poff[0] = its total)
+    uint32_t *pnodes;  // the pool's node array
+    uint64_t base;     // the pool's total before the append
+    uint32_t start;    // the item's first slot in the batch
+};
+
+// 16 lanes per slot: write the slot's pool offset and copy its set.
+__global__ __launch_bounds__(256) void compact_items_kernel(const uint32_t *stage, const uint64_t *stage_off,
+                                                            const uint64_t *prefix, const AppendDst *dst,
+                                                            uint32_t nitems, uint64_t count) {
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t group = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+    const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (uint64_t t = group; t < count; t += groups) {
+        uint32_t lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (dst[mid].start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const AppendDst d = dst[lo];
+        const uint64_t rel = prefix[t] - prefix[d.start];
+        const uint64_t len = prefix[t + 1] - prefix[t];
+        if (sub == 0) d.poff[t - d.start + 1] = d.base + rel + len;
+        const uint32_t *src = stage + stage_off[t];
+        uint32_t *out = d.pnodes + d.base + rel;
+        for (uint64_t j = sub; j < len; j += 16) out[j] = src[j];
+    }
 }
 
 uint32_t blocks_for(uint64_t items, uint32_t per_block, uint32_t cap) {
@@ -794,10 +857,15 @@ static im_status ensure_slots(im_ctx *ctx, uint32_t n) {
     return IM_OK;
 }
 
-im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t key, uint64_t s0,
-                       uint64_t count, SampleMode mode, double size_hint, SampleResult *res) {
+im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const SampleItem *items, uint32_t nitems,
+                       SampleMode mode, double size_hint, SampleResult *res, ItemTotals *per_item) {
     *res = SampleResult{};
-    if (count == 0) return IM_OK;
+    uint64_t count = 0;
+    for (uint32_t i = 0; i < nitems; ++i) count += items[i].count;
+    if (count == 0 || nitems == 0) {
+        for (uint32_t i = 0; i < nitems; ++i) per_item[i] = ItemTotals{};
+        return IM_OK;
+    }
     if (count > 0xFFFFFFF0ull) {
         set_error("sample batch of %llu samples is too large", static_cast<unsigned long long>(count));
         return IM_E_ARG;
@@ -806,6 +874,7 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
     hipStream_t st = ctx->stream;
     IM_TRY(dev_reserve(ctx, ctx->sample_meta, meta_bytes(count)));
     IM_TRY(dev_reserve(ctx, ctx->counters, 256));
+    IM_TRY(dev_reserve(ctx, ctx->items, size_t(nitems) * (sizeof(WorkItem) + 16) + 256));
     if (mode == SampleMode::Hits) IM_TRY(dev_reserve(ctx, ctx->zflags, count + 64));
     IM_TRY(ensure_slots(ctx, g->n));
     if (model == IM_LT && !ctx->lt_tables.ptr) {
@@ -819,6 +888,18 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
     }
     Meta meta = meta_view(ctx, count);
     auto *cnt = static_cast<Counters *>(ctx->counters.ptr);
+    // device work queue: items, then their accumulators
+    auto *ditems = static_cast<WorkItem *>(ctx->items.ptr);
+    auto *dacc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->items.ptr) +
+                                                        ((size_t(nitems) * sizeof(WorkItem) + 255) & ~size_t(255)));
+    std::vector<WorkItem> hitems(nitems);
+    uint32_t start = 0;
+    for (uint32_t i = 0; i < nitems; ++i) {
+        hitems[i] = WorkItem{items[i].key, items[i].s0, start, static_cast<uint32_t>(items[i].count),
+                             items[i].seedbits, dacc + 2ull * i};
+        start += static_cast<uint32_t>(items[i].count);
+    }
+    IM_HIP(hipMemcpyAsync(ditems, hitems.data(), sizeof(WorkItem) * nitems, hipMemcpyHostToDevice, st));
 
     // staging capacity: LT reserves a region per sample, then a bump area
     // for long walks; IC bump-allocates every set.
@@ -835,8 +916,8 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
         p.src_cum = static_cast<const uint64_t *>(g->src_cum.ptr);
         p.n = g->n;
         p.count = static_cast<uint32_t>(count);
-        p.key = key;
-        p.s0 = s0;
+        p.items = ditems;
+        p.nitems = nitems;
         p.cnt = cnt;
         p.defer_list = meta.defer_list;
         p.stage = static_cast<uint32_t *>(ctx->stage.ptr);
@@ -844,10 +925,10 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
         p.stage_off = meta.stage_off;
         p.sizes = meta.sizes;
         p.z = (mode == SampleMode::Hits) ? static_cast<uint8_t *>(ctx->zflags.ptr) : meta.z;
-        p.seedbits = static_cast<const uint32_t *>(ctx->seedbits.ptr);
         p.lt_cap = kLtCap;
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
+        zero_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(dacc), 2ull * nitems);
         const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
         if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_begin, st));
         if (model == IM_IC) {
@@ -889,15 +970,19 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
         }
         IM_HIP(hipGetLastError());
         Counters hc{};
+        std::vector<unsigned long long> hacc(2ull * nitems);
+        IM_HIP(hipMemcpyAsync(hacc.data(), dacc, 16ull * nitems, hipMemcpyDeviceToHost, st));
         IM_TRY(to_host_sync(ctx, &hc, cnt, sizeof(hc)));
         ctx->slot_epoch += hc.defer_count;
         if (hc.overflow) {
             cap = std::max<uint64_t>(cap * 2, hc.stage_cursor + (1u << 20));
             continue;
         }
+        for (uint32_t i = 0; i < nitems; ++i) per_item[i] = ItemTotals{hacc[2 * i], hacc[2 * i + 1]};
         res->total_nodes = hc.total_nodes + hc.nodes_long;
         res->edges = hc.edges + hc.edges_long;
         res->deferred = hc.defer_count;
+        res->count = count;
         if (ctx->timing && mode == SampleMode::Pool) {
             float ms = 0.f;
             IM_HIP(hipEventElapsedTime(&ms, ctx->ev_begin, ctx->ev_end));
@@ -912,6 +997,13 @@ im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t 
     }
     set_error("sampler staging kept overflowing");
     return IM_E_OOM;
+}
+
+im_status sample_batch(im_ctx *ctx, const im_graph *g, im_model model, uint64_t key, uint64_t s0, uint64_t count,
+                       SampleMode mode, double size_hint, SampleResult *res) {
+    SampleItem it{key, s0, count, static_cast<const uint32_t *>(ctx->seedbits.ptr)};
+    ItemTotals tot;
+    return sample_items(ctx, g, model, &it, 1, mode, size_hint, res, &tot);
 }
 
 static im_status grow_pool(im_pool *p, uint64_t need_sets, uint64_t need_nodes) {
@@ -947,32 +1039,58 @@ static im_status grow_pool(im_pool *p, uint64_t need_sets, uint64_t need_nodes) 
     return IM_OK;
 }
 
-im_status pool_append_staged(im_pool *p, uint64_t count, uint64_t total_nodes) {
-    if (count == 0) return IM_OK;
-    im_ctx *ctx = p->ctx;
+im_status pool_append_items(im_ctx *ctx, const AppendItem *items, uint32_t nitems) {
+    if (nitems == 0) return IM_OK;
     hipStream_t st = ctx->stream;
-    IM_TRY(grow_pool(p, p->count + count, p->total + total_nodes + 1));
+    uint64_t count = 0;
+    for (uint32_t i = 0; i < nitems; ++i) {
+        const AppendItem &a = items[i];
+        IM_TRY(grow_pool(a.pool, a.pool->count + a.count, a.pool->total + a.nodes + 1));
+        count += a.count;
+    }
+    if (count == 0) return IM_OK;
     Meta meta = meta_view(ctx, count);
+    // global exclusive prefix of the batch's set sizes: prefix[t] (count+1)
     const uint64_t tiles = (count + kScanTile - 1) / kScanTile;
-    IM_TRY(dev_reserve(ctx, ctx->scan_tmp, (tiles + 1) * 8));
+    IM_TRY(dev_reserve(ctx, ctx->scan_tmp, (tiles + 1) * 8 + (count + 1) * 8 + 256));
     auto *tsum = static_cast<uint64_t *>(ctx->scan_tmp.ptr);
-    auto *poff = static_cast<uint64_t *>(p->poff.ptr) + p->count;  // poff[count] already holds p->total
+    auto *prefix = tsum + ((tiles + 1 + 31) & ~uint64_t(31));
+    set_first_kernel<<<1, 1, 0, st>>>(prefix, 0);
     scan_tiles_kernel<<<static_cast<uint32_t>(tiles), kScanThreads, 0, st>>>(meta.sizes, count, tsum);
     scan_sums_kernel<<<1, 1024, 0, st>>>(tsum, tiles);
-    scan_apply_kernel<<<static_cast<uint32_t>(tiles), kScanThreads, 0, st>>>(meta.sizes, count, tsum, p->total, poff);
-    compact_kernel<<<blocks_for(count * 16, 256, static_cast<uint32_t>(ctx->cu_count) * 16), 256, 0, st>>>(
-        static_cast<const uint32_t *>(ctx->stage.ptr), meta.stage_off, poff, static_cast<uint32_t *>(p->pnodes.ptr),
-        count);
-    IM_HIP(hipGetLastError());
-    uint64_t end = 0;
-    IM_TRY(to_host_sync(ctx, &end, poff + count, 8));
-    if (end != p->total + total_nodes) {
-        set_error("pool append: offsets end at %llu, expected %llu", static_cast<unsigned long long>(end),
-                  static_cast<unsigned long long>(p->total + total_nodes));
-        return IM_E_DEVICE;
+    scan_apply_kernel<<<static_cast<uint32_t>(tiles), kScanThreads, 0, st>>>(meta.sizes, count, tsum, 0, prefix);
+    // per-item destinations
+    std::vector<AppendDst> hd(nitems);
+    uint32_t start = 0;
+    for (uint32_t i = 0; i < nitems; ++i) {
+        im_pool *pl = items[i].pool;
+        hd[i] = AppendDst{static_cast<uint64_t *>(pl->poff.ptr) + pl->count, static_cast<uint32_t *>(pl->pnodes.ptr),
+                          pl->total, start};
+        start += static_cast<uint32_t>(items[i].count);
     }
-    p->count += count;
-    p->total = end;
+    IM_TRY(dev_reserve(ctx, ctx->append_dst, sizeof(AppendDst) * nitems + 64));
+    auto *dd = static_cast<AppendDst *>(ctx->append_dst.ptr);
+    IM_HIP(hipMemcpyAsync(dd, hd.data(), sizeof(AppendDst) * nitems, hipMemcpyHostToDevice, st));
+    compact_items_kernel<<<blocks_for(count * 16, 256, static_cast<uint32_t>(ctx->cu_count) * 16), 256, 0, st>>>(
+        static_cast<const uint32_t *>(ctx->stage.ptr), meta.stage_off, prefix, dd, nitems, count);
+    IM_HIP(hipGetLastError());
+    for (uint32_t i = 0; i < nitems; ++i) {
+        im_pool *pl = items[i].pool;
+        pl->count += items[i].count;
+        pl->total += items[i].nodes;
+        pl->edges += items[i].edges;
+        if (pl->count) pl->mean_size = double(pl->total) / double(pl->count);
+    }
+    if (nitems == 1) {  // cross-check the device offsets against the item totals
+        uint64_t end = 0;
+        im_pool *pl = items[0].pool;
+        IM_TRY(to_host_sync(ctx, &end, static_cast<const uint64_t *>(pl->poff.ptr) + pl->count, 8));
+        if (end != pl->total) {
+            set_error("pool append: offsets end at %llu, expected %llu", static_cast<unsigned long long>(end),
+                      static_cast<unsigned long long>(pl->total));
+            return IM_E_DEVICE;
+        }
+    }
     return IM_OK;
 }
 

@@ -1,0 +1,166 @@
+"""GPU tests of the multi-query engine: every query's result equals the
+single-query run (im_ssa / im_dssa) with the same arguments and the oracle,
+whatever else is admitted beside it, under any admission limits."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import note
+
+pytestmark = pytest.mark.gpu
+
+INT_KEYS = ["iterations", "stopped_by_cap", "n_sets", "n_verify", "cov", "cov_c", "edges", "it_sets", "it_cov",
+            "it_cov_c"]
+FP_KEYS = ["i_hat", "i_c", "eps1", "eps2", "eps3", "eps_t"]
+
+
+@pytest.fixture(scope="module")
+def im():
+    from paper_1605_07990_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(im):
+    c = im.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def graphs(im, ctx):
+    out = {}
+    for name in ("cl_small", "nethept", "rmat16"):
+        g = synth.make(name)
+        out[name] = (g, im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic, w_lt=g.w_lt))
+    return out
+
+
+def _same(a, b):
+    """Engine and single-query results agree exactly (the engine runs the
+    same FP64 code on the same integers)."""
+    sa, sta = a
+    sb, stb = b
+    assert sa.tolist() == sb.tolist()
+    for key in INT_KEYS:
+        assert sta[key] == stb[key], (key, sta[key], stb[key])
+    for key in FP_KEYS:
+        assert sta[key] == stb[key], (key, sta[key], stb[key])
+    assert sta["it_eps_t"] == stb["it_eps_t"]
+
+
+# (graph, model, algo, k, eps, key): a mix of IC and LT, SSA and D-SSA,
+# budgets from 1 to 60 and several precisions, all on shared graphs.
+MIX = [
+    ("cl_small", 0, "ssa", 10, 0.2, 1),
+    ("cl_small", 1, "dssa", 10, 0.2, 2),
+    ("cl_small", 0, "dssa", 1, 0.1, 3),
+    ("cl_small", 1, "ssa", 25, 0.15, 4),
+    ("nethept", 0, "ssa", 50, 0.1, 0),
+    ("nethept", 0, "dssa", 50, 0.1, 0),
+    ("nethept", 1, "dssa", 20, 0.2, 7),
+    ("nethept", 1, "ssa", 5, 0.1, 8),
+    ("rmat16", 1, "dssa", 40, 0.1, 6),
+    ("rmat16", 0, "ssa", 60, 0.2, 9),
+    ("rmat16", 0, "dssa", 3, 0.3, 10),
+]
+
+
+def _single(graphs, case):
+    name, model, algo, k, eps, key = case
+    g, dg = graphs[name]
+    return getattr(dg, algo)(model, k, eps, 1.0 / g.n, key)
+
+
+def _engine(im, ctx, graphs, cases, budget=16 << 30, max_active=64):
+    eng = im.Engine(ctx, pool_budget_bytes=budget, max_active=max_active)
+    tickets = []
+    for name, model, algo, k, eps, key in cases:
+        g, dg = graphs[name]
+        tickets.append(eng.submit(dg, model, algo, k, eps, 1.0 / g.n, key))
+    steps = 0
+    while True:
+        active, pending = eng.step()
+        steps += 1
+        if active + pending == 0:
+            break
+        assert steps < 10_000
+    res = [eng.result(t) for t in tickets]
+    eng.close()
+    return res, steps
+
+
+def test_engine_mix_matches_single(im, ctx, graphs):
+    note(f"engine mix of {len(MIX)} queries vs single-query runs")
+    res, _ = _engine(im, ctx, graphs, MIX)
+    for case, r in zip(MIX, res):
+        note(f"compare {case}")
+        _same(r, _single(graphs, case))
+
+
+def test_engine_matches_oracle(im, ctx, graphs, oracle_lib):
+    cases = [MIX[0], MIX[1], MIX[4], MIX[6]]
+    note("engine vs oracle")
+    res, _ = _engine(im, ctx, graphs, cases)
+    for (name, model, algo, k, eps, key), (seeds, st) in zip(cases, res):
+        g, _ = graphs[name]
+        w = g.w_ic if model == 0 else g.w_lt
+        og = oracle_lib.Graph(model, g.n, g.src, g.dst, w)
+        oseeds, ost = getattr(og, algo)(k, eps, 1.0 / g.n, key)
+        assert seeds.tolist() == oseeds.tolist()
+        keys = ["iterations", "n_sets", "n_verify", "cov", "cov_c", "it_sets", "it_cov", "it_cov_c"]
+        if algo == "dssa":
+            keys.append("edges")
+        for kk in keys:
+            assert st[kk] == ost[kk], (kk, st[kk], ost[kk])
+
+
+def test_alone_vs_mix_bit_identical(im, ctx, graphs):
+    probe = MIX[5]
+    note("alone vs mix")
+    alone, _ = _engine(im, ctx, graphs, [probe])
+    mixed, _ = _engine(im, ctx, graphs, MIX[::-1])
+    _same(alone[0], mixed[MIX[::-1].index(probe)])
+
+
+@pytest.mark.parametrize("budget,max_active", [(1, 64), (64 << 20, 3), (16 << 30, 1)])
+def test_admission_limits(im, ctx, graphs, budget, max_active):
+    cases = MIX[:6]
+    note(f"admission budget={budget} max_active={max_active}")
+    res, steps = _engine(im, ctx, graphs, cases, budget=budget, max_active=max_active)
+    ref, ref_steps = _engine(im, ctx, graphs, cases)
+    assert steps >= ref_steps
+    for a, b in zip(res, ref):
+        _same(a, b)
+
+
+def test_engine_errors(im, ctx, graphs):
+    g, dg = graphs["cl_small"]
+    eng = im.Engine(ctx, max_active=4)
+    note("engine argument errors")
+    with pytest.raises(im.ImError):
+        eng.submit(dg, 0, "ssa", 0, 0.1, 0.1, 0)
+    with pytest.raises(im.ImError):
+        eng.submit(dg, 0, "dssa", 5, 0.9, 0.1, 0)
+    t = eng.submit(dg, 0, "dssa", 5, 0.1, 1.0 / g.n, 0)
+    assert eng.poll(t) == 0
+    with pytest.raises(im.ImError) as e:
+        eng.result(t)
+    assert e.value.status == -6
+    eng.run()
+    assert eng.poll(t) == 1
+    seeds, st = eng.result(t)
+    assert len(set(seeds.tolist())) == 5
+    with pytest.raises(im.ImError):
+        eng.poll(t)
+    with pytest.raises(im.ImError):
+        eng.result(12345)
+    eng.close()
+
+
+def test_engine_empty_step(im, ctx):
+    eng = im.Engine(ctx)
+    note("empty engine step")
+    assert eng.step() == (0, 0)
+    eng.run()
+    eng.close()
