@@ -37,6 +37,7 @@ constexpr uint32_t kIcHbits = 11;            // log2(kIcHcap)
 constexpr uint32_t kBitmapMaxN = kIcHcap * 32;
 constexpr uint32_t kLtCap = 512;             // per-sample staging region (LT)
 constexpr int kLongWaves = 4;
+constexpr uint32_t kStageChunk = 1024;       // IC staging entries a wave reserves at once
 
 struct Counters {
     uint32_t ticket;        // next sample of the main pass
@@ -77,6 +78,7 @@ struct Params {
     uint32_t *sizes;      // per sample
     uint8_t *z;           // per sample (hits mode)
     uint32_t lt_cap;
+    uint32_t ticket_block;  // IC: consecutive samples a wave takes per ticket
 };
 
 // The work item owning global slot t.
@@ -88,6 +90,69 @@ __device__ __forceinline__ const WorkItem &item_of(const Params &p, uint32_t t) 
         else hi = mid - 1;
     }
     return p.items[lo];
+}
+
+// The work item of slot t, reusing `cur` (an index) while t stays inside it:
+// a wave's or lane's tickets increase, so the search runs once per item.
+__device__ __forceinline__ const WorkItem &item_cached(const Params &p, uint32_t t, uint32_t &cur) {
+    const WorkItem &c = p.items[cur];
+    if (t >= c.start && t - c.start < c.count) return c;
+    uint32_t lo = 0, hi = p.nitems - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (p.items[mid].start <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    cur = lo;
+    return p.items[lo];
+}
+
+// Per-item totals (node entries, edges) held in registers while a lane or
+// wave stays on one work item and added to the item's accumulator with two
+// atomics when it moves to another item or ends: one item's accumulator is
+// shared by every wave, so a per-sample atomic would serialise them.
+struct ItemAcc {
+    unsigned long long *acc = nullptr;
+    uint64_t nodes = 0, edges = 0;
+
+    __device__ __forceinline__ void flush() {
+        if (acc) {
+            if (nodes) atomicAdd(&acc[0], static_cast<unsigned long long>(nodes));
+            if (edges) atomicAdd(&acc[1], static_cast<unsigned long long>(edges));
+        }
+        nodes = edges = 0;
+    }
+    // `owner`: whether this lane issues the flush (lane 0 when the totals are
+    // wave-uniform)
+    __device__ __forceinline__ void move_to(unsigned long long *a, bool owner) {
+        if (a != acc) {
+            if (owner) flush();
+            nodes = edges = 0;
+            acc = a;
+        }
+    }
+};
+
+// End of a lane-per-sample kernel: one atomic pair per wave when every lane
+// with totals holds the same item, else one pair per lane.
+__device__ __forceinline__ void flush_lanes(ItemAcc &ia) {
+    const uint64_t has = __ballot((ia.nodes | ia.edges) != 0);
+    if (has == 0) return;
+    const uint64_t mine = reinterpret_cast<uint64_t>(ia.acc);
+    const uint64_t first = __shfl(mine, __ffsll(static_cast<unsigned long long>(has)) - 1, kWave);
+    const bool same = (ia.nodes | ia.edges) == 0 || mine == first;
+    if (__ballot(!same) == 0) {
+        const uint64_t nsum = wave_sum_u64(ia.nodes);
+        const uint64_t esum = wave_sum_u64(ia.edges);
+        if (lane_id() == 0) {
+            auto *a = reinterpret_cast<unsigned long long *>(first);
+            if (nsum) atomicAdd(&a[0], static_cast<unsigned long long>(nsum));
+            if (esum) atomicAdd(&a[1], static_cast<unsigned long long>(esum));
+        }
+        ia.nodes = ia.edges = 0;
+    } else {
+        ia.flush();
+    }
 }
 
 __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
@@ -173,13 +238,24 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
     for (uint32_t i = lane; i < kIcHcap; i += kWave) vis[i] = 0u;
     wave_sync();
     uint64_t edges_acc = 0, nodes_acc = 0;
+    ItemAcc ia;  // wave-uniform; lane 0 flushes
+    // wave-uniform: the block of samples taken per ticket, the item cache and
+    // the staging chunk carved up without further atomics
+    uint32_t t_next = 0, t_end = 0, cur = 0;
+    uint64_t chunk_pos = 0, chunk_end = 0;
 
     for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(&p.cnt->ticket, 1u);
-        t = __shfl(t, 0, kWave);
-        if (t >= p.count) break;
-        const WorkItem &it = item_of(p, t);
+        if (t_next == t_end) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&p.cnt->ticket, p.ticket_block);
+            base = __shfl(base, 0, kWave);
+            if (base >= p.count) break;
+            t_next = base;
+            t_end = min(base + p.ticket_block, p.count);
+        }
+        const uint32_t t = t_next++;
+        const WorkItem &it = item_cached(p, t, cur);
+        ia.move_to(it.acc, lane == 0);
         const Stream st(it.key);
         const uint32_t *seedbits = it.seedbits;
         const uint64_t s = it.s0 + (t - it.start);
@@ -274,35 +350,36 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                 p.defer_list[d] = t;
             }
         } else if (kMode == 1) {
-            if (lane == 0) {
-                p.z[t] = hit ? 1 : 0;
-                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
-            }
+            if (lane == 0) p.z[t] = hit ? 1 : 0;
+            ia.edges += sample_edges;
             edges_acc += sample_edges;
         } else {
-            unsigned long long base = 0;
-            if (lane == 0) {
-                atomicAdd(&it.acc[0], static_cast<unsigned long long>(tail));
-                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
-                base = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(tail));
-                if (base + tail > p.stage_cap) {
-                    atomicOr(&p.cnt->overflow, 1u);
-                    p.sizes[t] = 0;
-                    p.stage_off[t] = 0;
-                } else {
-                    p.sizes[t] = tail;
-                    p.stage_off[t] = base;
-                }
+            if (chunk_end - chunk_pos < tail) {
+                const uint64_t want = max(static_cast<uint64_t>(tail), static_cast<uint64_t>(kStageChunk));
+                unsigned long long c0 = 0;
+                if (lane == 0) c0 = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(want));
+                chunk_pos = __shfl(c0, 0, kWave);
+                chunk_end = chunk_pos + want;
             }
-            base = __shfl(base, 0, kWave);
-            if (base + tail <= p.stage_cap)
+            const uint64_t base = chunk_pos;
+            chunk_pos += tail;
+            const bool fits = base + tail <= p.stage_cap;
+            if (lane == 0) {
+                if (!fits) atomicOr(&p.cnt->overflow, 1u);
+                p.sizes[t] = fits ? tail : 0;
+                p.stage_off[t] = fits ? base : 0;
+            }
+            if (fits)
                 for (uint32_t i = lane; i < tail; i += kWave) p.stage[base + i] = queue[i];
+            ia.nodes += tail;
+            ia.edges += sample_edges;
             edges_acc += sample_edges;
             nodes_acc += tail;
         }
         vis_clear<kBitmap>(vis, queue, min(tail, kIcQcap), overflow || hit, lane);
     }
     if (lane == 0) {
+        ia.flush();
         if (edges_acc) atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(edges_acc));
         if (nodes_acc) atomicAdd(&p.cnt->total_nodes, static_cast<unsigned long long>(nodes_acc));
     }
@@ -390,7 +467,8 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
     uint64_t *table = tables + (static_cast<uint64_t>(blockIdx.x) * kWave + lane) * kLtTableSlots;
     Stream st(0);
     const uint32_t *seedbits = nullptr;
-    unsigned long long *acc = nullptr;
+    ItemAcc ia;        // per lane
+    uint32_t cur = 0;  // per-lane item cache
 
     bool active = false, finished = false;
     uint32_t t = 0, v = 0, len = 0, stamp = 0;
@@ -410,10 +488,10 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                 const uint32_t mine = base + lanes_below(mask);
                 if (mine < p.count) {
                     t = mine;
-                    const WorkItem &it = item_of(p, t);
+                    const WorkItem &it = item_cached(p, t, cur);
                     st = Stream(it.key);
                     seedbits = it.seedbits;
-                    acc = it.acc;
+                    ia.move_to(it.acc, true);
                     s = it.s0 + (t - it.start);
                     stamp = stamp_base + t;
                     v = pick_source(st, s, p.src_cum, p.n);
@@ -428,7 +506,7 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                     if (kMode == 1 && test_bit(seedbits, v)) {
                         p.z[t] = 1;
                         edges_acc += 1;
-                        atomicAdd(&acc[1], 1ull);
+                        ia.edges += 1;
                         active = false;
                     }
                 } else {
@@ -482,9 +560,9 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                 p.sizes[t] = len;
                 p.stage_off[t] = static_cast<uint64_t>(t) * p.lt_cap;
                 nodes_acc += len;
-                atomicAdd(&acc[0], static_cast<unsigned long long>(len));
+                ia.nodes += len;
             }
-            atomicAdd(&acc[1], static_cast<unsigned long long>(len));
+            ia.edges += len;
             edges_acc += len;
             active = false;
             continue;
@@ -502,10 +580,11 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
         if (kMode == 1 && test_bit(seedbits, u)) {
             p.z[t] = 1;
             edges_acc += len;
-            atomicAdd(&acc[1], static_cast<unsigned long long>(len));
+            ia.edges += len;
             active = false;
         }
     }
+    flush_lanes(ia);
     const uint64_t e_sum = wave_sum_u64(edges_acc);
     const uint64_t n_sum = wave_sum_u64(nodes_acc);
     if (lane == 0) {
@@ -905,7 +984,10 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
     // for long walks; IC bump-allocates every set.
     const double hint = size_hint > 0 ? size_hint : (model == IM_IC ? 16.0 : 64.0);
     uint64_t lt_regions = (model == IM_LT) ? count * kLtCap : 0;
-    uint64_t cap = lt_regions + static_cast<uint64_t>(std::ceil(hint * 1.5 * count)) + (1u << 20);
+    // IC waves reserve staging in chunks of kStageChunk: allow one partly
+    // used chunk per wave on top of the expected sizes
+    const uint64_t chunk_slack = (model == IM_IC) ? uint64_t(ctx->cu_count) * 8 * kIcWaves * kStageChunk : 0;
+    uint64_t cap = lt_regions + static_cast<uint64_t>(std::ceil(hint * 1.5 * count)) + (1u << 20) + chunk_slack;
     if (mode == SampleMode::Hits && model == IM_IC) cap = 0;
 
     for (int attempt = 0; attempt < 8; ++attempt) {
@@ -926,6 +1008,7 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         p.sizes = meta.sizes;
         p.z = (mode == SampleMode::Hits) ? static_cast<uint8_t *>(ctx->zflags.ptr) : meta.z;
         p.lt_cap = kLtCap;
+        p.ticket_block = 1;
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
         zero_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(dacc), 2ull * nitems);
@@ -933,6 +1016,9 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_begin, st));
         if (model == IM_IC) {
             const uint32_t grid = blocks_for(count, kIcWaves, cu * 8);
+            // several samples per ticket once there are many per wave
+            const uint64_t per_wave = count / (uint64_t(grid) * kIcWaves);
+            p.ticket_block = static_cast<uint32_t>(std::min<uint64_t>(16, std::max<uint64_t>(1, per_wave / 8)));
             const bool bitmap = g->n <= kBitmapMaxN;
             if (mode == SampleMode::Pool) {
                 if (bitmap) ic_main_kernel<0, true><<<grid, kIcWaves * kWave, 0, st>>>(p);

@@ -170,30 +170,49 @@ static int bits_for(uint64_t v) {
 }
 
 /* Keep exactly m of the len sorted unique keys: the m with the smallest
- * hash mix64(key ^ salt), preserving sorted order. */
+ * hash mix64(key ^ salt), preserving sorted order (among equal hashes, the
+ * earlier keys). The cut is found by a histogram of the hashes' top bits and
+ * a sort of the one bucket that holds it, so no copy of the keys is made. */
 static uint64_t keep_m_smallest_hash(uint64_t *keys, uint64_t len, uint64_t m, uint64_t salt) {
     if (len <= m) return len;
-    uint64_t *h = (uint64_t *)malloc(sizeof(uint64_t) * len);
-    uint64_t *t = (uint64_t *)malloc(sizeof(uint64_t) * len);
-#pragma omp parallel for schedule(static)
-    for (uint64_t i = 0; i < len; ++i) h[i] = mix64(keys[i] ^ salt);
-    memcpy(t, h, sizeof(uint64_t) * len);
-    uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * len);
-    radix_sort_u64(t, tmp, len, 64);
+    const int hb = 20;
+    const uint64_t nb = 1ull << hb;
+    const int nthr = omp_get_max_threads();
+    uint64_t *hist = (uint64_t *)calloc(nb * (size_t)(nthr + 1), sizeof(uint64_t));
+#pragma omp parallel num_threads(nthr)
+    {
+        uint64_t *h = hist + nb * (size_t)(omp_get_thread_num() + 1);
+#pragma omp for schedule(static)
+        for (uint64_t i = 0; i < len; ++i) h[mix64(keys[i] ^ salt) >> (64 - hb)]++;
+    }
+    for (int t = 1; t <= nthr; ++t)
+        for (uint64_t b = 0; b < nb; ++b) hist[b] += hist[nb * (size_t)t + b];
+    uint64_t below = 0, bucket = 0;
+    while (below + hist[bucket] < m) below += hist[bucket++];
+    const uint64_t in_bucket = hist[bucket];
+    free(hist);
+    uint64_t *hv = (uint64_t *)malloc(sizeof(uint64_t) * (in_bucket ? in_bucket : 1));
+    uint64_t c = 0;
+    for (uint64_t i = 0; i < len; ++i) {
+        const uint64_t h = mix64(keys[i] ^ salt);
+        if ((h >> (64 - hb)) == bucket) hv[c++] = h;
+    }
+    uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * (c ? c : 1));
+    radix_sort_u64(hv, tmp, c, 64);
     free(tmp);
-    uint64_t cut = t[m - 1];
-    uint64_t below_cut = 0;
-    for (uint64_t i = 0; i < m; ++i) below_cut += (t[i] < cut);
+    const uint64_t cut = hv[m - below - 1];
+    uint64_t below_cut = below;
+    for (uint64_t i = 0; i < m - below; ++i) below_cut += (hv[i] < cut);
+    free(hv);
     uint64_t need_eq = m - below_cut;
-    free(t);
     uint64_t w = 0;
     for (uint64_t i = 0; i < len; ++i) {
-        if (h[i] < cut || (h[i] == cut && need_eq > 0)) {
-            if (h[i] == cut) --need_eq;
+        const uint64_t h = mix64(keys[i] ^ salt);
+        if (h < cut || (h == cut && need_eq > 0)) {
+            if (h == cut) --need_eq;
             keys[w++] = keys[i];
         }
     }
-    free(h);
     return w;
 }
 
