@@ -14,6 +14,9 @@ Other workloads (one JSON line each, same fields):
                   SSA queries (k log-uniform in [1, 500], eps in
                   {0.05, 0.1, 0.2}, delta = 1/n, key = query index) through
                   the multi-query engine, all sampling fused per pass.
+  twitter-ic-dssa Twitter-shaped Chung-Lu graph (41.7M nodes, 1.47B edges,
+                  exponent 2.0), IC weighted cascade; each step is three D-SSA
+                  queries, k = 1, 100, 1000, eps = 0.1, delta = 1/n.
   serving         Poisson stream of queries over the resident NetHEPT-,
                   R-MAT-20- and Pokec-shaped graphs through the request loop
                   (continuous batching, admission by RR-pool bytes).
@@ -62,6 +65,24 @@ def percentile(xs, q):
     return xs[i]
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known size), or
+    None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+
+    path = ROOT / "profiles" / "traffic.json"
+    if not path.exists():
+        return None
+    rec = json.loads(path.read_text()).get(kernel)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update((ROOT / src).read_bytes())
+    return rec["hbm_bytes_per_dispatch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def roofline(kt: dict, model: int) -> dict:
     """Roofline of the main sampler kernel from its event timing: algorithmic
     bytes per launch over the mean launch duration, against HBM peak."""
@@ -76,8 +97,9 @@ def roofline(kt: dict, model: int) -> dict:
     ms_per_launch = kt["sample_ms"] / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
     sec = kt["sample_ms"] * 1e-3
+    traffic = measured_traffic("lt_main_kernel" if model == 1 else "ic_main_kernel")
     return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "launches": kt["sample_launches"],
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "launches": kt["sample_launches"],
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
             "sampler_sets_per_s": round(kt["sample_sets"] / sec) if sec else None,
             "sampler_steps_per_s": round(kt["sample_steps"] / sec) if sec else None}
@@ -103,6 +125,24 @@ def pokec_queries(n: int, count: int = 64, seed: int = 64):
 
 # ----------------------------------------------------------- workloads ----
 
+def run_engine_batch(im, ctx, dg, model, algo, queries, budget, max_active):
+    """Run `queries` [(k, eps, delta, key)] concurrently through one engine;
+    returns per-query (seeds, stats) and latency from submission in ms."""
+    eng = im.Engine(ctx, pool_budget_bytes=budget, max_active=max_active)
+    t_sub = time.perf_counter()
+    tickets = [eng.submit(dg, model, algo, k, eps, delta, key) for k, eps, delta, key in queries]
+    done = {}
+    while len(done) < len(tickets):
+        eng.step()
+        now = time.perf_counter()
+        for t in tickets:
+            if t not in done and eng.poll(t) != 0:
+                done[t] = (now - t_sub) * 1e3
+    res = [eng.result(t) for t in tickets]
+    eng.close()
+    return res, [done[t] for t in tickets]
+
+
 def run_rmat20(args, im, ctx, sync):
     import synth
 
@@ -110,8 +150,20 @@ def run_rmat20(args, im, ctx, sync):
     n, k, eps = g.n, args.k, args.eps
     delta = 1.0 / n
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_lt=g.w_lt)
+    B = args.queries_per_step
+    budget = int(args.pool_budget_gb * (1 << 30))
+
+    def step(i):
+        if B == 1:
+            q0 = time.perf_counter()
+            _, st = dg.dssa(im.IM_LT, k, eps, delta, i)
+            return [st], [(time.perf_counter() - q0) * 1e3]
+        res, lat_ = run_engine_batch(im, ctx, dg, im.IM_LT, "dssa", [(k, eps, delta, i * B + j) for j in range(B)],
+                                     budget, B)
+        return [st for _, st in res], lat_
+
     for i in range(args.warmup):
-        dg.dssa(im.IM_LT, k, eps, delta, 1_000_000 + i)
+        step(1_000_000 + i)
     ctx.set_timing(True)
     ctx.read_timing(reset=True)
     sync()
@@ -119,14 +171,14 @@ def run_rmat20(args, im, ctx, sync):
     stage = {"ms_sample": 0.0, "ms_cover": 0.0, "ms_verify": 0.0}
     t0 = time.perf_counter()
     for i in range(args.steps):
-        q0 = time.perf_counter()
-        _, st = dg.dssa(im.IM_LT, k, eps, delta, i)
-        lat.append((time.perf_counter() - q0) * 1e3)
-        sets += st["n_sets"]
-        edges += st["edges"]
-        iters.append(st["iterations"])
-        for key in stage:
-            stage[key] += st[key]
+        sts, l_ = step(i)
+        lat += l_
+        for st in sts:
+            sets += st["n_sets"]
+            edges += st["edges"]
+            iters.append(st["iterations"])
+            for key in stage:
+                stage[key] += st[key] / B
     sync()
     dt = time.perf_counter() - t0
     kt = ctx.read_timing(reset=True)
@@ -134,9 +186,9 @@ def run_rmat20(args, im, ctx, sync):
     dg.close()
     out = {"value": round(sets / dt, 1), "ms_per_step": round(dt * 1e3 / args.steps, 4),
            "config": {"workload": "R-MAT-20 LT D-SSA", "n": n, "m": g.m, "k": k, "eps": eps, "delta": "1/n",
-                      "queries_per_step": 1},
+                      "queries_per_step": B},
            "edges_per_s": round(edges / dt, 1), "p50_ms": round(percentile(lat, 50), 3),
-           "p99_ms": round(percentile(lat, 99), 3), "rr_sets_per_query": sets // max(args.steps, 1),
+           "p99_ms": round(percentile(lat, 99), 3), "rr_sets_per_query": sets // max(args.steps * B, 1),
            "iterations_per_query": sorted(set(iters)),
            "stage_ms_per_query": {k_: round(v_ / args.steps, 3) for k_, v_ in stage.items()},
            "roofline": roofline(kt, 1)}
@@ -173,19 +225,8 @@ def run_pokec64(args, im, ctx, sync):
     budget = int(args.pool_budget_gb * (1 << 30))
 
     def one_batch(key_base):
-        eng = im.Engine(ctx, pool_budget_bytes=budget, max_active=64)
-        t_sub = time.perf_counter()
-        tickets = [eng.submit(dg, im.IM_IC, "ssa", k, eps, delta, key_base + key) for k, eps, key in qs]
-        done = {}
-        while len(done) < len(tickets):
-            eng.step()
-            now = time.perf_counter()
-            for t in tickets:
-                if t not in done and eng.poll(t) != 0:
-                    done[t] = (now - t_sub) * 1e3
-        res = [eng.result(t) for t in tickets]
-        eng.close()
-        return res, [done[t] for t in tickets]
+        return run_engine_batch(im, ctx, dg, im.IM_IC, "ssa", [(k, eps, delta, key_base + key) for k, eps, key in qs],
+                                budget, 64)
 
     for i in range(args.warmup):
         one_batch(1_000_000 * (i + 1))
@@ -282,7 +323,71 @@ def run_serving(args, im, ctx, sync):
     return out, None
 
 
-WORKLOADS = {"rmat20-lt-dssa": run_rmat20, "pokec-ic-ssa64": run_pokec64, "serving": run_serving}
+def run_twitter(args, im, ctx, sync):
+    import synth
+
+    t_gen = time.perf_counter()
+    g = synth.make("twitter", cache=os.environ.get("IM_CACHE_BIG", "") == "1")
+    t_gen = time.perf_counter() - t_gen
+    n = g.n
+    delta = 1.0 / n
+    t_load = time.perf_counter()
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    sync()
+    t_load = time.perf_counter() - t_load
+    ks = [1, 100, 1000]
+    for i in range(args.warmup):
+        dg.dssa(im.IM_IC, 100, 0.1, delta, 1_000_000 + i)
+    ctx.set_timing(True)
+    ctx.read_timing(reset=True)
+    sync()
+    lat, sets, edges, per_k = [], 0, 0, {}
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        for k in ks:
+            q0 = time.perf_counter()
+            _, st = dg.dssa(im.IM_IC, k, 0.1, delta, step)
+            ms = (time.perf_counter() - q0) * 1e3
+            lat.append(ms)
+            sets += st["n_sets"]
+            edges += st["edges"]
+            per_k.setdefault(k, []).append({"ms": round(ms, 3), "n_sets": st["n_sets"], "edges": st["edges"],
+                                            "iterations": st["iterations"],
+                                            "ms_sample": round(st["ms_sample"], 3),
+                                            "ms_cover": round(st["ms_cover"], 3)})
+    sync()
+    dt = time.perf_counter() - t0
+    kt = ctx.read_timing(reset=True)
+    ctx.set_timing(False)
+    dg.close()
+    out = {"value": round(sets / dt, 1), "ms_per_step": round(dt * 1e3 / args.steps, 4),
+           "config": {"workload": "Twitter-shaped IC weighted cascade D-SSA, k in {1, 100, 1000}", "n": n,
+                      "m": g.m, "k": ks, "eps": 0.1, "delta": "1/n", "queries_per_step": len(ks)},
+           "edges_per_s": round(edges / dt, 1), "p50_ms": round(percentile(lat, 50), 3),
+           "p99_ms": round(percentile(lat, 99), 3), "per_k": per_k,
+           "graph_generate_s": round(t_gen, 1), "graph_load_s": round(t_load, 2),
+           "roofline": roofline(kt, 0)}
+
+    def cpu(budget_s):
+        import oracle
+
+        og = oracle.Graph(oracle.IC, g.n, g.src, g.dst, g.w_ic)
+        pool = oracle.Pool(og, 0)
+        c = 0
+        t = time.perf_counter()
+        while time.perf_counter() - t < budget_s and c < (1 << 16):
+            c += 4096
+            pool.extend(c)
+        d = time.perf_counter() - t
+        return {"value": c / d, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
+                "sample": f"oracle RR-set sampling of samples 0..{c - 1} of key 0 on the same graph "
+                          f"({d:.1f} s, one host core); sampling only"}
+
+    return out, cpu
+
+
+WORKLOADS = {"rmat20-lt-dssa": run_rmat20, "pokec-ic-ssa64": run_pokec64, "serving": run_serving,
+             "twitter-ic-dssa": run_twitter}
 
 
 def main() -> int:
@@ -299,6 +404,10 @@ def main() -> int:
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--compare-plain", action="store_true", help="also time the queries one at a time")
+    ap.add_argument("--queries-per-step", type=int, default=1,
+                    help="R-MAT-20: concurrent D-SSA queries per step through the multi-query engine")
+    ap.add_argument("--greedy-wg-max-entries", type=int, default=None,
+                    help="launch parameter: largest Max-Coverage range run in one workgroup")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -318,6 +427,8 @@ def main() -> int:
             torch.cuda.synchronize()
 
     ctx = im.Context(0)
+    if args.greedy_wg_max_entries is not None:
+        ctx.set_param("greedy_wg_max_entries", args.greedy_wg_max_entries)
     body, cpu = WORKLOADS[args.workload](args, im, ctx, sync)
     steps = args.steps if args.workload != "serving" else 1
     out = {"metric": METRIC, "value": body.pop("value"), "unit": "RR sets/s", "n_gpus": 1, "steps": steps,

@@ -30,7 +30,10 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_pool_device", "im_max_coverage", "im_max_coverage_range", "im_coverage_range", "im_estimate_inf",
            "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing",
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
-           "im_engine_poll", "im_engine_result"]
+           "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param"]
+
+IM_PARAM_GREEDY_WG_MAX_ENTRIES, IM_PARAM_IC_TICKET_BLOCK = 0, 1
+PARAMS = {"greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK}
 
 IM_ALGO_SSA, IM_ALGO_DSSA = 0, 1
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}
@@ -139,6 +142,8 @@ def load_library(path: Path | str | None = None):
         "im_last_error": (ctypes.c_char_p, []),
         "im_ctx_set_timing": (st, [vp, ctypes.c_int]),
         "im_ctx_read_timing": (st, [vp, ctypes.POINTER(KernelTimes), ctypes.c_int]),
+        "im_ctx_set_param": (st, [vp, ctypes.c_int, ctypes.c_uint64]),
+        "im_ctx_get_param": (st, [vp, ctypes.c_int, u64p]),
         "im_engine_create": (st, [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(vp)]),
         "im_engine_free": (None, [vp]),
         "im_engine_submit": (st, [vp, ctypes.POINTER(Query), u64p]),
@@ -227,6 +232,14 @@ class Context:
 
     def set_timing(self, enable: bool = True):
         _check(load_library().im_ctx_set_timing(self.h, 1 if enable else 0))
+
+    def set_param(self, name: str, value: int):
+        _check(load_library().im_ctx_set_param(self.h, PARAMS[name], int(value)))
+
+    def get_param(self, name: str) -> int:
+        v = ctypes.c_uint64()
+        _check(load_library().im_ctx_get_param(self.h, PARAMS[name], ctypes.byref(v)))
+        return int(v.value)
 
     def read_timing(self, reset: bool = False) -> dict:
         t = KernelTimes()

@@ -262,6 +262,37 @@ extern "C" im_status im_ctx_set_timing(im_ctx *c, int enable) {
     return IM_OK;
 }
 
+extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value) {
+    clear_error();
+    if (!c) return IM_E_ARG;
+    switch (param) {
+    case IM_PARAM_GREEDY_WG_MAX_ENTRIES:
+        c->greedy_wg_max_entries = value;
+        return IM_OK;
+    case IM_PARAM_IC_TICKET_BLOCK:
+        if (value > 64) break;
+        c->ic_ticket_block = static_cast<uint32_t>(value);
+        return IM_OK;
+    }
+    set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
+    return IM_E_ARG;
+}
+
+extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t *value) {
+    clear_error();
+    if (!c || !value) return IM_E_ARG;
+    switch (param) {
+    case IM_PARAM_GREEDY_WG_MAX_ENTRIES:
+        *value = c->greedy_wg_max_entries;
+        return IM_OK;
+    case IM_PARAM_IC_TICKET_BLOCK:
+        *value = c->ic_ticket_block;
+        return IM_OK;
+    }
+    set_error("im_ctx_get_param: bad parameter %d", int(param));
+    return IM_E_ARG;
+}
+
 extern "C" im_status im_ctx_read_timing(im_ctx *c, im_kernel_times *out, int reset) {
     clear_error();
     if (!c || !out) return IM_E_ARG;

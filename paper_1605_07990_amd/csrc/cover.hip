@@ -151,7 +151,9 @@ constexpr uint32_t kChosen = 0x80000000u;
 constexpr uint32_t kL1Shift = 6;  // 64 nodes per m1 entry (one 256-byte line of gains)
 constexpr uint32_t kL2Shift = 6;  // 64 m1 entries per m2 entry
 constexpr int kPersistThreads = 1024;
-constexpr uint64_t kPersistEntries = 1u << 16;  // ranges this small run all rounds in one workgroup
+constexpr uint32_t kPersistDirtyCap = 2048;     // chunks listed per round before a full refresh
+constexpr uint32_t kPersistCovWords = 8192;     // covered-set bits kept in LDS (262,144 sets)
+constexpr uint32_t kPersistGroupWords = 512;    // m2 entries tracked per round (n up to 2^26)
 
 struct GreedyState {
     uint32_t *gain;
@@ -168,6 +170,8 @@ struct GreedyState {
     uint32_t *pick;  // the current round's seed
     uint32_t *done;  // blocks of the current refresh that finished
     unsigned long long *cov;
+    uint32_t *dirty;  // one-workgroup rounds: chunk bitmap (n1 bits), zeroed
+    uint64_t nsets;   // sets in the range
 };
 
 // Load flavours. State written by earlier kernels is read with plain loads.
@@ -363,67 +367,187 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g) {
     if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
 }
 
-// Rounds [r0, k) of job blockIdx.x in one workgroup. The cover step is
-// flattened: first the
-// winner's incidence entries (1024 at a time) yield the newly covered sets,
-// then their members are decremented 1024 at a time.
-__global__ __launch_bounds__(kPersistThreads) void persist_kernel(const GreedyState *jobs, uint32_t r0) {
-    const GreedyState g = jobs[blockIdx.x];
-    __shared__ unsigned long long smem[kPersistThreads / kWave];
+// Batched rounds: blockIdx.y is the job; jobs whose k is reached idle.
+__global__ __launch_bounds__(kThreads) void batch_refresh_choose_kernel(const GreedyState *jobs, uint32_t r) {
+    __shared__ unsigned long long smem[kThreads / kWave];
     __shared__ uint32_t s_pick;
-    __shared__ uint32_t s_nfresh;
-    __shared__ uint64_t s_start[kPersistThreads];
-    __shared__ uint32_t s_pre[kPersistThreads + 1];
+    __shared__ bool s_last;
+    const GreedyState &g = jobs[blockIdx.y];
+    if (r >= g.k) return;
+    if (r > 0) {
+        for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n1; c += gridDim.x * blockDim.x)
+            refresh_m1_one<false>(g, c);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(g.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (r > 0) {
+        for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) refresh_m2_one<false>(g, d);
+        __syncthreads();
+    }
+    const uint32_t v = choose<true>(g, r, smem, &s_pick);
+    if (threadIdx.x == 0) {
+        *g.pick = v;
+        *g.done = 0u;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void batch_cover_kernel(const GreedyState *jobs, uint32_t r) {
+    const GreedyState &g = jobs[blockIdx.y];
+    if (r >= g.k) return;
+    const uint32_t v = *g.pick;
+    const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+    const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    unsigned long long newly = 0;
+    for (uint64_t i = a + grp; i < b; i += ngrp) {
+        const uint32_t j = g.isets[i];
+        uint32_t fresh = 0;
+        if (sub == 0) {
+            const uint32_t bit = 1u << (j & 31u);
+            fresh = (atomicOr(&g.covbits[j >> 5], bit) & bit) ? 0u : 1u;
+        }
+        fresh = __shfl(fresh, static_cast<int>(lane_id() & ~15u), kWave);
+        if (fresh) {
+            if (sub == 0) ++newly;
+            const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
+            for (uint64_t q = sa + sub; q < sb; q += 16) atomicSub(&g.gain[g.pnodes[q]], 1u);
+        }
+    }
+    newly = wave_sum_u64(newly);
+    if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+}
+
+// LDS of the one-workgroup rounds.
+struct PersistLds {
+    unsigned long long smem[kPersistThreads / kWave];
+    uint64_t scan[kPersistThreads / kWave];
+    uint64_t start[kPersistThreads];
+    uint64_t pre[kPersistThreads];
+    uint32_t dlist[kPersistDirtyCap];
+    uint32_t groups[kPersistGroupWords];
+    uint32_t cov[kPersistCovWords];
+    uint32_t pick, dcount, dall;
+};
+
+// Rounds [r0, k) of one job in one workgroup. Each round chooses from m2,
+// covers the winner's sets (the newly covered sets' members are decremented
+// 1024 at a time, located through a block scan of the set sizes) and notes
+// the chunks whose maximum holder lost gain; only those m1 entries, and the
+// m2 entries above them, are re-derived before the next choice (all of them
+// when more than kPersistDirtyCap chunks were hit). Covered-set bits live in
+// LDS when the range is small enough.
+template <bool kLdsCov>
+__device__ void persist_rounds(const GreedyState &g, uint32_t r0, PersistLds &L) {
     const uint32_t tid = threadIdx.x;
+    uint32_t *covbits = kLdsCov ? L.cov : g.covbits;
+    const bool track = g.n2 <= kPersistGroupWords * 32;
+    for (uint32_t w = tid; w < kPersistGroupWords; w += blockDim.x) L.groups[w] = 0u;
+    if (tid == 0) {
+        L.dcount = 0;
+        L.dall = 0;
+    }
+    __syncthreads();
+    // chunk c must be re-derived before the next choice
+    auto mark = [&](uint32_t c) {
+        const uint32_t bit = 1u << (c & 31u);
+        if (!(atomicOr(&g.dirty[c >> 5], bit) & bit)) {
+            const uint32_t slot = atomicAdd(&L.dcount, 1u);
+            if (slot < kPersistDirtyCap) L.dlist[slot] = c;
+            else L.dall = 1u;
+        }
+    };
     unsigned long long newly = 0;
     for (uint32_t r = r0; r < g.k; ++r) {
         if (r > r0) {
-            for (uint32_t c = tid; c < g.n1; c += blockDim.x) refresh_m1_one<true>(g, c);
             __syncthreads();
-            for (uint32_t d = tid; d < g.n2; d += blockDim.x) refresh_m2_one<true>(g, d);
+            const uint32_t nd = L.dcount;
+            const bool all = L.dall != 0;
+            if (all) {
+                for (uint32_t c = tid; c < g.n1; c += blockDim.x) {
+                    g.m1[c] = m1_lane<true>(g, c);
+                    if ((c & 31u) == 0) atomicAnd(&g.dirty[c >> 5], 0u);
+                }
+            } else {
+                for (uint32_t i = tid; i < nd; i += blockDim.x) {
+                    const uint32_t c = L.dlist[i];
+                    g.m1[c] = m1_lane<true>(g, c);
+                    atomicAnd(&g.dirty[c >> 5], ~(1u << (c & 31u)));
+                    const uint32_t d = c >> kL2Shift;
+                    if (track) atomicOr(&L.groups[d >> 5], 1u << (d & 31u));
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+            const bool every = all || !track;
+            for (uint32_t d = tid; d < g.n2; d += blockDim.x)
+                if (every || ((L.groups[d >> 5] >> (d & 31u)) & 1u)) g.m2[d] = m2_lane<true>(g, d);
+            __threadfence_block();
+            __syncthreads();
+            for (uint32_t w = tid; w < kPersistGroupWords; w += blockDim.x) L.groups[w] = 0u;
+            if (tid == 0) {
+                L.dcount = 0;
+                L.dall = 0;
+            }
             __syncthreads();
         }
-        const uint32_t v = choose<true>(g, r, smem, &s_pick);
+        const uint32_t v = choose<true>(g, r, L.smem, &L.pick);
+        if (tid == 0) mark(v >> kL1Shift);
         const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
         for (uint64_t base = a; base < b; base += blockDim.x) {
-            if (tid == 0) s_nfresh = 0;
-            __syncthreads();
             const uint64_t i = base + tid;
+            uint64_t size = 0, start = 0;
             if (i < b) {
                 const uint32_t j = g.isets[i];
                 const uint32_t bit = 1u << (j & 31u);
-                if (!(atomicOr(&g.covbits[j >> 5], bit) & bit)) {
-                    const uint32_t slot = atomicAdd(&s_nfresh, 1u);
-                    const uint64_t sa = g.poff[g.begin + j];
-                    s_start[slot] = sa;
-                    s_pre[slot + 1] = static_cast<uint32_t>(g.poff[g.begin + j + 1] - sa);
+                if (!(atomicOr(&covbits[j >> 5], bit) & bit)) {
+                    start = g.poff[g.begin + j];
+                    size = g.poff[g.begin + j + 1] - start;
+                    ++newly;
                 }
             }
+            uint64_t members = 0;
+            const uint64_t pre = block_scan_excl(size, L.scan, members);
+            L.start[tid] = start;
+            L.pre[tid] = pre;
             __syncthreads();
-            const uint32_t nf = s_nfresh;
-            newly += (tid == 0) ? nf : 0;
-            if (tid == 0) {  // prefix sums of the fresh sets' sizes
-                s_pre[0] = 0;
-                for (uint32_t q = 0; q < nf; ++q) s_pre[q + 1] += s_pre[q];
-            }
-            __syncthreads();
-            const uint32_t members = s_pre[nf];
-            for (uint32_t mb = 0; mb < members; mb += blockDim.x) {
-                const uint32_t idx = mb + tid;
-                if (idx < members) {
-                    uint32_t lo = 0, hi = nf - 1;  // last set whose prefix <= idx
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi + 1) >> 1;
-                        if (s_pre[mid] <= idx) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    atomicSub(&g.gain[g.pnodes[s_start[lo] + (idx - s_pre[lo])]], 1u);
+            for (uint64_t idx = tid; idx < members; idx += blockDim.x) {
+                // the last slot whose prefix is <= idx owns member idx
+                uint32_t lo = 0, hi = kPersistThreads - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (L.pre[mid] <= idx) lo = mid;
+                    else hi = mid - 1;
                 }
+                const uint32_t u = g.pnodes[L.start[lo] + (idx - L.pre[lo])];
+                const uint32_t c = u >> kL1Shift;
+                const unsigned long long m = ld<true>(g.m1 + c);
+                atomicSub(&g.gain[u], 1u);
+                if (static_cast<uint32_t>(~m) == u) mark(c);
             }
             __syncthreads();
         }
     }
-    if (tid == 0 && newly) atomicAdd(g.cov, newly);
+    newly = wave_sum_u64(newly);
+    if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+}
+
+// Job blockIdx.x, rounds [r0, k).
+__global__ __launch_bounds__(kPersistThreads) void persist_kernel(const GreedyState *jobs, uint32_t r0) {
+    __shared__ PersistLds L;
+    const GreedyState g = jobs[blockIdx.x];
+    const uint64_t words = (g.nsets + 31) / 32;
+    if (r0 == 0 && words <= kPersistCovWords) {
+        for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) L.cov[w] = 0u;
+        __syncthreads();
+        persist_rounds<true>(g, r0, L);
+    } else {
+        persist_rounds<false>(g, r0, L);
+    }
 }
 
 // Sets in [begin, end) that contain a node of the seed bitmap.
@@ -742,7 +866,8 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const size_t o_gain = take(4ull * n), o_fill = take(4ull * n), o_ioff = take(8ull * (n + 1)),
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
                  o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
-                 o_m2 = take(8ull * n2), o_cnt = take(16), o_job = take(sizeof(GreedyState));
+                 o_m2 = take(8ull * n2), o_cnt = take(16), o_job = take(sizeof(GreedyState)),
+                 o_dirty = take(4ull * ((n1 + 31) / 32));
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
@@ -772,6 +897,8 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     g.k = k;
     g.seeds = at32(o_seeds);
     g.cov = dcov;
+    g.dirty = at32(o_dirty);
+    g.nsets = nsets;
 
     hipStream_t st = ctx->stream;
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
@@ -793,7 +920,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     init_m2_kernel<<<grid_of(n2, kThreads, cu * 8), kThreads, 0, st>>>(g);
     // per-round launches pay for themselves once the cover work per round is
     // large; tiny problems keep every round in one workgroup
-    const bool small = entries <= kPersistEntries;
+    const bool small = entries <= ctx->greedy_wg_max_entries;
     const uint32_t big = small ? 0u : k;
     const uint32_t cgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
     const uint32_t rgrid = grid_of(uint64_t(n1), kThreads, cu * 4);
@@ -803,6 +930,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         cover_kernel<<<cgrid, kThreads, 0, st>>>(g);
     }
     if (big < k) {
+        fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
         auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
         IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
         persist_kernel<<<1, kPersistThreads, 0, st>>>(dg, big);
@@ -891,7 +1019,8 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
                  o_tsum = take(8 * (tiles + 1)), o_isets = take(4 * (tot_entries + 1)), o_covbits = take(4 * tot_cov),
                  o_m1 = take(8ull * nj * n1), o_m2 = take(8ull * nj * n2), o_seeds = take(4 * (tot_seeds + 1)),
                  o_cov = take(8ull * nj), o_covc = take(8ull * nj), o_bits = take(4 * words * nj),
-                 o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj);
+                 o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj),
+                 o_dirty = take(4ull * nj * ((n1 + 31) / 32)), o_pd = take(8ull * nj);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto *gains = reinterpret_cast<uint32_t *>(base + o_gain);
@@ -930,9 +1059,11 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.n2 = n2;
         g.k = cj.k;
         g.seeds = seeds + jt[j].seed_start;
-        g.pick = nullptr;
-        g.done = nullptr;
+        g.pick = reinterpret_cast<uint32_t *>(base + o_pd) + 2ull * j;
+        g.done = g.pick + 1;
         g.cov = covs + j;
+        g.dirty = reinterpret_cast<uint32_t *>(base + o_dirty) + uint64_t(j) * ((n1 + 31) / 32);
+        g.nsets = cj.end - cj.begin;
     }
     IM_HIP(hipMemcpyAsync(djt, jt.data(), sizeof(JobTable) * nj, hipMemcpyHostToDevice, st));
     IM_HIP(hipMemcpyAsync(dgs, gs.data(), sizeof(GreedyState) * nj, hipMemcpyHostToDevice, st));
@@ -940,6 +1071,8 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
     fill_u32_kernel<<<grid_of(cells, kThreads, cu * 8), kThreads, 0, st>>>(fills, cells, 0u);
     fill_u32_kernel<<<grid_of(tot_cov, kThreads, cu * 8), kThreads, 0, st>>>(covbits, tot_cov, 0u);
     fill_u32_kernel<<<grid_of(words * nj, kThreads, cu * 8), kThreads, 0, st>>>(bits, words * nj, 0u);
+    fill_u32_kernel<<<grid_of(uint64_t(nj) * ((n1 + 31) / 32), kThreads, cu * 8), kThreads, 0, st>>>(
+        reinterpret_cast<uint32_t *>(base + o_dirty), uint64_t(nj) * ((n1 + 31) / 32), 0u);
     fill_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(covs), nj, 0);
     fill_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(covcs), nj, 0);
     if (tot_entries)
@@ -952,7 +1085,27 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
                                                                                              isets);
     batch_init_m1_kernel<<<grid_of(uint64_t(nj) * n1, kThreads, cu * 8), kThreads, 0, st>>>(dgs, nj, n1);
     batch_init_m2_kernel<<<grid_of(uint64_t(nj) * n2, kThreads, cu * 8), kThreads, 0, st>>>(dgs, nj, n2);
-    persist_kernel<<<nj, kPersistThreads, 0, st>>>(dgs, 0);
+    // ranges up to the one-workgroup limit all run their rounds in one
+    // launch; beyond it every round is two grid launches shared by all jobs
+    uint64_t max_entries = 0;
+    uint32_t max_k = 0;
+    for (uint32_t j = 0; j < nj; ++j) {
+        max_entries = std::max<uint64_t>(max_entries, he[4 * j + 1] - he[4 * j]);
+        max_k = std::max(max_k, jobs[j].k);
+    }
+    if (max_entries <= ctx->greedy_wg_max_entries) {
+        persist_kernel<<<nj, kPersistThreads, 0, st>>>(dgs, 0);
+    } else {
+        fill_u32_kernel<<<grid_of(2ull * nj, kThreads, cu), kThreads, 0, st>>>(
+            reinterpret_cast<uint32_t *>(base + o_pd), 2ull * nj, 0u);
+        const uint32_t per = std::max<uint32_t>(1, (cu * 4 + nj - 1) / nj);
+        const uint32_t rx = std::min<uint32_t>(per, grid_of(uint64_t(n1), kThreads, cu * 4));
+        const uint32_t cx = std::min<uint32_t>(per, std::max<uint32_t>(1, grid_of(max_entries * 16, kThreads, cu * 4)));
+        for (uint32_t r = 0; r < max_k; ++r) {
+            batch_refresh_choose_kernel<<<dim3(rx, nj), kThreads, 0, st>>>(dgs, r);
+            batch_cover_kernel<<<dim3(cx, nj), kThreads, 0, st>>>(dgs, r);
+        }
+    }
     if (tot_stare) {
         batch_seed_bits_kernel<<<grid_of(tot_seeds, kThreads, cu * 4), kThreads, 0, st>>>(djt, nj, seeds, tot_seeds);
         batch_coverage_kernel<<<grid_of(tot_stare * 16, kThreads, cu * 16), kThreads, 0, st>>>(djt, nj, tot_stare);

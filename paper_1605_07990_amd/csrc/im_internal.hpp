@@ -68,6 +68,10 @@ struct im_ctx {
     DevBuf append_dst;   // per-item pool destinations of a fused append
     void *host_pinned = nullptr;  // small pinned staging for read-backs
 
+    // launch parameters (im_param)
+    uint64_t greedy_wg_max_entries = 1u << 16;
+    uint32_t ic_ticket_block = 0;  // 0: automatic
+
     // optional event timing of the main sampler launches
     bool timing = false;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;

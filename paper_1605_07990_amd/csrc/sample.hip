@@ -1018,7 +1018,9 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
             const uint32_t grid = blocks_for(count, kIcWaves, cu * 8);
             // several samples per ticket once there are many per wave
             const uint64_t per_wave = count / (uint64_t(grid) * kIcWaves);
-            p.ticket_block = static_cast<uint32_t>(std::min<uint64_t>(16, std::max<uint64_t>(1, per_wave / 8)));
+            p.ticket_block = ctx->ic_ticket_block
+                                 ? ctx->ic_ticket_block
+                                 : static_cast<uint32_t>(std::min<uint64_t>(16, std::max<uint64_t>(1, per_wave / 8)));
             const bool bitmap = g->n <= kBitmapMaxN;
             if (mode == SampleMode::Pool) {
                 if (bitmap) ic_main_kernel<0, true><<<grid, kIcWaves * kWave, 0, st>>>(p);

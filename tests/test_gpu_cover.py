@@ -40,7 +40,7 @@ def pools(im, ctx, oracle_lib):
 
 
 @pytest.mark.parametrize("name", ["nethept", "rmat16", "cl_small"])
-@pytest.mark.parametrize("k", [1, 7, 50, 200])
+@pytest.mark.parametrize("k", [1, 7, 50, 200, 2000])
 def test_max_coverage_matches_oracle(pools, name, k):
     g, dg, og, p, op = pools[name]
     note(f"max coverage {name} k={k}")
@@ -108,3 +108,43 @@ def test_estimate_inf_matches_oracle(im, ctx, oracle_lib, name, model):
     ic, T = dg.estimate_inf(model, np.arange(g.n), 0.2, 0.01, 1e9, 40)
     lam2 = 1 + 1.2 * oracle_lib.upsilon(0.2, 0.01)
     assert T == math.ceil(lam2)
+
+
+@pytest.mark.parametrize("limit", [0, 1 << 62])
+@pytest.mark.parametrize("name", ["nethept", "rmat16", "cl_small"])
+def test_greedy_paths_agree(im, ctx, pools, name, limit):
+    """Both greedy schedules (per-round grid launches, all rounds in one
+    workgroup) give the oracle's seeds, whatever the size threshold."""
+    g, dg, og, p, op = pools[name]
+    note(f"greedy path limit={limit} {name}")
+    old = ctx.get_param("greedy_wg_max_entries")
+    ctx.set_param("greedy_wg_max_entries", limit)
+    try:
+        for k in (1, 50, 300):
+            seeds, cov = p.max_coverage(k)
+            oseeds, ocov = op.max_coverage(k)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
+    finally:
+        ctx.set_param("greedy_wg_max_entries", old)
+
+
+def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):
+    """More sets than the LDS covered-set bitmap holds and more dirty chunks
+    per round than the list holds, in one workgroup."""
+    g = synth.make("cl_20k")
+    note("one-workgroup greedy on 400k sets")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+    p = im.Pool(dg, 0, 9)
+    p.sample(400_000)
+    op = oracle_lib.Pool(og, 9)
+    op.extend(400_000)
+    old = ctx.get_param("greedy_wg_max_entries")
+    ctx.set_param("greedy_wg_max_entries", 1 << 62)
+    try:
+        for k in (5, 120):
+            seeds, cov = p.max_coverage(k)
+            oseeds, ocov = op.max_coverage(k)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
+    finally:
+        ctx.set_param("greedy_wg_max_entries", old)

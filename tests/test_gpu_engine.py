@@ -90,9 +90,18 @@ def _engine(im, ctx, graphs, cases, budget=16 << 30, max_active=64):
     return res, steps
 
 
-def test_engine_mix_matches_single(im, ctx, graphs):
-    note(f"engine mix of {len(MIX)} queries vs single-query runs")
-    res, _ = _engine(im, ctx, graphs, MIX)
+@pytest.mark.parametrize("limit", [None, 0, 1 << 62])
+def test_engine_mix_matches_single(im, ctx, graphs, limit):
+    """limit: the one-workgroup greedy threshold (None = default; 0 forces
+    the batched per-round launches, 2^62 one workgroup per job)."""
+    note(f"engine mix of {len(MIX)} queries vs single-query runs, greedy limit {limit}")
+    old = ctx.get_param("greedy_wg_max_entries")
+    if limit is not None:
+        ctx.set_param("greedy_wg_max_entries", limit)
+    try:
+        res, _ = _engine(im, ctx, graphs, MIX)
+    finally:
+        ctx.set_param("greedy_wg_max_entries", old)
     for case, r in zip(MIX, res):
         note(f"compare {case}")
         _same(r, _single(graphs, case))
