@@ -83,6 +83,25 @@ def measured_traffic(kernel: str):
     return rec["hbm_bytes_per_dispatch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_gib: int = 16, trials: int = 3) -> dict:
+    """Measured random-gather bandwidth (GB/s of segment bytes) per segment
+    size, from the probe library: hashed random segment-aligned reads of a
+    buffer far larger than the last-level cache."""
+    import ctypes
+
+    lib = ctypes.CDLL(str(ROOT / "paper_1605_07990_amd" / "libimprobe.so"))
+    lib.im_probe_gather.restype = ctypes.c_int
+    lib.im_probe_gather.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for seg in segs:
+        g = ctypes.c_double(0.0)
+        if lib.im_probe_gather(0, buffer_gib << 30, seg, trials, ctypes.byref(g)) != 0:
+            raise RuntimeError(f"gather probe failed for {seg}-byte segments")
+        out[seg] = round(g.value, 1)
+    return out
+
+
 def roofline(kt: dict, model: int) -> dict:
     """Roofline of the main sampler kernel from its event timing: algorithmic
     bytes per launch over the mean launch duration, against HBM peak."""
@@ -98,11 +117,26 @@ def roofline(kt: dict, model: int) -> dict:
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
     sec = kt["sample_ms"] * 1e-3
     traffic = measured_traffic("lt_main_kernel" if model == 1 else "ic_main_kernel")
-    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "launches": kt["sample_launches"],
+    out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "launches": kt["sample_launches"],
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
-            "sampler_sets_per_s": round(kt["sample_sets"] / sec) if sec else None,
-            "sampler_steps_per_s": round(kt["sample_steps"] / sec) if sec else None}
+           "sampler_sets_per_s": round(kt["sample_sets"] / sec) if sec else None,
+           "sampler_steps_per_s": round(kt["sample_steps"] / sec) if sec else None}
+    if GATHER:
+        # segment size of one gather: an LT step reads an 8-record threshold
+        # window (64 B); an IC node its in-list (mean length x 8 B)
+        if model == 1:
+            seg = 64
+        else:
+            mean = 8.0 * kt["sample_steps"] / max(kt["sample_nodes"], 1)
+            seg = min(GATHER, key=lambda x: abs(math.log2(x) - math.log2(max(mean, 1.0))))
+        out["gather_gbs"] = GATHER
+        out["gather_segment_bytes"] = seg
+        out["gather_frac"] = round(achieved / GATHER[seg], 5)
+    return out
+
+
+GATHER = {}
 
 
 def log_uniform_k(rng, hi: int, n: int) -> int:
@@ -326,15 +360,20 @@ def run_serving(args, im, ctx, sync):
 def run_twitter(args, im, ctx, sync):
     import synth
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     t_gen = time.perf_counter()
     g = synth.make("twitter", cache=os.environ.get("IM_CACHE_BIG", "") == "1")
     t_gen = time.perf_counter() - t_gen
+    progress(f"graph n={g.n} m={g.m} generated in {t_gen:.1f} s")
     n = g.n
     delta = 1.0 / n
     t_load = time.perf_counter()
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
     sync()
     t_load = time.perf_counter() - t_load
+    progress(f"graph loaded in {t_load:.1f} s")
     ks = [1, 100, 1000]
     for i in range(args.warmup):
         dg.dssa(im.IM_IC, 100, 0.1, delta, 1_000_000 + i)
@@ -348,6 +387,7 @@ def run_twitter(args, im, ctx, sync):
             q0 = time.perf_counter()
             _, st = dg.dssa(im.IM_IC, k, 0.1, delta, step)
             ms = (time.perf_counter() - q0) * 1e3
+            progress(f"step {step} k={k}: {ms:.1f} ms, {st['n_sets']} sets, {st['iterations']} iterations")
             lat.append(ms)
             sets += st["n_sets"]
             edges += st["edges"]
@@ -408,8 +448,12 @@ def main() -> int:
                     help="R-MAT-20: concurrent D-SSA queries per step through the multi-query engine")
     ap.add_argument("--greedy-wg-max-entries", type=int, default=None,
                     help="launch parameter: largest Max-Coverage range run in one workgroup")
+    ap.add_argument("--no-speculate", action="store_true",
+                    help="launch parameter: D-SSA draws each iteration's sets only after the previous check")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gather-probe", action="store_true",
+                    help="skip measuring the random-gather bandwidth the sampler is compared with")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -426,9 +470,13 @@ def main() -> int:
         if torch is not None:
             torch.cuda.synchronize()
 
+    if not args.no_gather_probe:
+        GATHER.update(gather_bandwidth())
     ctx = im.Context(0)
     if args.greedy_wg_max_entries is not None:
         ctx.set_param("greedy_wg_max_entries", args.greedy_wg_max_entries)
+    if args.no_speculate:
+        ctx.set_param("dssa_speculate", 0)
     body, cpu = WORKLOADS[args.workload](args, im, ctx, sync)
     steps = args.steps if args.workload != "serving" else 1
     out = {"metric": METRIC, "value": body.pop("value"), "unit": "RR sets/s", "n_gpus": 1, "steps": steps,

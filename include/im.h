@@ -240,10 +240,18 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       are at most this runs all k rounds in one workgroup; a larger one
  *       launches grid-wide kernels every round (default 65536);
  *   IM_PARAM_IC_TICKET_BLOCK        consecutive samples an IC wave takes per
- *       ticket, 1..64, or 0 for the automatic choice (default 0).
+ *       ticket, 1..64, or 0 for the automatic choice (default 0);
+ *   IM_PARAM_DSSA_SPECULATE         1: im_dssa draws the next iteration's
+ *       new RR sets on a second stream (own work buffers, from a helper
+ *       thread) while the current iteration is covered, and drops them if
+ *       it stops; 0: strictly one step after another (default 1).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
-typedef enum { IM_PARAM_GREEDY_WG_MAX_ENTRIES = 0, IM_PARAM_IC_TICKET_BLOCK = 1 } im_param;
+typedef enum {
+    IM_PARAM_GREEDY_WG_MAX_ENTRIES = 0,
+    IM_PARAM_IC_TICKET_BLOCK = 1,
+    IM_PARAM_DSSA_SPECULATE = 2
+} im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);
 im_status im_ctx_read_timing(im_ctx *ctx, im_kernel_times *out, int reset);

@@ -32,8 +32,9 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
            "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param"]
 
-IM_PARAM_GREEDY_WG_MAX_ENTRIES, IM_PARAM_IC_TICKET_BLOCK = 0, 1
-PARAMS = {"greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK}
+IM_PARAM_GREEDY_WG_MAX_ENTRIES, IM_PARAM_IC_TICKET_BLOCK, IM_PARAM_DSSA_SPECULATE = 0, 1, 2
+PARAMS = {"greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK,
+          "dssa_speculate": IM_PARAM_DSSA_SPECULATE}
 
 IM_ALGO_SSA, IM_ALGO_DSSA = 0, 1
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}

@@ -10,6 +10,9 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libim.so"
 SOURCES = ["api.hip", "graph.hip", "sample.hip", "cover.hip", "engine.hip"]
+# measurement helper (random-gather bandwidth probe), a library of its own
+PROBE_LIB = HERE / "libimprobe.so"
+PROBE_SOURCES = ["gather_probe.hip"]
 ARCH = os.environ.get("IM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,12 +31,19 @@ def flags() -> list[str]:
 
 
 def build(verbose: bool = False) -> Path:
-    """Compile every source to an object, then link libim.so (always rebuilds)."""
+    """Compile every source to an object, then link libim.so and the probe
+    library (always rebuilds)."""
+    _build_lib(SOURCES, LIB, verbose)
+    _build_lib(PROBE_SOURCES, PROBE_LIB, verbose)
+    return LIB
+
+
+def _build_lib(sources, lib: Path, verbose: bool) -> Path:
     objdir = HERE / "_build"
     objdir.mkdir(exist_ok=True)
     objs = []
     procs = []
-    for src in SOURCES:
+    for src in sources:
         obj = objdir / (Path(src).stem + ".o")
         cmd = [hipcc(), *flags(), "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
@@ -49,10 +59,10 @@ def build(verbose: bool = False) -> Path:
             print(out)
     if failed:
         raise RuntimeError("HIP build failed:\n" + "\n".join(failed))
-    tmp = str(LIB) + ".tmp"
+    tmp = str(lib) + ".tmp"
     subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "im_internal.hpp"
@@ -159,6 +161,44 @@ im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps,
 // Largest batch drawn at once: LT reserves a staging region per sample.
 uint64_t max_batch(im_model model) { return model == IM_LT ? (1ull << 20) : (1ull << 24); }
 
+im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
+    if (!ctx->aux) {
+        auto *a = new (std::nothrow) im_ctx();
+        if (!a) return IM_E_OOM;
+        a->device = ctx->device;
+        a->alloc = ctx->alloc;
+        a->free_ = ctx->free_;
+        a->user = ctx->user;
+        a->cu_count = ctx->cu_count;
+        a->total_mem = ctx->total_mem;
+        a->slot_budget = ctx->slot_budget;
+        a->speculate = false;
+        if (hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete a;
+            set_error("auxiliary stream creation failed");
+            return IM_E_DEVICE;
+        }
+        a->owns_stream = true;
+        if (hipHostMalloc(&a->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+            (void)hipStreamDestroy(a->stream);
+            delete a;
+            set_error("pinned host allocation failed");
+            return IM_E_OOM;
+        }
+        ctx->aux = a;
+    }
+    im_ctx *a = ctx->aux;
+    if (ctx->timing && !a->ev_begin) {
+        IM_HIP(hipEventCreate(&a->ev_begin));
+        IM_HIP(hipEventCreate(&a->ev_end));
+    }
+    a->timing = ctx->timing;
+    a->greedy_wg_max_entries = ctx->greedy_wg_max_entries;
+    a->ic_ticket_block = ctx->ic_ticket_block;
+    *out = a;
+    return IM_OK;
+}
+
 static im_status pool_extend_to(im_pool *p, uint64_t target, double *ms) {
     const double t0 = now_ms();
     while (p->count < target) {
@@ -273,6 +313,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 64) break;
         c->ic_ticket_block = static_cast<uint32_t>(value);
         return IM_OK;
+    case IM_PARAM_DSSA_SPECULATE:
+        if (value > 1) break;
+        c->speculate = value != 0;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -288,6 +332,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
     case IM_PARAM_IC_TICKET_BLOCK:
         *value = c->ic_ticket_block;
         return IM_OK;
+    case IM_PARAM_DSSA_SPECULATE:
+        *value = c->speculate ? 1 : 0;
+        return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
     return IM_E_ARG;
@@ -297,12 +344,23 @@ extern "C" im_status im_ctx_read_timing(im_ctx *c, im_kernel_times *out, int res
     clear_error();
     if (!c || !out) return IM_E_ARG;
     *out = c->times;
+    if (c->aux) {
+        const im_kernel_times &a = c->aux->times;
+        out->sample_launches += a.sample_launches;
+        out->sample_ms += a.sample_ms;
+        out->sample_sets += a.sample_sets;
+        out->sample_steps += a.sample_steps;
+        out->sample_nodes += a.sample_nodes;
+        if (a.sample_launches) out->model = a.model;
+        if (reset) c->aux->times = im_kernel_times{};
+    }
     if (reset) c->times = im_kernel_times{};
     return IM_OK;
 }
 
 extern "C" void im_ctx_free(im_ctx *c) {
     if (!c) return;
+    if (c->aux) im_ctx_free(c->aux);
     (void)hipStreamSynchronize(c->stream);
     if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
@@ -310,6 +368,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
                       &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    if (c->owns_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -589,6 +648,50 @@ extern "C" im_status im_ssa(const im_graph *g, im_model model, uint32_t k, doubl
     return rc;
 }
 
+namespace {
+
+// One speculative draw: samples [s0, s0+count) of a pool's stream, drawn on
+// the auxiliary context by a helper thread into that context's staging.
+struct Speculation {
+    std::thread th;
+    bool running = false;
+    im_status rc = IM_OK;
+    std::string err;
+    uint64_t s0 = 0, count = 0;
+    SampleResult res;
+    ItemTotals tot;
+
+    void start(im_ctx *aux, const im_pool *p, uint64_t first, uint64_t n) {
+        s0 = first;
+        count = n;
+        running = true;
+        const im_graph *g = p->g;
+        const im_model model = p->model;
+        const uint64_t key = p->key;
+        const double hint = p->mean_size;
+        th = std::thread([this, aux, g, model, key, hint] {
+            if (hipSetDevice(aux->device) != hipSuccess) {
+                rc = IM_E_DEVICE;
+                err = "hipSetDevice failed in the sampling thread";
+                return;
+            }
+            SampleItem it{key, s0, count, nullptr};
+            rc = sample_items(aux, g, model, &it, 1, SampleMode::Pool, hint, &res, &tot);
+            if (rc != IM_OK) err = im_last_error();
+        });
+    }
+    // Wait for the draw; on failure the thread's message becomes this one's.
+    im_status join() {
+        if (!running) return IM_OK;
+        th.join();
+        running = false;
+        if (rc != IM_OK) set_error("%s", err.c_str());
+        return rc;
+    }
+};
+
+}  // namespace
+
 extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
                              uint32_t *seeds_out, im_stats *st) {
     clear_error();
@@ -601,19 +704,46 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     const Caps c = caps(g->n, k, eps, delta);  // t_max = i_max
     const double lambda1 = 1.0 + (1.0 + eps) * upsilon(eps, delta / (3.0 * c.i_max));
     const double n = double(g->n);
+    im_ctx *ctx = g->ctx;
 
     im_pool *pool = nullptr;
-    IM_TRY(im_pool_create(g->ctx, g, model, key, &pool));
+    IM_TRY(im_pool_create(ctx, g, model, key, &pool));
+    im_ctx *aux = nullptr;
+    if (ctx->speculate && aux_ctx(ctx, &aux) != IM_OK) aux = nullptr;  // run without speculation
+    clear_error();
+    Speculation spec;
+    double ms_draw = 0.0, ms_cover_last = 0.0;  // wall time of the last own draw of N_t sets / last cover
     std::vector<uint32_t> seeds(k);
     const uint64_t n1 = uint64_t(std::ceil(c.lambda));
     im_status rc = IM_OK;
     for (uint32_t t = 1;; ++t) {
         const uint64_t nt = n1 << (t - 1);
-        if ((rc = pool_extend_to(pool, 2 * nt, &st->ms_sample))) break;
-        uint64_t cov = 0, cov_c = 0;
         double t0 = now_ms();
+        if (spec.running) {
+            // the previous iteration drew this one's new sets on the side
+            if ((rc = spec.join())) break;
+            if (spec.s0 == pool->count) {
+                AppendItem ap{pool, spec.count, spec.tot.nodes, spec.tot.edges};
+                if ((rc = pool_append_items(aux, &ap, 1))) break;
+            }
+        }
+        const double t_fresh = now_ms();
+        if ((rc = pool_extend_to(pool, 2 * nt, nullptr))) break;
+        const double ms_fresh = now_ms() - t_fresh;  // this iteration's own draw, if any
+        st->ms_sample += now_ms() - t0;
+        // draw the next iteration's new sets [2 N_t, 4 N_t) while this one is
+        // covered (they are dropped if this iteration stops), when the cover
+        // step is expected to take at least half as long as that draw: the
+        // last iteration's cover time, or about 15 us per greedy round
+        if (ms_fresh > 0) ms_draw = ms_fresh;
+        const double est_cover = std::max(ms_cover_last, 0.015 * k);
+        if (aux && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw)
+            spec.start(aux, pool, 2 * nt, 2 * nt);
+        uint64_t cov = 0, cov_c = 0;
+        t0 = now_ms();
         if ((rc = max_coverage(pool, 0, nt, k, seeds.data(), &cov))) break;
-        st->ms_cover += now_ms() - t0;
+        ms_cover_last = now_ms() - t0;
+        st->ms_cover += ms_cover_last;
         t0 = now_ms();
         if ((rc = coverage_range(pool, nt, 2 * nt, seeds.data(), k, &cov_c))) break;
         st->ms_verify += now_ms() - t0;
@@ -651,6 +781,8 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
             break;
         }
     }
+    const im_status rs = spec.join();  // a draw still running is waited for and dropped
+    if (rc == IM_OK) rc = rs;
     if (rc == IM_OK) {
         st->edges = pool->edges;
         std::memcpy(seeds_out, seeds.data(), 4ull * k);

@@ -50,27 +50,6 @@ __global__ void histogram_kernel(const uint32_t *nodes, uint64_t begin, uint64_t
 
 // ---- exclusive scan of u32 counts into u64 offsets (n+1 entries) ----
 
-__device__ __forceinline__ uint64_t block_scan_excl(uint64_t x, uint64_t *smem, uint64_t &total) {
-    const uint32_t lane = lane_id();
-    const uint32_t wave = threadIdx.x / kWave;
-    uint64_t inc = x;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint64_t y = __shfl_up(inc, d, kWave);
-        if (lane >= static_cast<uint32_t>(d)) inc += y;
-    }
-    if (lane == kWave - 1) smem[wave] = inc;
-    __syncthreads();
-    uint64_t off = 0, tot = 0;
-    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) {
-        if (w < wave) off += smem[w];
-        tot += smem[w];
-    }
-    __syncthreads();
-    total = tot;
-    return off + inc - x;
-}
-
 constexpr uint32_t kTile = 1024;
 
 __global__ __launch_bounds__(kThreads) void tile_sums_kernel(const uint32_t *in, uint64_t count, uint64_t *tsum) {
@@ -172,6 +151,7 @@ struct GreedyState {
     unsigned long long *cov;
     uint32_t *dirty;  // one-workgroup rounds: chunk bitmap (n1 bits), zeroed
     uint64_t nsets;   // sets in the range
+    unsigned long long *bmax;  // per-round launches: each refresh block's largest key
 };
 
 // Load flavours. State written by earlier kernels is read with plain loads.
@@ -284,14 +264,10 @@ __global__ __launch_bounds__(kThreads) void init_m2_kernel(GreedyState g) {
 // The seed of round r from m2 (all threads of one block): the argmax key's
 // node, or, when every remaining gain is zero, the lowest id not yet chosen
 // (at most r, since only r nodes are chosen).
-template <bool kWg>
-__device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long *smem, uint32_t *s_pick) {
-    unsigned long long best = 0;
-    for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) {
-        const unsigned long long m = ld<true>(g.m2 + d);
-        best = m > best ? m : best;
-    }
-    best = block_max_u64(best, smem);
+// The seed of round r given the largest key `best` (all threads of one
+// block): that key's node, or, when every remaining gain is zero, the lowest
+// id not yet chosen (at most r, since only r nodes are chosen).
+__device__ uint32_t choose_key(const GreedyState &g, uint32_t r, unsigned long long best, uint32_t *s_pick) {
     if ((best >> 32) == 0) {
         if (threadIdx.x == 0) *s_pick = 0xFFFFFFFFu;
         __syncthreads();
@@ -313,32 +289,60 @@ __device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long 
     return v;
 }
 
-// Round step 1 (grid-wide): re-validate m1; the last block to finish then
-// re-validates m2 and chooses the round's seed (release fence + counter on
-// the writers' side, acquire fence on the last block's side).
-__global__ __launch_bounds__(kThreads) void refresh_choose_kernel(GreedyState g, uint32_t r) {
-    __shared__ unsigned long long smem[kThreads / kWave];
-    __shared__ uint32_t s_pick;
-    __shared__ bool s_last;
-    if (r > 0) {
-        for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n1; c += gridDim.x * blockDim.x)
-            refresh_m1_one<false>(g, c);
+// The seed of round r from m2 (all threads of one block).
+template <bool kWg>
+__device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long *smem, uint32_t *s_pick) {
+    unsigned long long best = 0;
+    for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) {
+        const unsigned long long m = ld<true>(g.m2 + d);
+        best = m > best ? m : best;
     }
+    best = block_max_u64(best, smem);
+    return choose_key(g, r, best, s_pick);
+}
+
+// Round step 1 body (grid-wide over one job's blocks): re-validate m1 and
+// take each block's largest key; the last block to finish (release fence +
+// counter on the writers' side, acquire fence on its side) takes the largest
+// of those and chooses the round's seed.
+__device__ __forceinline__ void refresh_choose(const GreedyState &g, uint32_t r, uint32_t blk, uint32_t nblk,
+                                               unsigned long long *smem, uint32_t *s_pick, bool *s_last) {
+    unsigned long long best = 0;
+    for (uint32_t c = blk * blockDim.x + threadIdx.x; c < g.n1; c += nblk * blockDim.x) {
+        unsigned long long m = g.m1[c];
+        if (r > 0 && m != 0ull && node_key<false>(g.gain, ~static_cast<uint32_t>(m)) != m) {
+            m = m1_lane<false>(g, c);
+            g.m1[c] = m;
+        }
+        best = m > best ? m : best;
+    }
+    best = block_max_u64(best, smem);
+    if (threadIdx.x == 0) g.bmax[blk] = best;
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(g.done, 1u) == gridDim.x - 1;
+    if (threadIdx.x == 0) *s_last = atomicAdd(g.done, 1u) == nblk - 1;
     __syncthreads();
-    if (!s_last) return;
+    if (!*s_last) return;
     __threadfence();
-    if (r > 0) {
-        for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) refresh_m2_one<false>(g, d);
-        __syncthreads();
+    best = 0;
+    for (uint32_t i = threadIdx.x; i < nblk; i += blockDim.x) {
+        const unsigned long long m = g.bmax[i];
+        best = m > best ? m : best;
     }
-    const uint32_t v = choose<true>(g, r, smem, &s_pick);
+    best = block_max_u64(best, smem);
+    const uint32_t v = choose_key(g, r, best, s_pick);
     if (threadIdx.x == 0) {
         *g.pick = v;
         *g.done = 0u;
     }
+}
+
+// Round step 1 (grid-wide).
+__global__ __launch_bounds__(kThreads) void refresh_choose_kernel(GreedyState g, uint32_t r) {
+    __shared__ unsigned long long smem[kThreads / kWave];
+    __shared__ uint32_t s_pick;
+    __shared__ bool s_last;
+    refresh_choose(g, r, blockIdx.x, gridDim.x, smem, &s_pick, &s_last);
 }
 
 // Round step 3 (grid-wide): cover the seed's sets, 16 lanes per incidence entry.
@@ -374,25 +378,7 @@ __global__ __launch_bounds__(kThreads) void batch_refresh_choose_kernel(const Gr
     __shared__ bool s_last;
     const GreedyState &g = jobs[blockIdx.y];
     if (r >= g.k) return;
-    if (r > 0) {
-        for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < g.n1; c += gridDim.x * blockDim.x)
-            refresh_m1_one<false>(g, c);
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(g.done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (r > 0) {
-        for (uint32_t d = threadIdx.x; d < g.n2; d += blockDim.x) refresh_m2_one<false>(g, d);
-        __syncthreads();
-    }
-    const uint32_t v = choose<true>(g, r, smem, &s_pick);
-    if (threadIdx.x == 0) {
-        *g.pick = v;
-        *g.done = 0u;
-    }
+    refresh_choose(g, r, blockIdx.x, gridDim.x, smem, &s_pick, &s_last);
 }
 
 __global__ __launch_bounds__(kThreads) void batch_cover_kernel(const GreedyState *jobs, uint32_t r) {
@@ -867,7 +853,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
                  o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
                  o_m2 = take(8ull * n2), o_cnt = take(16), o_job = take(sizeof(GreedyState)),
-                 o_dirty = take(4ull * ((n1 + 31) / 32));
+                 o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
@@ -899,6 +885,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     g.cov = dcov;
     g.dirty = at32(o_dirty);
     g.nsets = nsets;
+    g.bmax = reinterpret_cast<unsigned long long *>(base + o_bmax);
 
     hipStream_t st = ctx->stream;
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
@@ -917,10 +904,11 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
                                                                                      fill, isets);
     // maximum index, then the rounds
     init_m1_kernel<<<grid_of(n1, kThreads, cu * 8), kThreads, 0, st>>>(g);
-    init_m2_kernel<<<grid_of(n2, kThreads, cu * 8), kThreads, 0, st>>>(g);
     // per-round launches pay for themselves once the cover work per round is
-    // large; tiny problems keep every round in one workgroup
+    // large; tiny problems keep every round in one workgroup (which chooses
+    // from m2; the per-round launches reduce block maxima of m1 instead)
     const bool small = entries <= ctx->greedy_wg_max_entries;
+    if (small) init_m2_kernel<<<grid_of(n2, kThreads, cu * 8), kThreads, 0, st>>>(g);
     const uint32_t big = small ? 0u : k;
     const uint32_t cgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
     const uint32_t rgrid = grid_of(uint64_t(n1), kThreads, cu * 4);
@@ -1020,7 +1008,8 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
                  o_m1 = take(8ull * nj * n1), o_m2 = take(8ull * nj * n2), o_seeds = take(4 * (tot_seeds + 1)),
                  o_cov = take(8ull * nj), o_covc = take(8ull * nj), o_bits = take(4 * words * nj),
                  o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj),
-                 o_dirty = take(4ull * nj * ((n1 + 31) / 32)), o_pd = take(8ull * nj);
+                 o_dirty = take(4ull * nj * ((n1 + 31) / 32)), o_pd = take(8ull * nj),
+                 o_bmax = take(8ull * nj * 1024);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto *gains = reinterpret_cast<uint32_t *>(base + o_gain);
@@ -1061,6 +1050,7 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.seeds = seeds + jt[j].seed_start;
         g.pick = reinterpret_cast<uint32_t *>(base + o_pd) + 2ull * j;
         g.done = g.pick + 1;
+        g.bmax = reinterpret_cast<unsigned long long *>(base + o_bmax) + 1024ull * j;
         g.cov = covs + j;
         g.dirty = reinterpret_cast<uint32_t *>(base + o_dirty) + uint64_t(j) * ((n1 + 31) / 32);
         g.nsets = cj.end - cj.begin;
@@ -1098,7 +1088,7 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
     } else {
         fill_u32_kernel<<<grid_of(2ull * nj, kThreads, cu), kThreads, 0, st>>>(
             reinterpret_cast<uint32_t *>(base + o_pd), 2ull * nj, 0u);
-        const uint32_t per = std::max<uint32_t>(1, (cu * 4 + nj - 1) / nj);
+        const uint32_t per = std::min<uint32_t>(1024, std::max<uint32_t>(1, (cu * 4 + nj - 1) / nj));
         const uint32_t rx = std::min<uint32_t>(per, grid_of(uint64_t(n1), kThreads, cu * 4));
         const uint32_t cx = std::min<uint32_t>(per, std::max<uint32_t>(1, grid_of(max_entries * 16, kThreads, cu * 4)));
         for (uint32_t r = 0; r < max_k; ++r) {

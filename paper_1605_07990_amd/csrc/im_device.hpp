@@ -146,6 +146,29 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Block-wide exclusive prefix sum (every thread of the block calls it;
+// smem holds one entry per wave); total receives the block's sum.
+__device__ __forceinline__ uint64_t block_scan_excl(uint64_t x, uint64_t *smem, uint64_t &total) {
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint64_t inc = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d, kWave);
+        if (lane >= static_cast<uint32_t>(d)) inc += y;
+    }
+    if (lane == kWave - 1) smem[wave] = inc;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) {
+        if (w < wave) off += smem[w];
+        tot += smem[w];
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - x;
+}
+
 __device__ __forceinline__ bool test_bit(const uint32_t *bits, uint32_t v) {
     return (bits[v >> 5] >> (v & 31u)) & 1u;
 }

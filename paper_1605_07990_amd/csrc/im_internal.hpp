@@ -76,6 +76,14 @@ struct im_ctx {
     bool timing = false;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     im_kernel_times times{};
+
+    // second sampling context on its own stream (same device and allocator,
+    // own work buffers), used by a helper thread to draw the next D-SSA
+    // iteration's sets while the current one is covered; created on first use
+    im_ctx *aux = nullptr;
+    bool owns_stream = false;
+    size_t slot_budget = 8ull << 30;  // long-path slot memory cap
+    bool speculate = true;
 };
 
 struct im_graph {
@@ -229,6 +237,8 @@ Caps caps(uint32_t n, uint32_t k, double eps, double delta);
 im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps, double delta);
 uint64_t derived_key(uint64_t key, uint64_t i);
 uint64_t max_batch(im_model model);
+// The context's auxiliary sampling context (created on first use).
+im_status aux_ctx(im_ctx *ctx, im_ctx **out);
 // Seed bitmap of n bits in `out` from host seeds.
 im_status seed_bits_into(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k, DevBuf &out);
 

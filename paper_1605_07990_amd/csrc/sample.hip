@@ -38,11 +38,18 @@ constexpr uint32_t kBitmapMaxN = kIcHcap * 32;
 constexpr uint32_t kLtCap = 512;             // per-sample staging region (LT)
 constexpr int kLongWaves = 4;
 constexpr uint32_t kStageChunk = 1024;       // IC staging entries a wave reserves at once
+constexpr uint64_t kIcEdgeBudget = 16384;    // edges a wave examines before a workgroup takes the sample over
+constexpr int kGrpThreads = 1024;            // IC workgroup tier: threads per sample
+constexpr uint32_t kGrpQcap = 8192;          // its LDS queue entries
+constexpr uint32_t kGrpHcap = 16384;         // its LDS hash slots
+constexpr uint32_t kGrpHbits = 14;
 
 struct Counters {
     uint32_t ticket;        // next sample of the main pass
-    uint32_t defer_count;   // samples handed to the long path
-    uint32_t defer_ticket;  // next deferred sample of the long path
+    uint32_t defer_count;   // samples handed on by the main pass (IC: to the workgroup tier; LT: to the long path)
+    uint32_t defer_ticket;  // next of them to take
+    uint32_t long_count;    // IC samples the workgroup tier hands to the long path
+    uint32_t long_ticket;
     uint32_t overflow;      // staging too small: the batch must be re-run
     unsigned long long stage_cursor;
     unsigned long long edges;        // main pass
@@ -72,6 +79,7 @@ struct Params {
     uint32_t nitems;
     Counters *cnt;
     uint32_t *defer_list;
+    uint32_t *long_list;  // IC: samples the workgroup tier hands to the long path
     uint32_t *stage;
     uint64_t stage_cap;
     uint64_t *stage_off;  // per sample
@@ -159,6 +167,8 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
     c->ticket = 0;
     c->defer_count = 0;
     c->defer_ticket = 0;
+    c->long_count = 0;
+    c->long_ticket = 0;
     c->overflow = 0;
     c->stage_cursor = cursor0;
     c->edges = 0;
@@ -270,7 +280,12 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
         uint64_t sample_edges = 0;
         wave_sync();
 
+        bool heavy = false;
         while (head < tail && !hit) {
+            if (sample_edges >= kIcEdgeBudget) {  // a workgroup finishes it
+                heavy = true;
+                break;
+            }
             const uint32_t nb = min(tail - head, static_cast<uint32_t>(kWave));
             uint32_t cg = 0;
             uint64_t a = 0, b = 0;
@@ -343,7 +358,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
             if (stop) break;
         }
 
-        const bool overflow = (tail > kIcQcap) || (__ballot(full) != 0);
+        const bool overflow = (tail > kIcQcap) || (__ballot(full) != 0) || heavy;
         if (overflow && !hit) {
             if (lane == 0) {
                 const uint32_t d = atomicAdd(&p.cnt->defer_count, 1u);
@@ -593,6 +608,166 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
     }
 }
 
+// ------------------------------------------------------- IC workgroup ----
+
+// LDS open-addressed set of node ids (key u + 1) for one workgroup.
+__device__ __forceinline__ bool grp_insert(uint32_t *vis, uint32_t u, bool &full) {
+    const uint32_t key = u + 1u;
+    uint32_t h = (u * 2654435761u) >> (32 - kGrpHbits);
+    for (uint32_t probe = 0; probe < kGrpHcap; ++probe) {
+        const uint32_t old = atomicCAS(&vis[h], 0u, key);
+        if (old == 0u) return true;
+        if (old == key) return false;
+        h = (h + 1u) & (kGrpHcap - 1u);
+    }
+    full = true;
+    return false;
+}
+
+// IC samples the wave pass handed on (too many edges for one wave, or too
+// large for its LDS), one workgroup per sample: each level's frontier (up to
+// 1024 nodes at a time) is laid out by a block scan of its aligned 4-edge
+// groups, which all threads then expand. Samples too large for this LDS go
+// on to the long path.
+template <int kMode>
+__global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
+    __shared__ uint32_t s_queue[kGrpQcap];
+    __shared__ uint32_t s_vis[kGrpHcap];
+    __shared__ uint64_t s_pre[kGrpThreads];
+    __shared__ uint64_t s_a[kGrpThreads];
+    __shared__ uint64_t s_b[kGrpThreads];
+    __shared__ uint64_t s_scan[kGrpThreads / kWave];
+    __shared__ unsigned long long s_edges;
+    __shared__ uint32_t s_t, s_tail, s_flags;  // flags: 1 hit, 2 too large
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < kGrpHcap; i += blockDim.x) s_vis[i] = 0u;
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t d = atomicAdd(&p.cnt->defer_ticket, 1u);
+            s_t = d < p.cnt->defer_count ? p.defer_list[d] : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        const uint32_t t = s_t;
+        if (t == 0xFFFFFFFFu) break;
+        const WorkItem &it = item_of(p, t);
+        const Stream st(it.key);
+        const uint32_t *seedbits = it.seedbits;
+        const uint64_t s = it.s0 + (t - it.start);
+        if (tid == 0) {
+            const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
+            bool full = false;
+            grp_insert(s_vis, v0, full);
+            s_queue[0] = v0;
+            s_tail = 1;
+            s_flags = (kMode == 1 && test_bit(seedbits, v0)) ? 1u : 0u;
+            s_edges = 0;
+        }
+        __syncthreads();
+        uint32_t head = 0;
+        for (;;) {
+            const uint32_t tail = s_tail;
+            if (head >= tail || s_flags != 0u) break;
+            const uint32_t nb = min(tail - head, static_cast<uint32_t>(kGrpThreads));
+            uint64_t a = 0, b = 0, cg = 0;
+            if (tid < nb) {
+                const uint32_t v = s_queue[head + tid];
+                a = p.off[v];
+                b = p.off[v + 1];
+                if (b > a) cg = ((b - 1) >> 2) - (a >> 2) + 1;
+            }
+            const uint64_t de = b - a;
+            if (de) atomicAdd(&s_edges, static_cast<unsigned long long>(de));
+            uint64_t groups = 0;
+            const uint64_t pre = block_scan_excl(cg, s_scan, groups);
+            s_pre[tid] = pre;
+            s_a[tid] = a;
+            s_b[tid] = b;
+            __syncthreads();
+            head += nb;
+            for (uint64_t w = tid; w < groups; w += blockDim.x) {
+                // owner: last frontier slot whose first group index <= w
+                uint32_t lo = 0, hi = nb - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= w) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint64_t ea = s_a[lo], eb = s_b[lo];
+                const uint64_t g = (ea >> 2) + (w - s_pre[lo]);
+                const uint4 coins = ic_coins(st, s, g);
+                bool full = false;
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) {
+                    const uint64_t e = (g << 2) + q;
+                    if (e >= ea && e < eb) {
+                        const uint2 rec = p.edges[e];
+                        if (ic_live(word_of(coins, q), rec.y) && grp_insert(s_vis, rec.x, full)) {
+                            const uint32_t pos = atomicAdd(&s_tail, 1u);
+                            if (pos < kGrpQcap) s_queue[pos] = rec.x;
+                            else atomicOr(&s_flags, 2u);
+                            if (kMode == 1 && test_bit(seedbits, rec.x)) atomicOr(&s_flags, 1u);
+                        }
+                    }
+                }
+                if (full) atomicOr(&s_flags, 2u);
+            }
+            __syncthreads();
+        }
+        const uint32_t flags = s_flags;
+        const uint32_t tail = min(s_tail, kGrpQcap);
+        const uint64_t sample_edges = s_edges;
+        if ((flags & 2u) && !(flags & 1u)) {
+            if (tid == 0) {
+                const uint32_t d = atomicAdd(&p.cnt->long_count, 1u);
+                p.long_list[d] = t;
+            }
+        } else if (kMode == 1) {
+            if (tid == 0) {
+                p.z[t] = (flags & 1u) ? 1 : 0;
+                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
+                atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(sample_edges));
+            }
+        } else {
+            __shared__ unsigned long long s_base;
+            if (tid == 0) {
+                const unsigned long long base = atomicAdd(&p.cnt->stage_cursor, static_cast<unsigned long long>(tail));
+                s_base = base;
+                const bool fits = base + tail <= p.stage_cap;
+                if (!fits) atomicOr(&p.cnt->overflow, 1u);
+                p.sizes[t] = fits ? tail : 0;
+                p.stage_off[t] = fits ? base : 0;
+                atomicAdd(&it.acc[0], static_cast<unsigned long long>(tail));
+                atomicAdd(&it.acc[1], static_cast<unsigned long long>(sample_edges));
+                atomicAdd(&p.cnt->edges, static_cast<unsigned long long>(sample_edges));
+                atomicAdd(&p.cnt->total_nodes, static_cast<unsigned long long>(tail));
+            }
+            __syncthreads();
+            const unsigned long long base = s_base;
+            if (base + tail <= p.stage_cap)
+                for (uint32_t i = tid; i < tail; i += blockDim.x) p.stage[base + i] = s_queue[i];
+        }
+        __syncthreads();
+        // clear the visited set: entry by entry unless it may be incomplete
+        if (flags != 0u) {
+            for (uint32_t i = tid; i < kGrpHcap; i += blockDim.x) s_vis[i] = 0u;
+        } else {
+            for (uint32_t i = tid; i < tail; i += blockDim.x) {
+                const uint32_t u = s_queue[i], key = u + 1u;
+                uint32_t h = (u * 2654435761u) >> (32 - kGrpHbits);
+                for (uint32_t probe = 0; probe < kGrpHcap; ++probe) {
+                    if (s_vis[h] == key) {
+                        s_vis[h] = 0u;
+                        break;
+                    }
+                    h = (h + 1u) & (kGrpHcap - 1u);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------------- long path ----
 
 // One wave per slot; each slot owns vis[n] (epoch stamps) and queue[n].
@@ -613,12 +788,17 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
     uint64_t *fb = s_b[wave];
     uint64_t edges_acc = 0, nodes_acc = 0;
 
+    // LT samples come straight from the main pass, IC ones from the
+    // workgroup tier
+    const uint32_t *list = (kModel == IM_IC) ? p.long_list : p.defer_list;
+    uint32_t *ticket = (kModel == IM_IC) ? &p.cnt->long_ticket : &p.cnt->defer_ticket;
+    const uint32_t *count = (kModel == IM_IC) ? &p.cnt->long_count : &p.cnt->defer_count;
     for (;;) {
         uint32_t d = 0;
-        if (lane == 0) d = atomicAdd(&p.cnt->defer_ticket, 1u);
+        if (lane == 0) d = atomicAdd(ticket, 1u);
         d = __shfl(d, 0, kWave);
-        if (d >= p.cnt->defer_count) break;
-        const uint32_t t = p.defer_list[d];
+        if (d >= *count) break;
+        const uint32_t t = list[d];
         const WorkItem &it = item_of(p, t);
         const Stream st(it.key);
         const uint32_t *seedbits = it.seedbits;
@@ -900,10 +1080,11 @@ struct Meta {
     uint64_t *stage_off;
     uint32_t *sizes;
     uint32_t *defer_list;
+    uint32_t *long_list;
     uint8_t *z;
 };
 
-size_t meta_bytes(uint64_t count) { return count * (8 + 4 + 4 + 1) + 256; }
+size_t meta_bytes(uint64_t count) { return count * (8 + 4 + 4 + 4 + 1) + 256; }
 
 Meta meta_view(im_ctx *ctx, uint64_t count) {
     Meta m;
@@ -911,7 +1092,8 @@ Meta meta_view(im_ctx *ctx, uint64_t count) {
     m.stage_off = reinterpret_cast<uint64_t *>(base);
     m.sizes = reinterpret_cast<uint32_t *>(base + count * 8);
     m.defer_list = reinterpret_cast<uint32_t *>(base + count * 12);
-    m.z = reinterpret_cast<uint8_t *>(base + count * 16);
+    m.long_list = reinterpret_cast<uint32_t *>(base + count * 16);
+    m.z = reinterpret_cast<uint8_t *>(base + count * 20);
     return m;
 }
 
@@ -923,7 +1105,7 @@ namespace im {
 // (epoch stamps, zeroed once) and queue[n].
 static im_status ensure_slots(im_ctx *ctx, uint32_t n) {
     const uint64_t per_slot = 2ull * n * 4;
-    const uint64_t budget = std::min<uint64_t>(8ull << 30, ctx->total_mem / 16);
+    const uint64_t budget = std::min<uint64_t>(ctx->slot_budget, ctx->total_mem / 16);
     uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>(1024, budget / std::max<uint64_t>(per_slot, 1)));
     if (ctx->slots.ptr && ctx->slot_n == n && ctx->slot_count == want && ctx->slot_epoch < 0xF0000000ull)
         return IM_OK;
@@ -1002,6 +1184,7 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         p.nitems = nitems;
         p.cnt = cnt;
         p.defer_list = meta.defer_list;
+        p.long_list = meta.long_list;
         p.stage = static_cast<uint32_t *>(ctx->stage.ptr);
         p.stage_cap = cap;
         p.stage_off = meta.stage_off;
@@ -1043,6 +1226,11 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
             else lt_main_kernel<1><<<grid, kWave, 0, st>>>(p, tables, stamp_base);
         }
         if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_end, st));
+        if (model == IM_IC) {
+            const uint32_t ggrid = static_cast<uint32_t>(ctx->cu_count);
+            if (mode == SampleMode::Pool) ic_group_kernel<0><<<ggrid, kGrpThreads, 0, st>>>(p);
+            else ic_group_kernel<1><<<ggrid, kGrpThreads, 0, st>>>(p);
+        }
         {
             const uint32_t nslots = ctx->slot_count;
             const uint32_t grid = (nslots + kLongWaves - 1) / kLongWaves;
@@ -1061,7 +1249,7 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         std::vector<unsigned long long> hacc(2ull * nitems);
         IM_HIP(hipMemcpyAsync(hacc.data(), dacc, 16ull * nitems, hipMemcpyDeviceToHost, st));
         IM_TRY(to_host_sync(ctx, &hc, cnt, sizeof(hc)));
-        ctx->slot_epoch += hc.defer_count;
+        ctx->slot_epoch += (model == IM_IC) ? hc.long_count : hc.defer_count;
         if (hc.overflow) {
             cap = std::max<uint64_t>(cap * 2, hc.stage_cursor + (1u << 20));
             continue;

@@ -179,3 +179,30 @@ def test_stream_mismatch_and_bad_graphs(im, ctx):
         im.Graph(ctx, 3, np.array([2, 1], np.uint32), np.array([0, 0], np.uint32),
                  w_ic=np.array([0.5, 0.5], np.float32))
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("n,deg,p", [(3000, 24, 0.5), (6000, 40, 1.0), (12000, 20, 1.0)])
+def test_heavy_ic_samples_workgroup_tier(im, ctx, oracle_lib, n, deg, p):
+    """IC samples that examine more edges than one wave takes on go to the
+    workgroup tier (1024 threads, LDS queue of 8192, LDS hash of 16384);
+    those with more nodes than that go on to the long path. Every tier must
+    give the oracle's sets."""
+    rng = np.random.default_rng(n + deg)
+    dst = np.repeat(np.arange(n, dtype=np.uint32), deg)
+    src = rng.integers(0, n, size=n * deg).astype(np.uint32)
+    keep = src != dst
+    pairs = np.unique(np.stack([dst[keep], src[keep]], axis=1), axis=0)
+    g = synth.from_edges(f"heavy{n}", n, pairs[:, 1], pairs[:, 0],
+                         w_ic=np.full(pairs.shape[0], p, dtype=np.float32))
+    note(f"heavy IC samples n={n} m={g.m} p={p}")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+    count = 300
+    pool = im.Pool(dg, 0, 17)
+    pool.sample(count)
+    op = oracle_lib.Pool(og, 17)
+    op.extend(count)
+    assert_pool_equal(pool, op, 0, count)
+    # hits mode through the same tiers: Estimate-Inf's stopping index
+    seeds = np.array([0, 1], dtype=np.uint32)
+    assert dg.estimate_inf(0, seeds, 0.2, 0.1, 5000.0, 99) == og.estimate_inf(seeds, 0.2, 0.1, 5000.0, 99)
