@@ -374,7 +374,7 @@ def run_twitter(args, im, ctx, sync):
     sync()
     t_load = time.perf_counter() - t_load
     progress(f"graph loaded in {t_load:.1f} s")
-    ks = [1, 100, 1000]
+    ks = args.ks or [1, 100, 1000]
     for i in range(args.warmup):
         dg.dssa(im.IM_IC, 100, 0.1, delta, 1_000_000 + i)
     ctx.set_timing(True)
@@ -444,6 +444,7 @@ def main() -> int:
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--compare-plain", action="store_true", help="also time the queries one at a time")
+    ap.add_argument("--ks", type=int, nargs="*", default=None, help="Twitter-shaped workload: the k values")
     ap.add_argument("--queries-per-step", type=int, default=1,
                     help="R-MAT-20: concurrent D-SSA queries per step through the multi-query engine")
     ap.add_argument("--greedy-wg-max-entries", type=int, default=None,

@@ -199,6 +199,43 @@ im_status im_ssa(const im_graph *g, im_model model, uint32_t k, double eps, doub
                  uint32_t *seeds_out, im_stats *st);
 
 /*
+ * SSA (Algorithm 1) with a caller's precision split eps1, eps2, eps3 instead
+ * of Eq. 15's: each in (0, 1) and together meeting Eq. 14,
+ * (1-1/e)(eps1 + eps2 + eps1 eps2 + eps3) / ((1+eps1)(1+eps2)) <= eps.
+ * Otherwise as im_ssa. Errors: those of im_ssa; IM_E_ARG for a split that
+ * breaks Eq. 14.
+ */
+im_status im_ssa_eps(const im_graph *g, im_model model, uint32_t k, double eps, double eps1, double eps2,
+                     double eps3, double delta, uint64_t key, uint32_t *seeds_out, im_stats *st);
+
+/*
+ * A precision split for im_ssa_eps following the orderings Section 4.2
+ * recommends per network size: IM_NET_SMALL eps1 = 2x (eps1 above the
+ * others), IM_NET_MODERATE eps1 = x (all alike), IM_NET_LARGE eps1 = x/8
+ * (eps1 well below eps2 and eps3), with eps2 = eps3 = x and x the largest
+ * value meeting Eq. 14. out[3] receives (eps1, eps2, eps3).
+ * Errors: IM_E_ARG (unknown regime, eps outside (0, 1-1/e)).
+ */
+enum { IM_NET_SMALL = 0, IM_NET_MODERATE = 1, IM_NET_LARGE = 2 };
+im_status im_ssa_eps_preset(int regime, double eps, double *out);
+
+/*
+ * The fixed RIS threshold of Section 3's simplified bound, taking
+ * OPT_k >= k: theta = 8 (1-1/e) (ln(2/delta) + ln C(n,k)) n / (eps^2 k).
+ */
+double im_ris_theta(uint32_t n, uint32_t k, double eps, double delta);
+
+/*
+ * Fixed-threshold RIS: draw ceil(theta) RR sets of stream `key` (Definition
+ * 2), then one Max-Coverage (Algorithm 2) over all of them. st->n_sets =
+ * ceil(theta), st->cov, st->i_hat = n Cov / ceil(theta). This is the
+ * sample count the stopping rules of SSA / D-SSA are measured against.
+ * Errors: those of im_ssa; IM_E_OOM when the sets do not fit.
+ */
+im_status im_ris(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                 uint32_t *seeds_out, im_stats *st);
+
+/*
  * D-SSA (Algorithm 4): one stream; at iteration t the first
  * N_t = ceil(Lambda) 2^(t-1) sets find S_k, the next N_t verify it
  * (condition D1 Cov_c >= Lambda1, then eps_t <= eps, condition D2); stops
@@ -244,13 +281,19 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *   IM_PARAM_DSSA_SPECULATE         1: im_dssa draws the next iteration's
  *       new RR sets on a second stream (own work buffers, from a helper
  *       thread) while the current iteration is covered, and drops them if
- *       it stops; 0: strictly one step after another (default 1).
+ *       it stops; 0: strictly one step after another (default 1);
+ *   IM_PARAM_GREEDY_MARK_MIN_CHUNKS per-round Max-Coverage launches on a
+ *       graph with more than this many 64-node chunks have the cover step
+ *       mark every chunk it touches and re-derive only those; on smaller
+ *       graphs each chunk's maximum holder is re-checked instead (default
+ *       65536, i.e. n above 4,194,304).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
     IM_PARAM_GREEDY_WG_MAX_ENTRIES = 0,
     IM_PARAM_IC_TICKET_BLOCK = 1,
-    IM_PARAM_DSSA_SPECULATE = 2
+    IM_PARAM_DSSA_SPECULATE = 2,
+    IM_PARAM_GREEDY_MARK_MIN_CHUNKS = 3
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -105,6 +105,16 @@ def _load():
                                    u32p, sp]),
         "ora_dssa": (ctypes.c_int, [gp, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                     u32p, sp]),
+        "ora_ssa_eps": (ctypes.c_int, [gp, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_uint64, u32p, sp]),
+        "ora_ris": (ctypes.c_int, [gp, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                   u32p, sp]),
+        "ora_ris_theta": (ctypes.c_double, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_double]),
+        "ora_eps_admissible": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double]),
+        "ora_ssa_constants_eps": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, f64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -151,6 +161,16 @@ def ssa_constants(n: int, k: int, eps: float, delta: float) -> dict:
         raise OracleError(f"ora_ssa_constants rc={rc}")
     keys = ["eps1", "eps2", "eps3", "n_max", "i_max", "lambda", "lambda1", "delta2p"]
     return dict(zip(keys, list(out)))
+
+
+def ris_theta(n: int, k: int, eps: float, delta: float) -> float:
+    """Fixed RIS threshold of the simplified bound (OPT_k >= k)."""
+    return float(_load().ora_ris_theta(n, k, eps, delta))
+
+
+def eps_admissible(eps: float, eps1: float, eps2: float, eps3: float) -> bool:
+    """Eq. 14 for a precision split."""
+    return bool(_load().ora_eps_admissible(eps, eps1, eps2, eps3))
 
 
 def dssa_constants(n: int, k: int, eps: float, delta: float) -> dict:
@@ -234,6 +254,24 @@ class Graph:
                               seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st))
         if rc:
             raise OracleError(f"ora_dssa rc={rc}")
+        return seeds, st.as_dict()
+
+    def ssa_eps(self, k, eps, eps1, eps2, eps3, delta, key):
+        seeds = np.zeros(k, dtype=np.uint32)
+        st = _Stats()
+        rc = _load().ora_ssa_eps(self.ref, k, eps, eps1, eps2, eps3, delta, key,
+                                 seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st))
+        if rc:
+            raise OracleError(f"ora_ssa_eps rc={rc}")
+        return seeds, st.as_dict()
+
+    def ris(self, k, eps, delta, key):
+        seeds = np.zeros(k, dtype=np.uint32)
+        st = _Stats()
+        rc = _load().ora_ris(self.ref, k, eps, delta, key,
+                             seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st))
+        if rc:
+            raise OracleError(f"ora_ris rc={rc}")
         return seeds, st.as_dict()
 
 

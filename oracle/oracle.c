@@ -433,14 +433,21 @@ static double n_max_of(uint32_t n, uint32_t k, double eps, double delta) {
     return 8.0 * c / (2.0 + 2.0 * eps / 3.0) * upsilon_ln(eps, ln_inv) * (double)n / (double)k;
 }
 
-int ora_ssa_constants(uint32_t n, uint32_t k, double eps, double delta, double out[8]) {
+/* Eq. 14: the precision split of SSA is admissible when each eps_i is in  */
+/* (0, 1) and (1-1/e)(eps1 + eps2 + eps1 eps2 + eps3) / ((1+eps1)(1+eps2))   */
+/* does not exceed eps (a relative slack of 1e-12 admits Eq. 15's split,    */
+/* which meets it with equality up to rounding).                             */
+int ora_eps_admissible(double eps, double eps1, double eps2, double eps3) {
+    if (!(eps1 > 0.0 && eps1 < 1.0 && eps2 > 0.0 && eps2 < 1.0 && eps3 > 0.0 && eps3 < 1.0)) return 0;
+    const double c = 1.0 - exp(-1.0);
+    const double lhs = c * (eps1 + eps2 + eps1 * eps2 + eps3) / ((1.0 + eps1) * (1.0 + eps2));
+    return lhs <= eps * (1.0 + 1e-12);
+}
+
+static int ssa_constants_from(uint32_t n, uint32_t k, double eps, double eps1, double eps2, double eps3,
+                              double delta, double out[8]) {
     int rc = check_args(n, k, eps, delta);
     if (rc) return rc;
-    const double c = 1.0 - exp(-1.0);
-    /* Eq. 15 default setting */
-    double eps2 = eps / (2.0 * c);
-    double eps3 = eps2;
-    double eps1 = (1.0 + eps / (2.0 * (c - eps))) / (1.0 + eps2) - 1.0;
     double nmax = n_max_of(n, k, eps, delta);
     double imax = ceil(log2(2.0 * nmax / ora_upsilon(eps, delta / 3.0)));
     double lambda = ora_upsilon(eps, delta / (3.0 * imax));
@@ -456,6 +463,30 @@ int ora_ssa_constants(uint32_t n, uint32_t k, double eps, double delta, double o
     out[6] = lambda1;
     out[7] = delta2p;
     return ORA_OK;
+}
+
+/* A caller's split must meet Eq. 14 with every eps_i in (0, 1). */
+int ora_ssa_constants_eps(uint32_t n, uint32_t k, double eps, double eps1, double eps2, double eps3,
+                          double delta, double out[8]) {
+    if (!ora_eps_admissible(eps, eps1, eps2, eps3)) return ORA_E_ARG;
+    return ssa_constants_from(n, k, eps, eps1, eps2, eps3, delta, out);
+}
+
+/* Eq. 15's default split, as printed (for eps near 1-1/e its eps1 exceeds 1). */
+int ora_ssa_constants(uint32_t n, uint32_t k, double eps, double delta, double out[8]) {
+    const double c = 1.0 - exp(-1.0);
+    double eps2 = eps / (2.0 * c);
+    double eps3 = eps2;
+    double eps1 = (1.0 + eps / (2.0 * (c - eps))) / (1.0 + eps2) - 1.0;
+    return ssa_constants_from(n, k, eps, eps1, eps2, eps3, delta, out);
+}
+
+/* The fixed RIS threshold of Section 3's simplified bound: with OPT_k >= k, */
+/* theta = 8 (1-1/e) (ln(2/delta) + ln C(n,k)) n / (eps^2 k) RR sets give a   */
+/* (1-1/e-eps)-approximation with probability at least 1-delta.             */
+double ora_ris_theta(uint32_t n, uint32_t k, double eps, double delta) {
+    const double c = 1.0 - exp(-1.0);
+    return 8.0 * c * (log(2.0 / delta) + ora_ln_choose(n, k)) / (eps * eps) * (double)n / (double)k;
 }
 
 int ora_dssa_constants(uint32_t n, uint32_t k, double eps, double delta, double out[4]) {
@@ -520,11 +551,9 @@ double ora_estimate_inf(const ora_graph *g, const uint32_t *seeds, uint32_t k, d
 /* reaches N_max, returning that iteration's seeds.                          */
 /* Pinned by the (1-1/e-eps) guarantee against exhaustive OPT_k.             */
 /* ------------------------------------------------------------------------ */
-int ora_ssa(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t key,
-            uint32_t *seeds, ora_stats *st) {
-    double c[8];
-    int rc = ora_ssa_constants(g->n, k, eps, delta, c);
-    if (rc) return rc;
+static int ssa_run(const ora_graph *g, uint32_t k, const double c[8], uint64_t key, uint32_t *seeds,
+                   ora_stats *st) {
+    int rc;
     double eps1 = c[0], eps2 = c[1], eps3 = c[2], nmax = c[3], imax = c[4], lambda = c[5],
            lambda1 = c[6], delta2p = c[7];
     memset(st, 0, sizeof(*st));
@@ -576,6 +605,53 @@ int ora_ssa(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t k
     st->edges += pool.edges;
     ora_pool_free(&pool);
     return ORA_OK;
+}
+
+int ora_ssa(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t key,
+            uint32_t *seeds, ora_stats *st) {
+    double c[8];
+    int rc = ora_ssa_constants(g->n, k, eps, delta, c);
+    if (rc) return rc;
+    return ssa_run(g, k, c, key, seeds, st);
+}
+
+/* SSA with a caller's precision split (eps1, eps2, eps3) meeting Eq. 14.    */
+int ora_ssa_eps(const ora_graph *g, uint32_t k, double eps, double eps1, double eps2, double eps3,
+                double delta, uint64_t key, uint32_t *seeds, ora_stats *st) {
+    double c[8];
+    int rc = ora_ssa_constants_eps(g->n, k, eps, eps1, eps2, eps3, delta, c);
+    if (rc) return rc;
+    return ssa_run(g, k, c, key, seeds, st);
+}
+
+/* Fixed-threshold RIS: ceil(theta) RR sets of stream `key`, then one        */
+/* Max-Coverage over all of them. n_sets = ceil(theta), cov, i_hat.          */
+int ora_ris(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t key, uint32_t *seeds,
+            ora_stats *st) {
+    int rc = check_args(g->n, k, eps, delta);
+    if (rc) return rc;
+    const double theta = ora_ris_theta(g->n, k, eps, delta);
+    if (!(theta < 1e12)) return ORA_E_OOM;
+    const uint64_t count = (uint64_t)ceil(theta);
+    memset(st, 0, sizeof(*st));
+    st->i_c = -1.0;
+    ora_pool pool;
+    if (ora_pool_init(&pool, key)) return ORA_E_OOM;
+    if (ora_pool_extend(&pool, g, count)) {
+        ora_pool_free(&pool);
+        return ORA_E_OOM;
+    }
+    uint64_t cov = 0;
+    rc = ora_max_coverage(&pool, 0, count, g->n, k, seeds, &cov);
+    if (rc == ORA_OK) {
+        st->iterations = 1;
+        st->n_sets = count;
+        st->cov = cov;
+        st->i_hat = (double)g->n * (double)cov / (double)count;
+        st->edges = pool.edges;
+    }
+    ora_pool_free(&pool);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -132,6 +132,12 @@ double ora_upsilon(double eps, double delta);
 double ora_ln_choose(uint32_t n, uint32_t k);
 /* out[]: eps1, eps2, eps3, n_max, i_max, lambda, lambda1, delta2p */
 int ora_ssa_constants(uint32_t n, uint32_t k, double eps, double delta, double out[8]);
+int ora_ssa_constants_eps(uint32_t n, uint32_t k, double eps, double eps1, double eps2, double eps3,
+                          double delta, double out[8]);
+/* 1 when (eps1, eps2, eps3) meets Eq. 14 for eps */
+int ora_eps_admissible(double eps, double eps1, double eps2, double eps3);
+/* fixed RIS threshold (simplified bound with OPT_k >= k) */
+double ora_ris_theta(uint32_t n, uint32_t k, double eps, double delta);
 /* out[]: n_max, t_max, lambda, lambda1 */
 int ora_dssa_constants(uint32_t n, uint32_t k, double eps, double delta, double out[4]);
 
@@ -145,6 +151,10 @@ int ora_ssa(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t k
             uint32_t *seeds, ora_stats *st);
 int ora_dssa(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t key,
              uint32_t *seeds, ora_stats *st);
+int ora_ssa_eps(const ora_graph *g, uint32_t k, double eps, double eps1, double eps2, double eps3,
+                double delta, uint64_t key, uint32_t *seeds, ora_stats *st);
+int ora_ris(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t key, uint32_t *seeds,
+            ora_stats *st);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ CANDIDATES = {
     "greedy_wg_max_entries": [0, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 62],
     "ic_ticket_block": [0, 1, 2, 4, 8, 16, 32],
     "dssa_speculate": [0, 1],
+    "greedy_mark_min_chunks": [0, 1 << 14, 1 << 16, 1 << 62],
 }
 
 

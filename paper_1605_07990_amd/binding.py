@@ -30,11 +30,16 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_pool_device", "im_max_coverage", "im_max_coverage_range", "im_coverage_range", "im_estimate_inf",
            "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing",
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
-           "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param"]
+           "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param", "im_ssa_eps",
+           "im_ssa_eps_preset", "im_ris_theta", "im_ris"]
+
+IM_NET_SMALL, IM_NET_MODERATE, IM_NET_LARGE = 0, 1, 2
+REGIMES = {"small": IM_NET_SMALL, "moderate": IM_NET_MODERATE, "large": IM_NET_LARGE}
 
 IM_PARAM_GREEDY_WG_MAX_ENTRIES, IM_PARAM_IC_TICKET_BLOCK, IM_PARAM_DSSA_SPECULATE = 0, 1, 2
+IM_PARAM_GREEDY_MARK_MIN_CHUNKS = 3
 PARAMS = {"greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK,
-          "dssa_speculate": IM_PARAM_DSSA_SPECULATE}
+          "dssa_speculate": IM_PARAM_DSSA_SPECULATE, "greedy_mark_min_chunks": IM_PARAM_GREEDY_MARK_MIN_CHUNKS}
 
 IM_ALGO_SSA, IM_ALGO_DSSA = 0, 1
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}
@@ -139,6 +144,12 @@ def load_library(path: Path | str | None = None):
                         u32p, ctypes.POINTER(Stats)]),
         "im_dssa": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                          u32p, ctypes.POINTER(Stats)]),
+        "im_ssa_eps": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_double, ctypes.c_uint64, u32p, ctypes.POINTER(Stats)]),
+        "im_ssa_eps_preset": (st, [ctypes.c_int, ctypes.c_double, f64p]),
+        "im_ris_theta": (ctypes.c_double, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_double]),
+        "im_ris": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                        u32p, ctypes.POINTER(Stats)]),
         "im_derived_key": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
         "im_last_error": (ctypes.c_char_p, []),
         "im_ctx_set_timing": (st, [vp, ctypes.c_int]),
@@ -325,6 +336,18 @@ class Graph:
     def dssa(self, model, k, eps, delta, key):
         return self._run(load_library().im_dssa, model, k, eps, delta, key)
 
+    def ris(self, model, k, eps, delta, key):
+        """Fixed-threshold RIS (ceil(ris_theta) RR sets, one greedy)."""
+        return self._run(load_library().im_ris, model, k, eps, delta, key)
+
+    def ssa_eps(self, model, k, eps, eps1, eps2, eps3, delta, key):
+        """SSA with a precision split meeting Eq. 14 (see ssa_eps_preset)."""
+        seeds = np.zeros(k, dtype=np.uint32)
+        st = Stats()
+        _check(load_library().im_ssa_eps(self.h, MODELS[model], k, eps, eps1, eps2, eps3, delta, key,
+                                         seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st)))
+        return seeds, st.as_dict()
+
 
 class Pool:
     """im_pool: RR sets of one (graph, model, stream key)."""
@@ -449,6 +472,18 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+
+def ssa_eps_preset(regime, eps: float):
+    """(eps1, eps2, eps3) for a network-size regime ("small", "moderate",
+    "large"), meeting Eq. 14 with equality."""
+    out = (ctypes.c_double * 3)()
+    _check(load_library().im_ssa_eps_preset(REGIMES.get(regime, regime), eps, out))
+    return tuple(out)
+
+
+def ris_theta(n: int, k: int, eps: float, delta: float) -> float:
+    return float(load_library().im_ris_theta(n, k, eps, delta))
 
 
 def derived_key(key: int, i: int) -> int:

@@ -194,6 +194,7 @@ im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
     }
     a->timing = ctx->timing;
     a->greedy_wg_max_entries = ctx->greedy_wg_max_entries;
+    a->greedy_mark_min_chunks = ctx->greedy_mark_min_chunks;
     a->ic_ticket_block = ctx->ic_ticket_block;
     *out = a;
     return IM_OK;
@@ -317,6 +318,9 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 1) break;
         c->speculate = value != 0;
         return IM_OK;
+    case IM_PARAM_GREEDY_MARK_MIN_CHUNKS:
+        c->greedy_mark_min_chunks = value;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -334,6 +338,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_DSSA_SPECULATE:
         *value = c->speculate ? 1 : 0;
+        return IM_OK;
+    case IM_PARAM_GREEDY_MARK_MIN_CHUNKS:
+        *value = c->greedy_mark_min_chunks;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
@@ -568,19 +575,25 @@ extern "C" const char *im_last_error(void) { return g_err; }
 
 // ------------------------------------------------------- SSA / D-SSA ----
 
-extern "C" im_status im_ssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
-                            uint32_t *seeds_out, im_stats *st) {
-    clear_error();
-    IM_TRY(check_query(g, model, k, eps, delta));
-    if (!seeds_out || !st) return IM_E_ARG;
+// Eq. 14: a caller's split needs every eps_i in (0, 1) and
+// (1-1/e)(eps1 + eps2 + eps1 eps2 + eps3) / ((1+eps1)(1+eps2)) <= eps
+// (relative slack 1e-12, so that a split meeting it with equality passes).
+static double eq14_lhs(double eps1, double eps2, double eps3) {
+    const double one_m = 1.0 - std::exp(-1.0);
+    return one_m * (eps1 + eps2 + eps1 * eps2 + eps3) / ((1.0 + eps1) * (1.0 + eps2));
+}
+
+static bool eq14_ok(double eps, double eps1, double eps2, double eps3) {
+    return eps1 > 0.0 && eps1 < 1.0 && eps2 > 0.0 && eps2 < 1.0 && eps3 > 0.0 && eps3 < 1.0 &&
+           eq14_lhs(eps1, eps2, eps3) <= eps * (1.0 + 1e-12);
+}
+
+// SSA (Algorithm 1) with a given precision split.
+static im_status ssa_run(const im_graph *g, im_model model, uint32_t k, double eps, double eps1, double eps2,
+                         double eps3, double delta, uint64_t key, uint32_t *seeds_out, im_stats *st) {
     const double t_start = now_ms();
     std::memset(st, 0, sizeof(*st));
     st->i_c = -1.0;
-    const double one_m = 1.0 - std::exp(-1.0);
-    // Eq. 15 defaults
-    const double eps2 = eps / (2.0 * one_m);
-    const double eps3 = eps2;
-    const double eps1 = (1.0 + eps / (2.0 * (one_m - eps))) / (1.0 + eps2) - 1.0;
     const Caps c = caps(g->n, k, eps, delta);
     const double lambda1 = (1.0 + eps1) * (1.0 + eps2) * upsilon(eps3, delta / (3.0 * c.i_max));
     const double delta2p = delta / (3.0 * c.i_max);
@@ -642,6 +655,108 @@ extern "C" im_status im_ssa(const im_graph *g, im_model model, uint32_t k, doubl
         st->eps3 = eps3;
         st->edges += pool->edges;
         std::memcpy(seeds_out, seeds.data(), 4ull * k);
+    }
+    im_pool_free(pool);
+    st->ms_total = now_ms() - t_start;
+    return rc;
+}
+
+extern "C" im_status im_ssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                            uint32_t *seeds_out, im_stats *st) {
+    clear_error();
+    IM_TRY(check_query(g, model, k, eps, delta));
+    if (!seeds_out || !st) return IM_E_ARG;
+    // Eq. 15 defaults
+    const double one_m = 1.0 - std::exp(-1.0);
+    const double eps2 = eps / (2.0 * one_m);
+    const double eps3 = eps2;
+    const double eps1 = (1.0 + eps / (2.0 * (one_m - eps))) / (1.0 + eps2) - 1.0;
+    return ssa_run(g, model, k, eps, eps1, eps2, eps3, delta, key, seeds_out, st);
+}
+
+extern "C" im_status im_ssa_eps(const im_graph *g, im_model model, uint32_t k, double eps, double eps1, double eps2,
+                                double eps3, double delta, uint64_t key, uint32_t *seeds_out, im_stats *st) {
+    clear_error();
+    IM_TRY(check_query(g, model, k, eps, delta));
+    if (!seeds_out || !st) return IM_E_ARG;
+    if (!eq14_ok(eps, eps1, eps2, eps3)) {
+        set_error("im_ssa_eps: (%g, %g, %g) does not meet Eq. 14 for eps = %g", eps1, eps2, eps3, eps);
+        return IM_E_ARG;
+    }
+    return ssa_run(g, model, k, eps, eps1, eps2, eps3, delta, key, seeds_out, st);
+}
+
+extern "C" im_status im_ssa_eps_preset(int regime, double eps, double *out) {
+    clear_error();
+    // eps1 = a x, eps2 = eps3 = x, with x the largest value meeting Eq. 14
+    double a = 0.0;
+    switch (regime) {
+    case IM_NET_SMALL: a = 2.0; break;
+    case IM_NET_MODERATE: a = 1.0; break;
+    case IM_NET_LARGE: a = 0.125; break;
+    default: break;
+    }
+    if (!out || a == 0.0 || !(eps > 0.0 && eps < 1.0 - std::exp(-1.0))) {
+        set_error("im_ssa_eps_preset: bad regime %d or eps %g", regime, eps);
+        return IM_E_ARG;
+    }
+    double lo = 0.0, hi = std::min(1.0, 1.0 / a) * (1.0 - 1e-9);
+    if (eq14_lhs(a * hi, hi, hi) <= eps) {
+        lo = hi;
+    } else {
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (eq14_lhs(a * mid, mid, mid) <= eps) lo = mid;
+            else hi = mid;
+        }
+    }
+    if (!eq14_ok(eps, a * lo, lo, lo)) {
+        set_error("im_ssa_eps_preset: no admissible split");
+        return IM_E_ARG;
+    }
+    out[0] = a * lo;
+    out[1] = lo;
+    out[2] = lo;
+    return IM_OK;
+}
+
+extern "C" double im_ris_theta(uint32_t n, uint32_t k, double eps, double delta) {
+    const double one_m = 1.0 - std::exp(-1.0);
+    return 8.0 * one_m * (std::log(2.0 / delta) + ln_choose(n, k)) / (eps * eps) * double(n) / double(k);
+}
+
+extern "C" im_status im_ris(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
+                            uint32_t *seeds_out, im_stats *st) {
+    clear_error();
+    IM_TRY(check_query(g, model, k, eps, delta));
+    if (!seeds_out || !st) return IM_E_ARG;
+    const double theta = im_ris_theta(g->n, k, eps, delta);
+    if (!(theta < 4.0e12)) {
+        set_error("im_ris: theta = %g RR sets", theta);
+        return IM_E_OOM;
+    }
+    const double t_start = now_ms();
+    std::memset(st, 0, sizeof(*st));
+    st->i_c = -1.0;
+    const uint64_t count = uint64_t(std::ceil(theta));
+    im_pool *pool = nullptr;
+    IM_TRY(im_pool_create(g->ctx, g, model, key, &pool));
+    im_status rc = pool_extend_to(pool, count, &st->ms_sample);
+    uint64_t cov = 0;
+    if (rc == IM_OK) {
+        const double t0 = now_ms();
+        rc = max_coverage(pool, 0, count, k, seeds_out, &cov);
+        st->ms_cover = now_ms() - t0;
+    }
+    if (rc == IM_OK) {
+        st->iterations = 1;
+        st->n_sets = count;
+        st->cov = cov;
+        st->i_hat = double(g->n) * double(cov) / double(count);
+        st->edges = pool->edges;
+        st->it_sets[0] = count;
+        st->it_cov[0] = cov;
+        st->it_eps_t[0] = -1.0;
     }
     im_pool_free(pool);
     st->ms_total = now_ms() - t_start;

@@ -149,9 +149,10 @@ struct GreedyState {
     uint32_t *pick;  // the current round's seed
     uint32_t *done;  // blocks of the current refresh that finished
     unsigned long long *cov;
-    uint32_t *dirty;  // one-workgroup rounds: chunk bitmap (n1 bits), zeroed
+    uint32_t *dirty;  // chunks whose m1 must be re-derived: bitmap (n1 bits), zeroed
     uint64_t nsets;   // sets in the range
     unsigned long long *bmax;  // per-round launches: each refresh block's largest key
+    uint32_t mark;             // per-round launches: cover marks touched chunks in `dirty` (large n)
 };
 
 // Load flavours. State written by earlier kernels is read with plain loads.
@@ -308,9 +309,20 @@ __device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long 
 __device__ __forceinline__ void refresh_choose(const GreedyState &g, uint32_t r, uint32_t blk, uint32_t nblk,
                                                unsigned long long *smem, uint32_t *s_pick, bool *s_last) {
     unsigned long long best = 0;
+    // 32 consecutive chunks share a dirty word and are read by 32 consecutive
+    // lanes of one wave; the word's first lane clears it once it has the value
     for (uint32_t c = blk * blockDim.x + threadIdx.x; c < g.n1; c += nblk * blockDim.x) {
         unsigned long long m = g.m1[c];
-        if (r > 0 && m != 0ull && node_key<false>(g.gain, ~static_cast<uint32_t>(m)) != m) {
+        if (r > 0 && g.mark) {
+            // re-derive the chunks whose nodes lost gain
+            const uint32_t word = g.dirty[c >> 5];
+            if ((word >> (c & 31u)) & 1u) {
+                m = m1_lane<false>(g, c);
+                g.m1[c] = m;
+            }
+            if ((c & 31u) == 0 && word != 0u) g.dirty[c >> 5] = 0u;
+        } else if (r > 0 && m != 0ull && node_key<false>(g.gain, ~static_cast<uint32_t>(m)) != m) {
+            // re-derive the chunks whose maximum holder lost gain
             m = m1_lane<false>(g, c);
             g.m1[c] = m;
         }
@@ -332,6 +344,8 @@ __device__ __forceinline__ void refresh_choose(const GreedyState &g, uint32_t r,
     best = block_max_u64(best, smem);
     const uint32_t v = choose_key(g, r, best, s_pick);
     if (threadIdx.x == 0) {
+        const uint32_t c = v >> kL1Shift;
+        if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));  // the seed's key is now 0
         *g.pick = v;
         *g.done = 0u;
     }
@@ -364,7 +378,12 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g) {
         if (fresh) {
             if (sub == 0) ++newly;
             const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
-            for (uint64_t q = sa + sub; q < sb; q += 16) atomicSub(&g.gain[g.pnodes[q]], 1u);
+            for (uint64_t q = sa + sub; q < sb; q += 16) {
+                const uint32_t u = g.pnodes[q];
+                const uint32_t c = u >> kL1Shift;
+                atomicSub(&g.gain[u], 1u);
+                if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
+            }
         }
     }
     newly = wave_sum_u64(newly);
@@ -401,7 +420,12 @@ __global__ __launch_bounds__(kThreads) void batch_cover_kernel(const GreedyState
         if (fresh) {
             if (sub == 0) ++newly;
             const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
-            for (uint64_t q = sa + sub; q < sb; q += 16) atomicSub(&g.gain[g.pnodes[q]], 1u);
+            for (uint64_t q = sa + sub; q < sb; q += 16) {
+                const uint32_t u = g.pnodes[q];
+                const uint32_t c = u >> kL1Shift;
+                atomicSub(&g.gain[u], 1u);
+                if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
+            }
         }
     }
     newly = wave_sum_u64(newly);
@@ -886,6 +910,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     g.dirty = at32(o_dirty);
     g.nsets = nsets;
     g.bmax = reinterpret_cast<unsigned long long *>(base + o_bmax);
+    g.mark = n1 > ctx->greedy_mark_min_chunks ? 1u : 0u;
 
     hipStream_t st = ctx->stream;
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
@@ -913,6 +938,8 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const uint32_t cgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
     const uint32_t rgrid = grid_of(uint64_t(n1), kThreads, cu * 4);
     fill_u32_kernel<<<1, 64, 0, st>>>(g.done, 1, 0u);
+    if (big)
+        fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
     for (uint32_t r = 0; r < big; ++r) {
         refresh_choose_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
         cover_kernel<<<cgrid, kThreads, 0, st>>>(g);
@@ -1051,6 +1078,7 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.pick = reinterpret_cast<uint32_t *>(base + o_pd) + 2ull * j;
         g.done = g.pick + 1;
         g.bmax = reinterpret_cast<unsigned long long *>(base + o_bmax) + 1024ull * j;
+        g.mark = n1 > ctx->greedy_mark_min_chunks ? 1u : 0u;
         g.cov = covs + j;
         g.dirty = reinterpret_cast<uint32_t *>(base + o_dirty) + uint64_t(j) * ((n1 + 31) / 32);
         g.nsets = cj.end - cj.begin;

@@ -71,6 +71,7 @@ struct im_ctx {
     // launch parameters (im_param)
     uint64_t greedy_wg_max_entries = 1u << 16;
     uint32_t ic_ticket_block = 0;  // 0: automatic
+    uint64_t greedy_mark_min_chunks = 1u << 16;
 
     // optional event timing of the main sampler launches
     bool timing = false;

@@ -52,3 +52,30 @@ def test_derived_key_matches_oracle(oracle_lib):
     for key in (0, 1, 2**63 + 5):
         for i in (1, 2, 17, 2**40):
             assert binding.derived_key(key, i) == oracle_lib.derived_key(key, i)
+
+
+def test_eps_presets_and_theta_host_only():
+    """Host-only entry points (no device work): the presets meet Eq. 14 with
+    equality and keep Section 4.2's orderings; the fixed RIS threshold
+    equals the oracle's."""
+    import math
+
+    import oracle
+    from paper_1605_07990_amd import binding as im
+
+    one_m = 1 - 1 / math.e
+    for eps in (0.05, 0.1, 0.2, 0.3):
+        splits = {r: im.ssa_eps_preset(r, eps) for r in ("small", "moderate", "large")}
+        for e1, e2, e3 in splits.values():
+            assert 0 < e1 < 1 and 0 < e2 < 1 and 0 < e3 < 1
+            lhs = one_m * (e1 + e2 + e1 * e2 + e3) / ((1 + e1) * (1 + e2))
+            assert lhs == pytest.approx(eps, rel=1e-9)
+            assert oracle.eps_admissible(eps, e1, e2, e3)
+        s, m, l = splits["small"], splits["moderate"], splits["large"]
+        assert s[0] > s[1] == s[2]
+        assert m[0] == m[1] == m[2]
+        assert l[0] < l[1] / 4 and l[1] == l[2]
+    with pytest.raises(im.ImError):
+        im.ssa_eps_preset("moderate", 0.7)
+    for args in ((15233, 50, 0.1, 1 / 15233), (1 << 20, 100, 0.1, 2 ** -20), (50, 50, 0.2, 0.1)):
+        assert im.ris_theta(*args) == pytest.approx(oracle.ris_theta(*args), rel=1e-12)

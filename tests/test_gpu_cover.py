@@ -110,22 +110,25 @@ def test_estimate_inf_matches_oracle(im, ctx, oracle_lib, name, model):
     assert T == math.ceil(lam2)
 
 
-@pytest.mark.parametrize("limit", [0, 1 << 62])
+@pytest.mark.parametrize("limit,mark", [(0, 1 << 62), (0, 0), (1 << 62, 1 << 62)])
 @pytest.mark.parametrize("name", ["nethept", "rmat16", "cl_small"])
-def test_greedy_paths_agree(im, ctx, pools, name, limit):
-    """Both greedy schedules (per-round grid launches, all rounds in one
-    workgroup) give the oracle's seeds, whatever the size threshold."""
+def test_greedy_paths_agree(im, ctx, pools, name, limit, mark):
+    """Every greedy schedule (per-round grid launches re-checking holders or
+    re-deriving marked chunks, all rounds in one workgroup) gives the
+    oracle's seeds."""
     g, dg, og, p, op = pools[name]
-    note(f"greedy path limit={limit} {name}")
-    old = ctx.get_param("greedy_wg_max_entries")
+    note(f"greedy path limit={limit} mark={mark} {name}")
+    old = ctx.get_param("greedy_wg_max_entries"), ctx.get_param("greedy_mark_min_chunks")
     ctx.set_param("greedy_wg_max_entries", limit)
+    ctx.set_param("greedy_mark_min_chunks", mark)
     try:
         for k in (1, 50, 300):
             seeds, cov = p.max_coverage(k)
             oseeds, ocov = op.max_coverage(k)
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
     finally:
-        ctx.set_param("greedy_wg_max_entries", old)
+        ctx.set_param("greedy_wg_max_entries", old[0])
+        ctx.set_param("greedy_mark_min_chunks", old[1])
 
 
 def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):

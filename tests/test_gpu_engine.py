@@ -90,18 +90,22 @@ def _engine(im, ctx, graphs, cases, budget=16 << 30, max_active=64):
     return res, steps
 
 
-@pytest.mark.parametrize("limit", [None, 0, 1 << 62])
-def test_engine_mix_matches_single(im, ctx, graphs, limit):
+@pytest.mark.parametrize("limit,mark", [(None, None), (0, None), (0, 0), (1 << 62, None)])
+def test_engine_mix_matches_single(im, ctx, graphs, limit, mark):
     """limit: the one-workgroup greedy threshold (None = default; 0 forces
-    the batched per-round launches, 2^62 one workgroup per job)."""
-    note(f"engine mix of {len(MIX)} queries vs single-query runs, greedy limit {limit}")
-    old = ctx.get_param("greedy_wg_max_entries")
+    the batched per-round launches, 2^62 one workgroup per job); mark: the
+    chunk count above which the cover step marks touched chunks (0: always)."""
+    note(f"engine mix of {len(MIX)} queries vs single-query runs, greedy limit {limit} mark {mark}")
+    old = ctx.get_param("greedy_wg_max_entries"), ctx.get_param("greedy_mark_min_chunks")
     if limit is not None:
         ctx.set_param("greedy_wg_max_entries", limit)
+    if mark is not None:
+        ctx.set_param("greedy_mark_min_chunks", mark)
     try:
         res, _ = _engine(im, ctx, graphs, MIX)
     finally:
-        ctx.set_param("greedy_wg_max_entries", old)
+        ctx.set_param("greedy_wg_max_entries", old[0])
+        ctx.set_param("greedy_mark_min_chunks", old[1])
     for case, r in zip(MIX, res):
         note(f"compare {case}")
         _same(r, _single(graphs, case))
