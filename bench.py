@@ -338,7 +338,15 @@ def run_serving(args, im, ctx, sync):
     ctx.set_timing(True)
     ctx.read_timing(reset=True)
     sync()
-    r = serve.serve(eng, graphs, reqs)
+    last = [0.0]
+
+    def progress(done, total, active):
+        now = time.perf_counter()
+        if now - last[0] > 5.0 or done == total:
+            last[0] = now
+            print(f"[serve] {done}/{total} done, {active} active", file=sys.stderr, flush=True)
+
+    r = serve.serve(eng, graphs, reqs, progress=progress)
     sync()
     kt = ctx.read_timing(reset=True)
     ctx.set_timing(False)

@@ -152,6 +152,7 @@ struct GreedyState {
     uint32_t *dirty;  // chunks whose m1 must be re-derived: bitmap (n1 bits), zeroed
     uint64_t nsets;   // sets in the range
     unsigned long long *bmax;  // per-round launches: each refresh block's largest key
+    uint32_t nbmax;            // per-round launches: refresh blocks
     uint32_t mark;             // per-round launches: cover marks touched chunks in `dirty` (large n)
 };
 
@@ -266,17 +267,16 @@ __global__ __launch_bounds__(kThreads) void init_m2_kernel(GreedyState g) {
 // node, or, when every remaining gain is zero, the lowest id not yet chosen
 // (at most r, since only r nodes are chosen).
 // The seed of round r given the largest key `best` (all threads of one
-// block): that key's node, or, when every remaining gain is zero, the lowest
-// id not yet chosen (at most r, since only r nodes are chosen).
+// block). An unchosen node with no gain left still has key ~v, so when every
+// gain is zero the largest key names the lowest unchosen id, as Algorithm
+// 2's argmax is read here; best is 0 only if every node is chosen, which
+// k <= n rules out (the scan over the chosen bits is kept for safety).
 __device__ uint32_t choose_key(const GreedyState &g, uint32_t r, unsigned long long best, uint32_t *s_pick) {
-    if ((best >> 32) == 0) {
+    if (best == 0ull) {
         if (threadIdx.x == 0) *s_pick = 0xFFFFFFFFu;
         __syncthreads();
-        for (uint32_t v = threadIdx.x; v <= r; v += blockDim.x) {
-            bool taken = false;
-            for (uint32_t q = 0; q < r; ++q) taken |= (ld<true>(g.seeds + q) == v);
-            if (!taken) atomicMin(s_pick, v);
-        }
+        for (uint32_t v = threadIdx.x; v < g.n; v += blockDim.x)
+            if (!(ld<true>(g.gain + v) & kChosen)) atomicMin(s_pick, v);
     } else if (threadIdx.x == 0) {
         *s_pick = ~static_cast<uint32_t>(best & 0xFFFFFFFFull);
     }
@@ -302,12 +302,11 @@ __device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long 
     return choose_key(g, r, best, s_pick);
 }
 
-// Round step 1 body (grid-wide over one job's blocks): re-validate m1 and
-// take each block's largest key; the last block to finish (release fence +
-// counter on the writers' side, acquire fence on its side) takes the largest
-// of those and chooses the round's seed.
-__device__ __forceinline__ void refresh_choose(const GreedyState &g, uint32_t r, uint32_t blk, uint32_t nblk,
-                                               unsigned long long *smem, uint32_t *s_pick, bool *s_last) {
+// Round step 1 body (grid-wide over one job's blocks): re-derive stale m1
+// entries and record each block's largest key in bmax[blk]. No block waits
+// for another: the next launch reads bmax.
+__device__ __forceinline__ void refresh_block(const GreedyState &g, uint32_t r, uint32_t blk, uint32_t nblk,
+                                              unsigned long long *smem) {
     unsigned long long best = 0;
     // 32 consecutive chunks share a dirty word and are read by 32 consecutive
     // lanes of one wave; the word's first lane clears it once it has the value
@@ -330,42 +329,40 @@ __device__ __forceinline__ void refresh_choose(const GreedyState &g, uint32_t r,
     }
     best = block_max_u64(best, smem);
     if (threadIdx.x == 0) g.bmax[blk] = best;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) *s_last = atomicAdd(g.done, 1u) == nblk - 1;
-    __syncthreads();
-    if (!*s_last) return;
-    __threadfence();
-    best = 0;
-    for (uint32_t i = threadIdx.x; i < nblk; i += blockDim.x) {
+}
+
+// Round step 2 body (grid-wide over one job's blocks): every block takes the
+// largest of the refresh blocks' maxima, so all agree on seed r without
+// waiting for one another; block 0 records it. Then the seed's sets are
+// covered, 16 lanes per incidence entry.
+__device__ __forceinline__ void cover_block(const GreedyState &g, uint32_t r, uint32_t blk, uint32_t nblk,
+                                            unsigned long long *smem, uint32_t *s_pick) {
+    unsigned long long best = 0;
+    for (uint32_t i = threadIdx.x; i < g.nbmax; i += blockDim.x) {
         const unsigned long long m = g.bmax[i];
         best = m > best ? m : best;
     }
     best = block_max_u64(best, smem);
-    const uint32_t v = choose_key(g, r, best, s_pick);
-    if (threadIdx.x == 0) {
+    if (best == 0ull) {  // every node chosen: cannot happen for k <= n, kept for safety
+        if (threadIdx.x == 0) *s_pick = 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t v = threadIdx.x; v < g.n; v += blockDim.x)
+            if (!(g.gain[v] & kChosen)) atomicMin(s_pick, v);
+    } else if (threadIdx.x == 0) {
+        *s_pick = ~static_cast<uint32_t>(best & 0xFFFFFFFFull);
+    }
+    __syncthreads();
+    const uint32_t v = *s_pick;
+    if (blk == 0 && threadIdx.x == 0) {
+        g.seeds[r] = v;
+        atomicOr(&g.gain[v], kChosen);
         const uint32_t c = v >> kL1Shift;
         if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));  // the seed's key is now 0
-        *g.pick = v;
-        *g.done = 0u;
     }
-}
-
-// Round step 1 (grid-wide).
-__global__ __launch_bounds__(kThreads) void refresh_choose_kernel(GreedyState g, uint32_t r) {
-    __shared__ unsigned long long smem[kThreads / kWave];
-    __shared__ uint32_t s_pick;
-    __shared__ bool s_last;
-    refresh_choose(g, r, blockIdx.x, gridDim.x, smem, &s_pick, &s_last);
-}
-
-// Round step 3 (grid-wide): cover the seed's sets, 16 lanes per incidence entry.
-__global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g) {
-    const uint32_t v = *g.pick;
     const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
     const uint32_t sub = threadIdx.x & 15u;
-    const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
-    const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    const uint64_t grp = (static_cast<uint64_t>(blk) * blockDim.x + threadIdx.x) >> 4;
+    const uint64_t ngrp = (static_cast<uint64_t>(nblk) * blockDim.x) >> 4;
     unsigned long long newly = 0;
     for (uint64_t i = a + grp; i < b; i += ngrp) {
         const uint32_t j = g.isets[i];
@@ -388,48 +385,35 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g) {
     }
     newly = wave_sum_u64(newly);
     if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+}
+
+// Round r, step 1 (grid-wide).
+__global__ __launch_bounds__(kThreads) void refresh_kernel(GreedyState g, uint32_t r) {
+    __shared__ unsigned long long smem[kThreads / kWave];
+    refresh_block(g, r, blockIdx.x, gridDim.x, smem);
+}
+
+// Round r, step 2 (grid-wide).
+__global__ __launch_bounds__(kThreads) void cover_kernel(GreedyState g, uint32_t r) {
+    __shared__ unsigned long long smem[kThreads / kWave];
+    __shared__ uint32_t s_pick;
+    cover_block(g, r, blockIdx.x, gridDim.x, smem, &s_pick);
 }
 
 // Batched rounds: blockIdx.y is the job; jobs whose k is reached idle.
-__global__ __launch_bounds__(kThreads) void batch_refresh_choose_kernel(const GreedyState *jobs, uint32_t r) {
+__global__ __launch_bounds__(kThreads) void batch_refresh_kernel(const GreedyState *jobs, uint32_t r) {
     __shared__ unsigned long long smem[kThreads / kWave];
-    __shared__ uint32_t s_pick;
-    __shared__ bool s_last;
     const GreedyState &g = jobs[blockIdx.y];
     if (r >= g.k) return;
-    refresh_choose(g, r, blockIdx.x, gridDim.x, smem, &s_pick, &s_last);
+    refresh_block(g, r, blockIdx.x, gridDim.x, smem);
 }
 
 __global__ __launch_bounds__(kThreads) void batch_cover_kernel(const GreedyState *jobs, uint32_t r) {
+    __shared__ unsigned long long smem[kThreads / kWave];
+    __shared__ uint32_t s_pick;
     const GreedyState &g = jobs[blockIdx.y];
     if (r >= g.k) return;
-    const uint32_t v = *g.pick;
-    const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
-    const uint32_t sub = threadIdx.x & 15u;
-    const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
-    const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
-    unsigned long long newly = 0;
-    for (uint64_t i = a + grp; i < b; i += ngrp) {
-        const uint32_t j = g.isets[i];
-        uint32_t fresh = 0;
-        if (sub == 0) {
-            const uint32_t bit = 1u << (j & 31u);
-            fresh = (atomicOr(&g.covbits[j >> 5], bit) & bit) ? 0u : 1u;
-        }
-        fresh = __shfl(fresh, static_cast<int>(lane_id() & ~15u), kWave);
-        if (fresh) {
-            if (sub == 0) ++newly;
-            const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
-            for (uint64_t q = sa + sub; q < sb; q += 16) {
-                const uint32_t u = g.pnodes[q];
-                const uint32_t c = u >> kL1Shift;
-                atomicSub(&g.gain[u], 1u);
-                if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
-            }
-        }
-    }
-    newly = wave_sum_u64(newly);
-    if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+    cover_block(g, r, blockIdx.x, gridDim.x, smem, &s_pick);
 }
 
 // LDS of the one-workgroup rounds.
@@ -940,9 +924,10 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     fill_u32_kernel<<<1, 64, 0, st>>>(g.done, 1, 0u);
     if (big)
         fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
+    g.nbmax = rgrid;
     for (uint32_t r = 0; r < big; ++r) {
-        refresh_choose_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
-        cover_kernel<<<cgrid, kThreads, 0, st>>>(g);
+        refresh_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
+        cover_kernel<<<cgrid, kThreads, 0, st>>>(g, r);
     }
     if (big < k) {
         fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
@@ -974,6 +959,16 @@ im_status first_crossing(im_ctx *ctx, uint64_t count, uint64_t need, int64_t *in
     return IM_OK;
 }
 
+
+// Blocks per job of the batched round launches (at most 1024: bmax holds
+// 1024 entries per job), and of their refresh step.
+static uint32_t batch_blocks_per_job(uint32_t cu, uint32_t nj) {
+    return std::min<uint32_t>(1024, std::max<uint32_t>(1, (cu * 4 + nj - 1) / nj));
+}
+
+static uint32_t batch_refresh_blocks(uint32_t cu, uint32_t nj, uint32_t n1) {
+    return std::min<uint32_t>(batch_blocks_per_job(cu, nj), grid_of(uint64_t(n1), kThreads, cu * 4));
+}
 
 im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, uint32_t nj) {
     if (nj == 0) return IM_OK;
@@ -1078,6 +1073,7 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.pick = reinterpret_cast<uint32_t *>(base + o_pd) + 2ull * j;
         g.done = g.pick + 1;
         g.bmax = reinterpret_cast<unsigned long long *>(base + o_bmax) + 1024ull * j;
+        g.nbmax = batch_refresh_blocks(cu, nj, n1);
         g.mark = n1 > ctx->greedy_mark_min_chunks ? 1u : 0u;
         g.cov = covs + j;
         g.dirty = reinterpret_cast<uint32_t *>(base + o_dirty) + uint64_t(j) * ((n1 + 31) / 32);
@@ -1116,11 +1112,11 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
     } else {
         fill_u32_kernel<<<grid_of(2ull * nj, kThreads, cu), kThreads, 0, st>>>(
             reinterpret_cast<uint32_t *>(base + o_pd), 2ull * nj, 0u);
-        const uint32_t per = std::min<uint32_t>(1024, std::max<uint32_t>(1, (cu * 4 + nj - 1) / nj));
-        const uint32_t rx = std::min<uint32_t>(per, grid_of(uint64_t(n1), kThreads, cu * 4));
+        const uint32_t per = batch_blocks_per_job(cu, nj);
+        const uint32_t rx = batch_refresh_blocks(cu, nj, n1);
         const uint32_t cx = std::min<uint32_t>(per, std::max<uint32_t>(1, grid_of(max_entries * 16, kThreads, cu * 4)));
         for (uint32_t r = 0; r < max_k; ++r) {
-            batch_refresh_choose_kernel<<<dim3(rx, nj), kThreads, 0, st>>>(dgs, r);
+            batch_refresh_kernel<<<dim3(rx, nj), kThreads, 0, st>>>(dgs, r);
             batch_cover_kernel<<<dim3(cx, nj), kThreads, 0, st>>>(dgs, r);
         }
     }

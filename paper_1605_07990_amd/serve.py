@@ -67,12 +67,15 @@ def percentile(xs, q):
     return xs[i]
 
 
-def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_results: bool = False) -> dict:
+def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_results: bool = False,
+          progress=None) -> dict:
     """Replay `requests` against the wall clock through `engine`.
 
     graphs: {name: binding.Graph} resident on the engine's context.
     Returns latency percentiles (arrival to result), throughput and, with
     keep_results, every request's (seeds, stats) in request order.
+    progress(done, total, active) is called after every engine step that
+    finished a query.
     """
     reqs = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
     outstanding = {}  # ticket -> request index
@@ -101,7 +104,8 @@ def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_resul
         steps += 1
         max_active = max(max_active, active)
         done_at = time.perf_counter() - t0
-        for t in [t for t in outstanding if engine.poll(t) != 0]:
+        finished = [t for t in outstanding if engine.poll(t) != 0]
+        for t in finished:
             i = outstanding.pop(t)
             seeds, st = engine.result(t)
             latency[i] = (done_at - requests[i].arrival) * 1e3
@@ -109,6 +113,8 @@ def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_resul
             edges += st["edges"]
             if keep_results:
                 results[i] = (seeds, st)
+        if finished and progress is not None:
+            progress(len(requests) - len(outstanding) - (len(reqs) - nxt), len(requests), active)
     wall = time.perf_counter() - t0
     span = requests[reqs[-1]].arrival if reqs else 0.0
     out = {"queries": len(requests), "wall_s": wall, "arrival_span_s": span,
