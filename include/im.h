@@ -275,7 +275,7 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  * depend on them):
  *   IM_PARAM_GREEDY_WG_MAX_ENTRIES  a Max-Coverage range whose node entries
  *       are at most this runs all k rounds in one workgroup; a larger one
- *       launches grid-wide kernels every round (default 65536);
+ *       launches grid-wide kernels every round (default 0: always grid);
  *   IM_PARAM_IC_TICKET_BLOCK        consecutive samples an IC wave takes per
  *       ticket, 1..64, or 0 for the automatic choice (default 0);
  *   IM_PARAM_DSSA_SPECULATE         1: im_dssa draws the next iteration's

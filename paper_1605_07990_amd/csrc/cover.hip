@@ -146,8 +146,6 @@ struct GreedyState {
     uint64_t begin;
     uint32_t n, n1, n2, k;
     uint32_t *seeds;
-    uint32_t *pick;  // the current round's seed
-    uint32_t *done;  // blocks of the current refresh that finished
     unsigned long long *cov;
     uint32_t *dirty;  // chunks whose m1 must be re-derived: bitmap (n1 bits), zeroed
     uint64_t nsets;   // sets in the range
@@ -860,7 +858,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const size_t o_gain = take(4ull * n), o_fill = take(4ull * n), o_ioff = take(8ull * (n + 1)),
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
                  o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
-                 o_m2 = take(8ull * n2), o_cnt = take(16), o_job = take(sizeof(GreedyState)),
+                 o_m2 = take(8ull * n2), o_job = take(sizeof(GreedyState)),
                  o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
@@ -877,8 +875,6 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     g.gain = gain;
     g.m1 = reinterpret_cast<unsigned long long *>(base + o_m1);
     g.m2 = reinterpret_cast<unsigned long long *>(base + o_m2);
-    g.pick = at32(o_cnt);
-    g.done = at32(o_cnt) + 1;
     g.covbits = covbits;
     g.ioff = ioff;
     g.isets = isets;
@@ -921,7 +917,6 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const uint32_t big = small ? 0u : k;
     const uint32_t cgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
     const uint32_t rgrid = grid_of(uint64_t(n1), kThreads, cu * 4);
-    fill_u32_kernel<<<1, 64, 0, st>>>(g.done, 1, 0u);
     if (big)
         fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
     g.nbmax = rgrid;
@@ -1030,7 +1025,7 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
                  o_m1 = take(8ull * nj * n1), o_m2 = take(8ull * nj * n2), o_seeds = take(4 * (tot_seeds + 1)),
                  o_cov = take(8ull * nj), o_covc = take(8ull * nj), o_bits = take(4 * words * nj),
                  o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj),
-                 o_dirty = take(4ull * nj * ((n1 + 31) / 32)), o_pd = take(8ull * nj),
+                 o_dirty = take(4ull * nj * ((n1 + 31) / 32)),
                  o_bmax = take(8ull * nj * 1024);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
@@ -1070,8 +1065,6 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.n2 = n2;
         g.k = cj.k;
         g.seeds = seeds + jt[j].seed_start;
-        g.pick = reinterpret_cast<uint32_t *>(base + o_pd) + 2ull * j;
-        g.done = g.pick + 1;
         g.bmax = reinterpret_cast<unsigned long long *>(base + o_bmax) + 1024ull * j;
         g.nbmax = batch_refresh_blocks(cu, nj, n1);
         g.mark = n1 > ctx->greedy_mark_min_chunks ? 1u : 0u;
@@ -1110,8 +1103,6 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
     if (max_entries <= ctx->greedy_wg_max_entries) {
         persist_kernel<<<nj, kPersistThreads, 0, st>>>(dgs, 0);
     } else {
-        fill_u32_kernel<<<grid_of(2ull * nj, kThreads, cu), kThreads, 0, st>>>(
-            reinterpret_cast<uint32_t *>(base + o_pd), 2ull * nj, 0u);
         const uint32_t per = batch_blocks_per_job(cu, nj);
         const uint32_t rx = batch_refresh_blocks(cu, nj, n1);
         const uint32_t cx = std::min<uint32_t>(per, std::max<uint32_t>(1, grid_of(max_entries * 16, kThreads, cu * 4)));

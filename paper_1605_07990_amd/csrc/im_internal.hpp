@@ -69,7 +69,7 @@ struct im_ctx {
     void *host_pinned = nullptr;  // small pinned staging for read-backs
 
     // launch parameters (im_param)
-    uint64_t greedy_wg_max_entries = 1u << 16;
+    uint64_t greedy_wg_max_entries = 0;  // grid rounds measured faster at every size tried
     uint32_t ic_ticket_block = 0;  // 0: automatic
     uint64_t greedy_mark_min_chunks = 1u << 16;
 
