@@ -111,7 +111,7 @@ def roofline(kt: dict, model: int) -> dict:
         name = "lt_main_kernel (LT RR-set sampler)"
     else:
         total = ic_bytes(kt["sample_steps"], kt["sample_nodes"], kt["sample_sets"])
-        name = "ic_main_kernel (IC RR-set sampler)"
+        name = "ic_main_kernel + ic_group_kernel (IC RR-set sampler: wave pass and workgroup tier)"
     bytes_per_launch = total / launches
     ms_per_launch = kt["sample_ms"] / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
@@ -122,6 +122,10 @@ def roofline(kt: dict, model: int) -> dict:
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
            "sampler_sets_per_s": round(kt["sample_sets"] / sec) if sec else None,
            "sampler_steps_per_s": round(kt["sample_steps"] / sec) if sec else None}
+    if model == 0 and kt.get("group_launches"):
+        out["workgroup_tier"] = {"ms_per_launch": round(kt["group_ms"] / kt["group_launches"], 5),
+                                 "samples": kt["group_samples"], "edges": kt["group_edges"],
+                                 "mean_levels": round(kt["group_levels"] / max(kt["group_samples"], 1), 2)}
     if GATHER:
         # segment size of one gather: an LT step reads an 8-record threshold
         # window (64 B); an IC node its in-list (mean length x 8 B)

@@ -246,9 +246,10 @@ im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, dou
 
 /*
  * Kernel timing for measurement. When enabled on a context, every launch of
- * the main RR-set sampler kernel (the pass that draws the RR sets of
- * Definition 2 into staging) is bracketed by HIP events on the context's
- * stream; im_ctx_read_timing returns the totals since the last reset.
+ * the main RR-set sampler (the pass that draws the RR sets of Definition 2
+ * into staging: for IC the wave pass and its workgroup tier, for LT the
+ * lane pass) is bracketed by HIP events on the context's stream;
+ * im_ctx_read_timing returns the totals since the last reset.
  *   sample_launches  number of timed sampler launches
  *   sample_ms        sum of their event-measured durations
  *   sample_sets      RR sets those launches completed (deferred ones excluded)
@@ -256,6 +257,8 @@ im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, dou
  *                    whose in-list was consulted (walk steps)
  *   sample_nodes     node entries of the sets they completed
  *   model            model of the last timed launch (IM_IC or IM_LT)
+ * and the same for the IC workgroup tier launch that follows each IC one
+ * (samples are counted there, not in sample_sets).
  * Errors: IM_E_ARG (null handle), IM_E_DEVICE.
  */
 typedef struct im_kernel_times {
@@ -266,6 +269,13 @@ typedef struct im_kernel_times {
     uint64_t sample_nodes;
     int32_t model;
     int32_t reserved;
+    /* IC workgroup tier (samples a wave hands on): launches, event time,
+     * samples it finished, their examined edges and BFS levels */
+    uint64_t group_launches;
+    double group_ms;
+    uint64_t group_samples;
+    uint64_t group_edges;
+    uint64_t group_levels;
 } im_kernel_times;
 
 im_status im_ctx_set_timing(im_ctx *ctx, int enable);
@@ -315,7 +325,7 @@ im_status im_ctx_read_timing(im_ctx *ctx, im_kernel_times *out, int reset);
  * im_query: graph (loaded on the engine's context), model, algo, k, eps,
  * delta, key: the arguments of im_ssa / im_dssa.
  */
-typedef enum { IM_ALGO_SSA = 0, IM_ALGO_DSSA = 1 } im_algo;
+typedef enum { IM_ALGO_SSA = 0, IM_ALGO_DSSA = 1, IM_ALGO_ESTIMATE = 2 } im_algo;
 
 typedef struct im_query {
     const im_graph *graph;
@@ -347,6 +357,20 @@ void im_engine_free(im_engine *e);
  * of another context or an unknown algo.
  */
 im_status im_engine_submit(im_engine *e, const im_query *q, uint64_t *ticket);
+
+/*
+ * Queue an influence-estimate query: Estimate-Inf (Algorithm 3) of the seed
+ * set seeds[k] (copied) on stream `key`, exactly as im_estimate_inf, run in
+ * the engine's fused verification passes beside the other queries. Its
+ * result (im_engine_result) carries the seeds back, st->i_c = I_c (-1 when
+ * floor(t_max) sets did not reach Lambda2), st->cov_c = st->n_verify = T,
+ * st->edges. Errors: IM_E_ARG (k == 0, seed out of range, eps_p or delta_p
+ * outside (0,1), t_max < 0, graph of another context or without the
+ * model's weights).
+ */
+im_status im_engine_submit_estimate(im_engine *e, const im_graph *g, im_model model, const uint32_t *seeds,
+                                    uint32_t k, double eps_p, double delta_p, double t_max, uint64_t key,
+                                    uint64_t *ticket);
 
 /*
  * One engine step: admission, then the fused sampling, verification and

@@ -31,7 +31,7 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing",
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
            "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param", "im_ssa_eps",
-           "im_ssa_eps_preset", "im_ris_theta", "im_ris"]
+           "im_ssa_eps_preset", "im_ris_theta", "im_ris", "im_engine_submit_estimate"]
 
 IM_NET_SMALL, IM_NET_MODERATE, IM_NET_LARGE = 0, 1, 2
 REGIMES = {"small": IM_NET_SMALL, "moderate": IM_NET_MODERATE, "large": IM_NET_LARGE}
@@ -41,7 +41,7 @@ IM_PARAM_GREEDY_MARK_MIN_CHUNKS = 3
 PARAMS = {"greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK,
           "dssa_speculate": IM_PARAM_DSSA_SPECULATE, "greedy_mark_min_chunks": IM_PARAM_GREEDY_MARK_MIN_CHUNKS}
 
-IM_ALGO_SSA, IM_ALGO_DSSA = 0, 1
+IM_ALGO_SSA, IM_ALGO_DSSA, IM_ALGO_ESTIMATE = 0, 1, 2
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}
 
 
@@ -83,7 +83,10 @@ class Query(ctypes.Structure):
 class KernelTimes(ctypes.Structure):
     _fields_ = [("sample_launches", ctypes.c_uint64), ("sample_ms", ctypes.c_double),
                 ("sample_sets", ctypes.c_uint64), ("sample_steps", ctypes.c_uint64),
-                ("sample_nodes", ctypes.c_uint64), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sample_nodes", ctypes.c_uint64), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("group_launches", ctypes.c_uint64), ("group_ms", ctypes.c_double),
+                ("group_samples", ctypes.c_uint64), ("group_edges", ctypes.c_uint64),
+                ("group_levels", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -160,6 +163,8 @@ def load_library(path: Path | str | None = None):
         "im_engine_free": (None, [vp]),
         "im_engine_submit": (st, [vp, ctypes.POINTER(Query), u64p]),
         "im_engine_step": (st, [vp, u32p, u32p]),
+        "im_engine_submit_estimate": (st, [vp, vp, ctypes.c_int, u32p, ctypes.c_uint32, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_uint64, u64p]),
         "im_engine_run": (st, [vp]),
         "im_engine_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
         "im_engine_result": (st, [vp, ctypes.c_uint64, u32p, ctypes.POINTER(Stats)]),
@@ -434,6 +439,18 @@ class Engine:
         _check(load_library().im_engine_submit(self.h, ctypes.byref(q), ctypes.byref(t)))
         self._k[int(t.value)] = k
         self._graphs[int(t.value)] = graph  # keep the graph alive while the query is held
+        return int(t.value)
+
+    def submit_estimate(self, graph: Graph, model, seeds, eps_p: float, delta_p: float, t_max: float,
+                        key: int) -> int:
+        """Queue Estimate-Inf of a seed set; its result's stats carry
+        i_c (the estimate, -1 if t_max was reached) and cov_c (= T)."""
+        s, sp = _u32(seeds)
+        t = ctypes.c_uint64()
+        _check(load_library().im_engine_submit_estimate(self.h, graph.h, MODELS[model], sp, s.shape[0], eps_p,
+                                                        delta_p, t_max, key, ctypes.byref(t)))
+        self._k[int(t.value)] = int(s.shape[0])
+        self._graphs[int(t.value)] = graph
         return int(t.value)
 
     def step(self):

@@ -191,6 +191,7 @@ im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
     if (ctx->timing && !a->ev_begin) {
         IM_HIP(hipEventCreate(&a->ev_begin));
         IM_HIP(hipEventCreate(&a->ev_end));
+        IM_HIP(hipEventCreate(&a->ev_group));
     }
     a->timing = ctx->timing;
     a->greedy_wg_max_entries = ctx->greedy_wg_max_entries;
@@ -298,6 +299,7 @@ extern "C" im_status im_ctx_set_timing(im_ctx *c, int enable) {
     if (enable && !c->ev_begin) {
         IM_HIP(hipEventCreate(&c->ev_begin));
         IM_HIP(hipEventCreate(&c->ev_end));
+        IM_HIP(hipEventCreate(&c->ev_group));
     }
     c->timing = enable != 0;
     return IM_OK;
@@ -358,6 +360,11 @@ extern "C" im_status im_ctx_read_timing(im_ctx *c, im_kernel_times *out, int res
         out->sample_sets += a.sample_sets;
         out->sample_steps += a.sample_steps;
         out->sample_nodes += a.sample_nodes;
+        out->group_launches += a.group_launches;
+        out->group_ms += a.group_ms;
+        out->group_samples += a.group_samples;
+        out->group_edges += a.group_edges;
+        out->group_levels += a.group_levels;
         if (a.sample_launches) out->model = a.model;
         if (reset) c->aux->times = im_kernel_times{};
     }
@@ -371,6 +378,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
+    if (c->ev_group) (void)hipEventDestroy(c->ev_group);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits,
                       &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);

@@ -49,6 +49,8 @@ struct Query {
     // SSA Estimate-Inf progress
     uint64_t vkey = 0, vdone = 0, vcov = 0, vlast = 0, vneed = 0, vchunk = 0;
     double vhint = 0;
+    // influence-estimate queries (Algorithm 3 for a given seed set)
+    double est_eps = 0, est_delta = 0, est_tmax = 0;
     DevBuf vbits;
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -95,11 +97,34 @@ void finish(im_engine *e, Query *q, Phase ph, im_status err) {
         q->st.edges = (q->q.algo == IM_ALGO_SSA ? q->verify_edges : 0) + q->pool->edges;
         im_pool_free(q->pool);
         q->pool = nullptr;
+    } else if (q->q.algo == IM_ALGO_ESTIMATE) {
+        q->st.edges = q->verify_edges;
     }
     dev_free(e->ctx, q->vbits);
 }
 
+// An influence-estimate query goes straight to verification on its own
+// stream: samples 0, 1, 2, ... of `key` against its seed set.
+im_status admit_estimate(im_engine *e, Query *q) {
+    std::memset(&q->st, 0, sizeof(q->st));
+    q->st.i_c = -1.0;
+    q->lambda2 = 1.0 + (1.0 + q->est_eps) * upsilon(q->est_eps, q->est_delta);
+    q->vkey = q->q.key;
+    q->vdone = 0;
+    q->vcov = 0;
+    q->vlast = q->est_tmax >= 1.8e19 ? ~0ull : uint64_t(std::floor(q->est_tmax));
+    q->vneed = uint64_t(std::ceil(q->lambda2));
+    q->vhint = 16.0 * double(q->vneed);
+    q->vchunk = uint64_t(std::min(1.1 * q->vhint + 1024.0, 4.0e8));
+    IM_TRY(seed_bits_into(e->ctx, q->q.graph->n, q->seeds.data(), q->q.k, q->vbits));
+    q->phase = kVerify;
+    q->t_admit = now_ms();
+    if (q->vlast == 0) finish(e, q, kDone, IM_OK);  // nothing may be drawn: -1 with T = 0
+    return IM_OK;
+}
+
 im_status admit(im_engine *e, Query *q) {
+    if (q->q.algo == IM_ALGO_ESTIMATE) return admit_estimate(e, q);
     const im_graph *g = q->q.graph;
     const uint32_t n = g->n, k = q->q.k;
     const double eps = q->q.eps, delta = q->q.delta;
@@ -219,9 +244,17 @@ im_status after_cover_ssa(im_engine *e, Query *q, uint64_t cov) {
     return IM_OK;
 }
 
-// SSA after Estimate-Inf ended (ic = -1 when T_max was reached): C2.
+// SSA after Estimate-Inf ended (ic = -1 when T_max was reached): C2. An
+// influence-estimate query simply reports I_c and T.
 void after_verify_ssa(im_engine *e, Query *q, double ic, uint64_t T) {
     im_stats &st = q->st;
+    if (q->q.algo == IM_ALGO_ESTIMATE) {
+        st.n_verify = T;
+        st.cov_c = T;
+        st.i_c = ic;
+        finish(e, q, kDone, IM_OK);
+        return;
+    }
     const uint32_t t = q->t;
     st.n_verify += T;
     st.cov_c = T;
@@ -424,6 +457,46 @@ extern "C" im_status im_engine_submit(im_engine *e, const im_query *query, uint6
     if (!q) return IM_E_OOM;
     q->ticket = e->next_ticket++;
     q->q = *query;
+    q->t_submit = now_ms();
+    e->pending.push_back(q);
+    e->all[q->ticket] = q;
+    *ticket = q->ticket;
+    return IM_OK;
+}
+
+extern "C" im_status im_engine_submit_estimate(im_engine *e, const im_graph *g, im_model model,
+                                               const uint32_t *seeds, uint32_t k, double eps_p, double delta_p,
+                                               double t_max, uint64_t key, uint64_t *ticket) {
+    clear_error();
+    if (!e || !g || !seeds || !ticket || k == 0 || g->ctx != e->ctx) {
+        set_error("im_engine_submit_estimate: bad arguments");
+        return IM_E_ARG;
+    }
+    if (model != IM_IC && model != IM_LT) {
+        set_error("im_engine_submit_estimate: unknown model %d", int(model));
+        return IM_E_ARG;
+    }
+    if (!(g->models & (1u << model))) {
+        set_error("im_engine_submit_estimate: graph has no weights for model %d", int(model));
+        return IM_E_ARG;
+    }
+    if (!(eps_p > 0.0 && eps_p < 1.0 && delta_p > 0.0 && delta_p < 1.0 && t_max >= 0.0)) {
+        set_error("im_engine_submit_estimate: eps_p, delta_p must be in (0,1), t_max >= 0");
+        return IM_E_ARG;
+    }
+    for (uint32_t i = 0; i < k; ++i)
+        if (seeds[i] >= g->n) {
+            set_error("im_engine_submit_estimate: seed %u out of range", seeds[i]);
+            return IM_E_ARG;
+        }
+    auto *q = new (std::nothrow) Query();
+    if (!q) return IM_E_OOM;
+    q->ticket = e->next_ticket++;
+    q->q = im_query{g, model, IM_ALGO_ESTIMATE, k, eps_p, delta_p, key};
+    q->seeds.assign(seeds, seeds + k);
+    q->est_eps = eps_p;
+    q->est_delta = delta_p;
+    q->est_tmax = t_max;
     q->t_submit = now_ms();
     e->pending.push_back(q);
     e->all[q->ticket] = q;

@@ -75,7 +75,7 @@ struct im_ctx {
 
     // optional event timing of the main sampler launches
     bool timing = false;
-    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr, ev_group = nullptr;
     im_kernel_times times{};
 
     // second sampling context on its own stream (same device and allocator,

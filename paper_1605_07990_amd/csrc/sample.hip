@@ -56,6 +56,9 @@ struct Counters {
     unsigned long long total_nodes;  // main pass
     unsigned long long edges_long;   // long path
     unsigned long long nodes_long;   // long path
+    unsigned long long grp_samples;  // IC workgroup tier: samples finished there
+    unsigned long long grp_edges;    //   their examined edges
+    unsigned long long grp_levels;   //   their BFS levels
 };
 
 // One entry of the device work queue: samples [s0, s0+count) of stream
@@ -175,6 +178,9 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
     c->total_nodes = 0;
     c->edges_long = 0;
     c->nodes_long = 0;
+    c->grp_samples = 0;
+    c->grp_edges = 0;
+    c->grp_levels = 0;
 }
 
 // ---------------------------------------------------------------- IC ----
@@ -664,10 +670,11 @@ __global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
             s_edges = 0;
         }
         __syncthreads();
-        uint32_t head = 0;
+        uint32_t head = 0, levels = 0;
         for (;;) {
             const uint32_t tail = s_tail;
             if (head >= tail || s_flags != 0u) break;
+            ++levels;
             const uint32_t nb = min(tail - head, static_cast<uint32_t>(kGrpThreads));
             uint64_t a = 0, b = 0, cg = 0;
             if (tid < nb) {
@@ -717,6 +724,11 @@ __global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
         const uint32_t flags = s_flags;
         const uint32_t tail = min(s_tail, kGrpQcap);
         const uint64_t sample_edges = s_edges;
+        if (tid == 0 && !((flags & 2u) && !(flags & 1u))) {
+            atomicAdd(&p.cnt->grp_samples, 1ull);
+            atomicAdd(&p.cnt->grp_edges, static_cast<unsigned long long>(sample_edges));
+            atomicAdd(&p.cnt->grp_levels, static_cast<unsigned long long>(levels));
+        }
         if ((flags & 2u) && !(flags & 1u)) {
             if (tid == 0) {
                 const uint32_t d = atomicAdd(&p.cnt->long_count, 1u);
@@ -1230,6 +1242,7 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
             const uint32_t ggrid = static_cast<uint32_t>(ctx->cu_count);
             if (mode == SampleMode::Pool) ic_group_kernel<0><<<ggrid, kGrpThreads, 0, st>>>(p);
             else ic_group_kernel<1><<<ggrid, kGrpThreads, 0, st>>>(p);
+            if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_group, st));
         }
         {
             const uint32_t nslots = ctx->slot_count;
@@ -1260,14 +1273,25 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         res->deferred = hc.defer_count;
         res->count = count;
         if (ctx->timing && mode == SampleMode::Pool) {
+            // IC: the wave pass and the workgroup tier together (the counters
+            // cover both); LT: the main pass. The long path is left out.
             float ms = 0.f;
-            IM_HIP(hipEventElapsedTime(&ms, ctx->ev_begin, ctx->ev_end));
+            IM_HIP(hipEventElapsedTime(&ms, ctx->ev_begin, model == IM_IC ? ctx->ev_group : ctx->ev_end));
             ctx->times.sample_launches += 1;
             ctx->times.sample_ms += ms;
-            ctx->times.sample_sets += count - hc.defer_count;
+            ctx->times.sample_sets += count - (model == IM_IC ? hc.long_count : hc.defer_count);
             ctx->times.sample_steps += hc.edges;
             ctx->times.sample_nodes += hc.total_nodes;
             ctx->times.model = model;
+            if (model == IM_IC) {
+                float gms = 0.f;
+                IM_HIP(hipEventElapsedTime(&gms, ctx->ev_end, ctx->ev_group));
+                ctx->times.group_launches += 1;
+                ctx->times.group_ms += gms;
+                ctx->times.group_samples += hc.grp_samples;
+                ctx->times.group_edges += hc.grp_edges;
+                ctx->times.group_levels += hc.grp_levels;
+            }
         }
         return IM_OK;
     }

@@ -177,3 +177,38 @@ def test_engine_empty_step(im, ctx):
     assert eng.step() == (0, 0)
     eng.run()
     eng.close()
+
+
+def test_engine_estimate_queries(im, ctx, graphs, oracle_lib):
+    """Influence-estimate queries ride the same fused verification passes
+    as the SSA queries beside them and give im_estimate_inf's (and the
+    oracle's) I_c and T exactly."""
+    import numpy as np
+
+    rng = np.random.default_rng(12)
+    eng = im.Engine(ctx, max_active=32)
+    cases = []
+    for name, model in (("cl_small", 0), ("cl_small", 1), ("nethept", 0), ("rmat16", 1)):
+        g, dg = graphs[name]
+        for j, (size, tmax) in enumerate(((5, 1e9), (40, 1e9), (3, 3000.5), (g.n, 1e9))):
+            S = np.arange(g.n) if size == g.n else rng.choice(g.n, size=size, replace=False)
+            key = 500 + 10 * len(cases) + j
+            cases.append((name, model, S, 0.15, 1e-3, tmax, key,
+                          eng.submit_estimate(dg, model, S, 0.15, 1e-3, tmax, key)))
+    ssa_t = [eng.submit(graphs[c[0]][1], c[1], c[2], c[3], c[4], 1.0 / graphs[c[0]][0].n, c[5])
+             for c in MIX[:4]]
+    note(f"engine with {len(cases)} estimate queries and {len(ssa_t)} SSA/D-SSA queries")
+    eng.run()
+    for name, model, S, e, d, tmax, key, t in cases:
+        g, dg = graphs[name]
+        seeds, st = eng.result(t)
+        assert seeds.tolist() == np.asarray(S, dtype=np.uint32).tolist()
+        ic, T = dg.estimate_inf(model, S, e, d, tmax, key)
+        w = g.w_ic if model == 0 else g.w_lt
+        oic, oT = oracle_lib.Graph(model, g.n, g.src, g.dst, w).estimate_inf(S, e, d, tmax, key)
+        assert (st["cov_c"], st["i_c"]) == (T, ic) == (oT, oic), (name, model, len(S), tmax)
+    for t, case in zip(ssa_t, MIX[:4]):
+        _same(eng.result(t), _single(graphs, case))
+    with pytest.raises(im.ImError):
+        eng.submit_estimate(graphs["cl_small"][1], 0, [graphs["cl_small"][0].n], 0.1, 0.1, 10.0, 1)
+    eng.close()
