@@ -461,6 +461,8 @@ def main() -> int:
                     help="R-MAT-20: concurrent D-SSA queries per step through the multi-query engine")
     ap.add_argument("--greedy-wg-max-entries", type=int, default=None,
                     help="launch parameter: largest Max-Coverage range run in one workgroup")
+    ap.add_argument("--param", nargs=2, action="append", default=[], metavar=("NAME", "VALUE"),
+                    help="set a launch parameter (im_ctx_set_param) before the run")
     ap.add_argument("--no-speculate", action="store_true",
                     help="launch parameter: D-SSA draws each iteration's sets only after the previous check")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
@@ -490,6 +492,8 @@ def main() -> int:
         ctx.set_param("greedy_wg_max_entries", args.greedy_wg_max_entries)
     if args.no_speculate:
         ctx.set_param("dssa_speculate", 0)
+    for name, value in args.param:
+        ctx.set_param(name, int(value))
     body, cpu = WORKLOADS[args.workload](args, im, ctx, sync)
     steps = args.steps if args.workload != "serving" else 1
     out = {"metric": METRIC, "value": body.pop("value"), "unit": "RR sets/s", "n_gpus": 1, "steps": steps,

@@ -303,7 +303,9 @@ typedef enum {
     IM_PARAM_GREEDY_WG_MAX_ENTRIES = 0,
     IM_PARAM_IC_TICKET_BLOCK = 1,
     IM_PARAM_DSSA_SPECULATE = 2,
-    IM_PARAM_GREEDY_MARK_MIN_CHUNKS = 3
+    IM_PARAM_GREEDY_MARK_MIN_CHUNKS = 3,
+    IM_PARAM_GREEDY_COVER_BLOCKS = 4,
+    IM_PARAM_IC_EDGE_BUDGET = 5
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

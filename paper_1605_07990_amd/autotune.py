@@ -21,6 +21,8 @@ CANDIDATES = {
     "ic_ticket_block": [0, 1, 2, 4, 8, 16, 32],
     "dssa_speculate": [0, 1],
     "greedy_mark_min_chunks": [0, 1 << 14, 1 << 16, 1 << 62],
+    "greedy_cover_blocks": [0, 64, 128, 256, 512, 1024],
+    "ic_edge_budget": [512, 1024, 2048, 4096, 8192, 16384, 65536],
 }
 
 

@@ -196,6 +196,8 @@ im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
     a->timing = ctx->timing;
     a->greedy_wg_max_entries = ctx->greedy_wg_max_entries;
     a->greedy_mark_min_chunks = ctx->greedy_mark_min_chunks;
+    a->greedy_cover_blocks = ctx->greedy_cover_blocks;
+    a->ic_edge_budget = ctx->ic_edge_budget;
     a->ic_ticket_block = ctx->ic_ticket_block;
     *out = a;
     return IM_OK;
@@ -323,6 +325,14 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
     case IM_PARAM_GREEDY_MARK_MIN_CHUNKS:
         c->greedy_mark_min_chunks = value;
         return IM_OK;
+    case IM_PARAM_GREEDY_COVER_BLOCKS:
+        if (value > 65535) break;
+        c->greedy_cover_blocks = static_cast<uint32_t>(value);
+        return IM_OK;
+    case IM_PARAM_IC_EDGE_BUDGET:
+        if (value < 64 || value > (1ull << 31)) break;
+        c->ic_edge_budget = static_cast<uint32_t>(value);
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -343,6 +353,12 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_GREEDY_MARK_MIN_CHUNKS:
         *value = c->greedy_mark_min_chunks;
+        return IM_OK;
+    case IM_PARAM_GREEDY_COVER_BLOCKS:
+        *value = c->greedy_cover_blocks;
+        return IM_OK;
+    case IM_PARAM_IC_EDGE_BUDGET:
+        *value = c->ic_edge_budget;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));

@@ -915,7 +915,10 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const bool small = entries <= ctx->greedy_wg_max_entries;
     if (small) init_m2_kernel<<<grid_of(n2, kThreads, cu * 8), kThreads, 0, st>>>(g);
     const uint32_t big = small ? 0u : k;
-    const uint32_t cgrid = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
+    const uint32_t cgrid =
+        ctx->greedy_cover_blocks
+            ? ctx->greedy_cover_blocks
+            : std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
     const uint32_t rgrid = grid_of(uint64_t(n1), kThreads, cu * 4);
     if (big)
         fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);

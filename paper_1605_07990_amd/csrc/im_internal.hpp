@@ -72,6 +72,8 @@ struct im_ctx {
     uint64_t greedy_wg_max_entries = 0;  // grid rounds measured faster at every size tried
     uint32_t ic_ticket_block = 0;  // 0: automatic
     uint64_t greedy_mark_min_chunks = 1u << 16;
+    uint32_t greedy_cover_blocks = 0;  // 0: automatic
+    uint32_t ic_edge_budget = 16384;
 
     // optional event timing of the main sampler launches
     bool timing = false;

@@ -38,17 +38,28 @@ constexpr uint32_t kBitmapMaxN = kIcHcap * 32;
 constexpr uint32_t kLtCap = 512;             // per-sample staging region (LT)
 constexpr int kLongWaves = 4;
 constexpr uint32_t kStageChunk = 1024;       // IC staging entries a wave reserves at once
-constexpr uint64_t kIcEdgeBudget = 16384;    // edges a wave examines before a workgroup takes the sample over
-constexpr int kGrpThreads = 1024;            // IC workgroup tier: threads per sample
-constexpr uint32_t kGrpQcap = 8192;          // its LDS queue entries
-constexpr uint32_t kGrpHcap = 16384;         // its LDS hash slots
-constexpr uint32_t kGrpHbits = 14;
+// IC workgroup tiers: a sample the wave pass hands on goes to a 256-thread
+// workgroup (five fit on a compute unit, so many heavy samples advance at
+// once: their BFS levels are many and small); one too large for its LDS goes
+// to a 1024-thread workgroup with four times the LDS, then to the long path.
+struct GrpSmall {
+    static constexpr int kThreads = 256;
+    static constexpr uint32_t kQcap = 2048;  // LDS queue entries
+    static constexpr uint32_t kHbits = 12;   // LDS hash slots: 4096
+};
+struct GrpLarge {
+    static constexpr int kThreads = 1024;
+    static constexpr uint32_t kQcap = 8192;
+    static constexpr uint32_t kHbits = 14;  // 16384
+};
 
 struct Counters {
     uint32_t ticket;        // next sample of the main pass
     uint32_t defer_count;   // samples handed on by the main pass (IC: to the workgroup tier; LT: to the long path)
     uint32_t defer_ticket;  // next of them to take
-    uint32_t long_count;    // IC samples the workgroup tier hands to the long path
+    uint32_t large_count;   // IC samples the small workgroup tier hands to the large one
+    uint32_t large_ticket;
+    uint32_t long_count;    // IC samples the large workgroup tier hands to the long path
     uint32_t long_ticket;
     uint32_t overflow;      // staging too small: the batch must be re-run
     unsigned long long stage_cursor;
@@ -82,7 +93,8 @@ struct Params {
     uint32_t nitems;
     Counters *cnt;
     uint32_t *defer_list;
-    uint32_t *long_list;  // IC: samples the workgroup tier hands to the long path
+    uint32_t *large_list;  // IC: samples the small workgroup tier hands to the large one
+    uint32_t *long_list;   // IC: samples the large workgroup tier hands to the long path
     uint32_t *stage;
     uint64_t stage_cap;
     uint64_t *stage_off;  // per sample
@@ -90,6 +102,7 @@ struct Params {
     uint8_t *z;           // per sample (hits mode)
     uint32_t lt_cap;
     uint32_t ticket_block;  // IC: consecutive samples a wave takes per ticket
+    uint32_t edge_budget;   // IC: edges a wave examines before a workgroup takes the sample over
 };
 
 // The work item owning global slot t.
@@ -170,6 +183,8 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
     c->ticket = 0;
     c->defer_count = 0;
     c->defer_ticket = 0;
+    c->large_count = 0;
+    c->large_ticket = 0;
     c->long_count = 0;
     c->long_ticket = 0;
     c->overflow = 0;
@@ -288,7 +303,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
 
         bool heavy = false;
         while (head < tail && !hit) {
-            if (sample_edges >= kIcEdgeBudget) {  // a workgroup finishes it
+            if (sample_edges >= p.edge_budget) {  // a workgroup finishes it
                 heavy = true;
                 break;
             }
@@ -617,26 +632,33 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
 // ------------------------------------------------------- IC workgroup ----
 
 // LDS open-addressed set of node ids (key u + 1) for one workgroup.
+template <uint32_t kHbits>
 __device__ __forceinline__ bool grp_insert(uint32_t *vis, uint32_t u, bool &full) {
+    constexpr uint32_t kHcap = 1u << kHbits;
     const uint32_t key = u + 1u;
-    uint32_t h = (u * 2654435761u) >> (32 - kGrpHbits);
-    for (uint32_t probe = 0; probe < kGrpHcap; ++probe) {
+    uint32_t h = (u * 2654435761u) >> (32 - kHbits);
+    for (uint32_t probe = 0; probe < kHcap; ++probe) {
         const uint32_t old = atomicCAS(&vis[h], 0u, key);
         if (old == 0u) return true;
         if (old == key) return false;
-        h = (h + 1u) & (kGrpHcap - 1u);
+        h = (h + 1u) & (kHcap - 1u);
     }
     full = true;
     return false;
 }
 
-// IC samples the wave pass handed on (too many edges for one wave, or too
-// large for its LDS), one workgroup per sample: each level's frontier (up to
-// 1024 nodes at a time) is laid out by a block scan of its aligned 4-edge
-// groups, which all threads then expand. Samples too large for this LDS go
-// on to the long path.
-template <int kMode>
-__global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
+// IC samples handed on by the previous tier, one workgroup per sample: each
+// level's frontier (up to kThreads nodes at a time) is laid out by a block
+// scan of its aligned 4-edge groups, which all threads then expand. Samples
+// too large for this tier's LDS go on to the next tier's list.
+template <int kMode, typename Tier>
+__global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, const uint32_t *in_list,
+                                                                  const uint32_t *in_count, uint32_t *in_ticket,
+                                                                  uint32_t *out_list, uint32_t *out_count) {
+    constexpr int kGrpThreads = Tier::kThreads;
+    constexpr uint32_t kGrpQcap = Tier::kQcap;
+    constexpr uint32_t kGrpHbits = Tier::kHbits;
+    constexpr uint32_t kGrpHcap = 1u << kGrpHbits;
     __shared__ uint32_t s_queue[kGrpQcap];
     __shared__ uint32_t s_vis[kGrpHcap];
     __shared__ uint64_t s_pre[kGrpThreads];
@@ -650,8 +672,8 @@ __global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
     __syncthreads();
     for (;;) {
         if (tid == 0) {
-            const uint32_t d = atomicAdd(&p.cnt->defer_ticket, 1u);
-            s_t = d < p.cnt->defer_count ? p.defer_list[d] : 0xFFFFFFFFu;
+            const uint32_t d = atomicAdd(in_ticket, 1u);
+            s_t = d < *in_count ? in_list[d] : 0xFFFFFFFFu;
         }
         __syncthreads();
         const uint32_t t = s_t;
@@ -663,7 +685,7 @@ __global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
         if (tid == 0) {
             const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
             bool full = false;
-            grp_insert(s_vis, v0, full);
+            grp_insert<kGrpHbits>(s_vis, v0, full);
             s_queue[0] = v0;
             s_tail = 1;
             s_flags = (kMode == 1 && test_bit(seedbits, v0)) ? 1u : 0u;
@@ -709,7 +731,7 @@ __global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
                     const uint64_t e = (g << 2) + q;
                     if (e >= ea && e < eb) {
                         const uint2 rec = p.edges[e];
-                        if (ic_live(word_of(coins, q), rec.y) && grp_insert(s_vis, rec.x, full)) {
+                        if (ic_live(word_of(coins, q), rec.y) && grp_insert<kGrpHbits>(s_vis, rec.x, full)) {
                             const uint32_t pos = atomicAdd(&s_tail, 1u);
                             if (pos < kGrpQcap) s_queue[pos] = rec.x;
                             else atomicOr(&s_flags, 2u);
@@ -731,8 +753,8 @@ __global__ __launch_bounds__(kGrpThreads) void ic_group_kernel(Params p) {
         }
         if ((flags & 2u) && !(flags & 1u)) {
             if (tid == 0) {
-                const uint32_t d = atomicAdd(&p.cnt->long_count, 1u);
-                p.long_list[d] = t;
+                const uint32_t d = atomicAdd(out_count, 1u);
+                out_list[d] = t;
             }
         } else if (kMode == 1) {
             if (tid == 0) {
@@ -1092,11 +1114,12 @@ struct Meta {
     uint64_t *stage_off;
     uint32_t *sizes;
     uint32_t *defer_list;
+    uint32_t *large_list;
     uint32_t *long_list;
     uint8_t *z;
 };
 
-size_t meta_bytes(uint64_t count) { return count * (8 + 4 + 4 + 4 + 1) + 256; }
+size_t meta_bytes(uint64_t count) { return count * (8 + 4 + 4 + 4 + 4 + 1) + 256; }
 
 Meta meta_view(im_ctx *ctx, uint64_t count) {
     Meta m;
@@ -1104,8 +1127,9 @@ Meta meta_view(im_ctx *ctx, uint64_t count) {
     m.stage_off = reinterpret_cast<uint64_t *>(base);
     m.sizes = reinterpret_cast<uint32_t *>(base + count * 8);
     m.defer_list = reinterpret_cast<uint32_t *>(base + count * 12);
-    m.long_list = reinterpret_cast<uint32_t *>(base + count * 16);
-    m.z = reinterpret_cast<uint8_t *>(base + count * 20);
+    m.large_list = reinterpret_cast<uint32_t *>(base + count * 16);
+    m.long_list = reinterpret_cast<uint32_t *>(base + count * 20);
+    m.z = reinterpret_cast<uint8_t *>(base + count * 24);
     return m;
 }
 
@@ -1196,6 +1220,7 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         p.nitems = nitems;
         p.cnt = cnt;
         p.defer_list = meta.defer_list;
+        p.large_list = meta.large_list;
         p.long_list = meta.long_list;
         p.stage = static_cast<uint32_t *>(ctx->stage.ptr);
         p.stage_cap = cap;
@@ -1204,6 +1229,7 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         p.z = (mode == SampleMode::Hits) ? static_cast<uint8_t *>(ctx->zflags.ptr) : meta.z;
         p.lt_cap = kLtCap;
         p.ticket_block = 1;
+        p.edge_budget = ctx->ic_edge_budget;
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
         zero_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(dacc), 2ull * nitems);
@@ -1239,9 +1265,19 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         }
         if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_end, st));
         if (model == IM_IC) {
-            const uint32_t ggrid = static_cast<uint32_t>(ctx->cu_count);
-            if (mode == SampleMode::Pool) ic_group_kernel<0><<<ggrid, kGrpThreads, 0, st>>>(p);
-            else ic_group_kernel<1><<<ggrid, kGrpThreads, 0, st>>>(p);
+            const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+            Counters *c = cnt;
+            if (mode == SampleMode::Pool) {
+                ic_group_kernel<0, GrpSmall><<<cu * 5, GrpSmall::kThreads, 0, st>>>(
+                    p, p.defer_list, &c->defer_count, &c->defer_ticket, p.large_list, &c->large_count);
+                ic_group_kernel<0, GrpLarge><<<cu, GrpLarge::kThreads, 0, st>>>(
+                    p, p.large_list, &c->large_count, &c->large_ticket, p.long_list, &c->long_count);
+            } else {
+                ic_group_kernel<1, GrpSmall><<<cu * 5, GrpSmall::kThreads, 0, st>>>(
+                    p, p.defer_list, &c->defer_count, &c->defer_ticket, p.large_list, &c->large_count);
+                ic_group_kernel<1, GrpLarge><<<cu, GrpLarge::kThreads, 0, st>>>(
+                    p, p.large_list, &c->large_count, &c->large_ticket, p.long_list, &c->long_count);
+            }
             if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_group, st));
         }
         {
