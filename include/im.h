@@ -296,7 +296,21 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       graph with more than this many 64-node chunks have the cover step
  *       mark every chunk it touches and re-derive only those; on smaller
  *       graphs each chunk's maximum holder is re-checked instead (default
- *       65536, i.e. n above 4,194,304).
+ *       65536, i.e. n above 4,194,304);
+ *   IM_PARAM_GREEDY_COVER_BLOCKS    workgroups per job that cover a round's
+ *       seed, 1..65535, or 0 for the automatic choice (default 0);
+ *   IM_PARAM_IC_EDGE_BUDGET         in-edges an IC sample may examine in the
+ *       one-wave pass before it is handed to the workgroup tiers,
+ *       64..2^31 (default 16384);
+ *   IM_PARAM_GREEDY_CANDIDATES      grid-wide Max-Coverage of one range
+ *       (im_max_coverage*, im_ssa*, im_dssa, im_ris) keeps this many 64-node
+ *       chunks as candidates, 1..64, together with a bound on every key
+ *       outside them, and takes a round in one launch while the best
+ *       candidate beats that bound (two more launches re-derive the index
+ *       and the candidates when it does not); 0: two launches every round
+ *       (default 0);
+ *   IM_PARAM_GREEDY_CANDIDATES_BATCH the same for the engine's batched
+ *       Max-Coverage of many queries (default 32).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -305,7 +319,9 @@ typedef enum {
     IM_PARAM_DSSA_SPECULATE = 2,
     IM_PARAM_GREEDY_MARK_MIN_CHUNKS = 3,
     IM_PARAM_GREEDY_COVER_BLOCKS = 4,
-    IM_PARAM_IC_EDGE_BUDGET = 5
+    IM_PARAM_IC_EDGE_BUDGET = 5,
+    IM_PARAM_GREEDY_CANDIDATES = 6,
+    IM_PARAM_GREEDY_CANDIDATES_BATCH = 7
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

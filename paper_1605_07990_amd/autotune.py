@@ -23,6 +23,8 @@ CANDIDATES = {
     "greedy_mark_min_chunks": [0, 1 << 14, 1 << 16, 1 << 62],
     "greedy_cover_blocks": [0, 64, 128, 256, 512, 1024],
     "ic_edge_budget": [512, 1024, 2048, 4096, 8192, 16384, 65536],
+    "greedy_candidates": [0, 8, 16, 32, 64],
+    "greedy_candidates_batch": [0, 8, 16, 32, 64],
 }
 
 

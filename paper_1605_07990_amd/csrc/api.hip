@@ -198,6 +198,8 @@ im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
     a->greedy_mark_min_chunks = ctx->greedy_mark_min_chunks;
     a->greedy_cover_blocks = ctx->greedy_cover_blocks;
     a->ic_edge_budget = ctx->ic_edge_budget;
+    a->greedy_candidates = ctx->greedy_candidates;
+    a->greedy_candidates_batch = ctx->greedy_candidates_batch;
     a->ic_ticket_block = ctx->ic_ticket_block;
     *out = a;
     return IM_OK;
@@ -333,6 +335,14 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value < 64 || value > (1ull << 31)) break;
         c->ic_edge_budget = static_cast<uint32_t>(value);
         return IM_OK;
+    case IM_PARAM_GREEDY_CANDIDATES:
+        if (value > 64) break;
+        c->greedy_candidates = static_cast<uint32_t>(value);
+        return IM_OK;
+    case IM_PARAM_GREEDY_CANDIDATES_BATCH:
+        if (value > 64) break;
+        c->greedy_candidates_batch = static_cast<uint32_t>(value);
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -359,6 +369,12 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_IC_EDGE_BUDGET:
         *value = c->ic_edge_budget;
+        return IM_OK;
+    case IM_PARAM_GREEDY_CANDIDATES:
+        *value = c->greedy_candidates;
+        return IM_OK;
+    case IM_PARAM_GREEDY_CANDIDATES_BATCH:
+        *value = c->greedy_candidates_batch;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));

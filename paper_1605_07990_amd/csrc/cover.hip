@@ -134,6 +134,21 @@ constexpr uint32_t kPersistDirtyCap = 2048;     // chunks listed per round befor
 constexpr uint32_t kPersistCovWords = 8192;     // covered-set bits kept in LDS (262,144 sets)
 constexpr uint32_t kPersistGroupWords = 512;    // m2 entries tracked per round (n up to 2^26)
 
+constexpr uint32_t kCandMax = 64;                       // candidate chunks at most
+constexpr uint32_t kCandSlots = kCandMax << kL1Shift;   // nodes of the candidate chunks
+constexpr uint32_t kCandNodes = 512;                    // candidate nodes at most
+constexpr uint32_t kCandHashBits = 10;                  // LDS map node -> slot: 1024 entries
+constexpr uint32_t kNoCand = 0xFFFFFFFFu;
+enum : uint32_t { kStepRound = 0, kStepRefresh = 1, kStepSelect = 2, kStepDone = 3 };
+
+// A job's step state. `thresh` bounds the key of every node outside the
+// candidate chunks; `r` is the next round.
+struct StepHdr {
+    uint32_t phase, r, stalls, nnode;  // nnode: candidate nodes
+    unsigned long long thresh;
+    unsigned long long pad;
+};
+
 struct GreedyState {
     uint32_t *gain;
     unsigned long long *m1;
@@ -152,6 +167,12 @@ struct GreedyState {
     unsigned long long *bmax;  // per-round launches: each refresh block's largest key
     uint32_t nbmax;            // per-round launches: refresh blocks
     uint32_t mark;             // per-round launches: cover marks touched chunks in `dirty` (large n)
+    // step launches (candidate chunks)
+    struct StepHdr *hdr;  // [2]: the job's step state, by launch parity
+    uint32_t *cnode;      // [kCandNodes] node of a slot
+    uint32_t *cbase;      // [2][kCandNodes] candidate gains at the start of the round before
+    uint32_t *cdec;       // [3][kCandNodes] drops of candidate nodes in one round
+    uint32_t want;        // candidate chunks asked for
 };
 
 // Load flavours. State written by earlier kernels is read with plain loads.
@@ -306,28 +327,41 @@ __device__ uint32_t choose(const GreedyState &g, uint32_t r, unsigned long long 
 __device__ __forceinline__ void refresh_block(const GreedyState &g, uint32_t r, uint32_t blk, uint32_t nblk,
                                               unsigned long long *smem) {
     unsigned long long best = 0;
-    // 32 consecutive chunks share a dirty word and are read by 32 consecutive
-    // lanes of one wave; the word's first lane clears it once it has the value
-    for (uint32_t c = blk * blockDim.x + threadIdx.x; c < g.n1; c += nblk * blockDim.x) {
-        unsigned long long m = g.m1[c];
-        if (r > 0 && g.mark) {
-            // re-derive the chunks whose nodes lost gain
-            const uint32_t word = g.dirty[c >> 5];
-            if ((word >> (c & 31u)) & 1u) {
+    // A wave takes 64 consecutive chunks (one m2 group) at a time. 32
+    // consecutive chunks share a dirty word and are read by 32 consecutive
+    // lanes; the word's first lane clears it once it has the value.
+    const uint32_t lane = lane_id();
+    for (uint32_t c0 = blk * blockDim.x + (threadIdx.x - lane); c0 < g.n1; c0 += nblk * blockDim.x) {
+        const uint32_t c = c0 + lane;
+        unsigned long long m = 0;
+        if (c < g.n1) {
+            m = g.m1[c];
+            if (r > 0 && g.mark) {
+                // re-derive the chunks whose nodes lost gain
+                const uint32_t word = g.dirty[c >> 5];
+                if ((word >> (c & 31u)) & 1u) {
+                    m = m1_lane<false>(g, c);
+                    g.m1[c] = m;
+                }
+                if ((c & 31u) == 0 && word != 0u) g.dirty[c >> 5] = 0u;
+            } else if (r > 0 && m != 0ull && node_key<false>(g.gain, ~static_cast<uint32_t>(m)) != m) {
+                // re-derive the chunks whose maximum holder lost gain
                 m = m1_lane<false>(g, c);
                 g.m1[c] = m;
             }
-            if ((c & 31u) == 0 && word != 0u) g.dirty[c >> 5] = 0u;
-        } else if (r > 0 && m != 0ull && node_key<false>(g.gain, ~static_cast<uint32_t>(m)) != m) {
-            // re-derive the chunks whose maximum holder lost gain
-            m = m1_lane<false>(g, c);
-            g.m1[c] = m;
         }
         best = m > best ? m : best;
+        const unsigned long long gm = wave_max_u64(m);
+        if (lane == 0) g.m2[c0 >> kL2Shift] = gm;
     }
     best = block_max_u64(best, smem);
     if (threadIdx.x == 0) g.bmax[blk] = best;
 }
+
+struct RoundLds;
+template <bool kCand>
+__device__ void cover_seed(const GreedyState &g, uint32_t r, uint32_t v, uint32_t blk, uint32_t nblk, uint32_t nnode,
+                           RoundLds *L);
 
 // Round step 2 body (grid-wide over one job's blocks): every block takes the
 // largest of the refresh blocks' maxima, so all agree on seed r without
@@ -357,6 +391,38 @@ __device__ __forceinline__ void cover_block(const GreedyState &g, uint32_t r, ui
         const uint32_t c = v >> kL1Shift;
         if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));  // the seed's key is now 0
     }
+    cover_seed<false>(g, r, v, blk, nblk, 0u, nullptr);
+}
+
+// LDS of a candidate round: the candidate nodes' slots by node id (open
+// addressing) and the drops this block gives each slot.
+struct RoundLds {
+    uint32_t key[1u << kCandHashBits];
+    uint32_t slot[1u << kCandHashBits];
+    uint32_t dec[kCandNodes];
+};
+
+__device__ __forceinline__ uint32_t cand_slot(const RoundLds &L, uint32_t u) {
+    constexpr uint32_t kMask = (1u << kCandHashBits) - 1u;
+    uint32_t h = (u * 2654435761u) >> (32 - kCandHashBits);
+    for (uint32_t p = 0; p <= kMask; ++p) {
+        const uint32_t k = L.key[h];
+        if (k == u) return L.slot[h];
+        if (k == kNoCand) break;
+        h = (h + 1u) & kMask;
+    }
+    return kNoCand;
+}
+
+// Cover seed v of round r (grid-wide over one job's blocks): every set
+// holding v not covered yet is marked, and each member's gain drops by one,
+// 16 lanes per incidence entry. With candidates (L holds their slots by node
+// and zeroed counts), the drops of candidate nodes (the nodes most sets
+// share) are summed in LDS per block and applied once per node at the end,
+// to the gain and to the round's dec buffer.
+template <bool kCand>
+__device__ void cover_seed(const GreedyState &g, uint32_t r, uint32_t v, uint32_t blk, uint32_t nblk, uint32_t nnode,
+                           RoundLds *L) {
     const uint64_t a = g.ioff[v], b = g.ioff[v + 1];
     const uint32_t sub = threadIdx.x & 15u;
     const uint64_t grp = (static_cast<uint64_t>(blk) * blockDim.x + threadIdx.x) >> 4;
@@ -364,25 +430,50 @@ __device__ __forceinline__ void cover_block(const GreedyState &g, uint32_t r, ui
     unsigned long long newly = 0;
     for (uint64_t i = a + grp; i < b; i += ngrp) {
         const uint32_t j = g.isets[i];
-        uint32_t fresh = 0;
-        if (sub == 0) {
-            const uint32_t bit = 1u << (j & 31u);
-            fresh = (atomicOr(&g.covbits[j >> 5], bit) & bit) ? 0u : 1u;
-        }
-        fresh = __shfl(fresh, static_cast<int>(lane_id() & ~15u), kWave);
+        // the set's extent, its covered flag and its first members are in
+        // flight together; the flag decides whether they are used
+        const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
+        const uint32_t u0 = sa + sub < sb ? g.pnodes[sa + sub] : 0u;
+        const uint32_t bit = 1u << (j & 31u);
+        uint32_t prior = bit;
+        if (sub == 0) prior = atomicOr(&g.covbits[j >> 5], bit);
+        const uint32_t fresh = __shfl((prior & bit) ? 0u : 1u, static_cast<int>(lane_id() & ~15u), kWave);
         if (fresh) {
             if (sub == 0) ++newly;
-            const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
             for (uint64_t q = sa + sub; q < sb; q += 16) {
-                const uint32_t u = g.pnodes[q];
+                const uint32_t u = q == sa + sub ? u0 : g.pnodes[q];
                 const uint32_t c = u >> kL1Shift;
-                atomicSub(&g.gain[u], 1u);
-                if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
+                bool direct = true;
+                if constexpr (kCand) {
+                    const uint32_t slot = cand_slot(*L, u);
+                    if (slot != kNoCand) {
+                        atomicAdd(&L->dec[slot], 1u);
+                        direct = false;
+                    }
+                }
+                if (direct) {
+                    atomicSub(&g.gain[u], 1u);
+                    if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
+                }
             }
         }
     }
     newly = wave_sum_u64(newly);
     if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+    if constexpr (kCand) {
+        __syncthreads();
+        uint32_t *dec = g.cdec + (r % 3u) * kCandNodes;
+        for (uint32_t i = threadIdx.x; i < nnode; i += blockDim.x) {
+            const uint32_t d = L->dec[i];
+            if (d) {
+                const uint32_t u = g.cnode[i];
+                const uint32_t c = u >> kL1Shift;
+                atomicSub(&g.gain[u], d);
+                atomicAdd(&dec[i], d);
+                if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
+            }
+        }
+    }
 }
 
 // Round r, step 1 (grid-wide).
@@ -412,6 +503,308 @@ __global__ __launch_bounds__(kThreads) void batch_cover_kernel(const GreedyState
     const GreedyState &g = jobs[blockIdx.y];
     if (r >= g.k) return;
     cover_block(g, r, blockIdx.x, gridDim.x, smem, &s_pick);
+}
+
+// ---- greedy rounds as steps over candidate chunks ----
+//
+// Keys only fall. So if C is a set of chunks and thresh bounds the key of
+// every node outside C (the largest m1 outside C when C was picked), then
+// while the largest current key inside C exceeds thresh it is the argmax
+// over all nodes, and a round needs no grid-wide maximum: every block reads
+// the candidate nodes' gains and all reach the same seed. Those gains come
+// from buffers no block of the same launch writes:
+//   gain at the start of round r = cbase[r & 1] - cdec[(r - 1) % 3]
+// where cbase[r & 1] holds the gains at the start of round r - 1 and
+// cdec[q % 3] the drops round q gave candidate nodes. Round r writes
+// cbase[(r + 1) & 1] (adding its seed's chosen bit), clears cdec[(r + 1) % 3]
+// for round r + 1 and counts its own drops in cdec[r % 3]. When the test
+// fails the job re-derives m1 and picks new candidates. Each launch moves
+// every job one step:
+//   REFRESH -> SELECT -> ROUND ... ROUND [-> REFRESH -> SELECT -> ROUND ...]
+// and the step state is kept twice, by launch parity, so the blocks of a
+// launch read what the previous launch left.
+
+struct SelectLds {
+    uint32_t hist[kThreads];
+    uint64_t scan[kThreads / kWave];
+    uint32_t list[kCandSlots];  // chunks, then node positions (chunk index << 6 | node bit)
+    uint32_t groups[kCandMax + 1];
+    uint32_t cand[kCandMax];
+    unsigned long long mask[kCandMax];
+    uint32_t start[kCandMax];
+    uint32_t ngroups, nlist, ncand, nnode, bin;
+    uint64_t above;
+};
+
+// The rank-th largest (1-based, counting repeats) of count keys get(i), by
+// eight 8-bit passes from the top byte; 0 when count < rank. All threads of
+// one 256-thread block.
+template <typename Get>
+__device__ unsigned long long block_kth_largest(Get get, uint32_t count, uint32_t rank, SelectLds &L) {
+    if (count < rank) return 0ull;
+    const uint32_t tid = threadIdx.x;
+    unsigned long long prefix = 0, mask = 0;
+    uint32_t need = rank;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        L.hist[tid] = 0u;
+        __syncthreads();
+        for (uint32_t i = tid; i < count; i += blockDim.x) {
+            const unsigned long long x = get(i);
+            if ((x & mask) == prefix) atomicAdd(&L.hist[(x >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        // thread t holds bin 255 - t, so the scan counts the larger bins first
+        const uint32_t bin = 255u - tid;
+        const uint64_t h = L.hist[bin];
+        uint64_t total = 0;
+        const uint64_t above = block_scan_excl(h, L.scan, total);
+        if (above < need && need <= above + h) {
+            L.bin = bin;
+            L.above = above;
+        }
+        __syncthreads();
+        prefix |= static_cast<unsigned long long>(L.bin) << shift;
+        mask |= 0xFFull << shift;
+        need -= static_cast<uint32_t>(L.above);
+        __syncthreads();
+    }
+    return prefix;
+}
+
+// Log-scale bin of a gain >= 1: eight bins per power of two, 1..255,
+// non-decreasing in the gain.
+__device__ __forceinline__ uint32_t gain_bin(uint32_t gain) {
+    const uint32_t lz = 31u - static_cast<uint32_t>(__clz(gain));
+    const uint32_t frac = lz >= 3u ? (gain >> (lz - 3u)) & 7u : (gain << (3u - lz)) & 7u;
+    return min(255u, 1u + 8u * lz + frac);
+}
+
+// A threshold t = (gain_t << 32 | 0xFFFFFFFF) keeping as many of the count
+// keys get(i) above it as whole gain bins allow without passing cap (keys
+// above t are exactly those with gain above gain_t). ok is false when no key
+// has a gain or the top bin alone holds more than cap keys. Two passes and a
+// scan; all threads of one 256-thread block.
+template <typename Get>
+__device__ unsigned long long block_gain_cut(Get get, uint32_t count, uint32_t cap, SelectLds &L, bool &ok) {
+    const uint32_t tid = threadIdx.x;
+    L.hist[tid] = 0u;
+    if (tid == 0) L.bin = kNoCand;
+    __syncthreads();
+    for (uint32_t i = tid; i < count; i += blockDim.x) {
+        const uint32_t gain = static_cast<uint32_t>(get(i) >> 32);
+        if (gain) atomicAdd(&L.hist[gain_bin(gain)], 1u);
+    }
+    __syncthreads();
+    const uint32_t bin = 255u - tid;
+    const uint64_t h = L.hist[bin];
+    uint64_t total = 0;
+    const uint64_t above = block_scan_excl(h, L.scan, total);
+    // the lowest bin whose keys, with those of the bins above, fit in cap
+    if (bin >= 1u && above + h <= cap && above + h > 0) atomicMin(&L.bin, bin);
+    __syncthreads();
+    const uint32_t cut = L.bin;
+    ok = cut != kNoCand;
+    if (!ok) return 0ull;
+    unsigned long long below = 0;
+    for (uint32_t i = tid; i < count; i += blockDim.x) {
+        const uint32_t gain = static_cast<uint32_t>(get(i) >> 32);
+        if (gain && gain_bin(gain) < cut && gain > below) below = gain;
+    }
+    below = block_max_u64(below, reinterpret_cast<unsigned long long *>(L.scan));
+    return (below << 32) | 0xFFFFFFFFull;
+}
+
+// SELECT (block 0 of the job), from the refreshed m1 and the group maxima
+// m2. Chunks: those whose maximum beats the (want+1)-th largest group
+// maximum t0 (they lie in the `want` leading groups); if more than kCandMax
+// qualify, the `want` largest, with the threshold raised to the next one.
+// Nodes: those of the chosen chunks whose key beats the threshold; if more
+// than kCandNodes, the kCandNodes largest, raising the threshold again.
+// Every node left out has a key at most the threshold. Then the
+// candidates' gains are copied for round h.r.
+__device__ void step_select(const GreedyState &g, const StepHdr &h, StepHdr *out, SelectLds &L) {
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        L.ngroups = 0;
+        L.nlist = 0;
+        L.ncand = 0;
+        L.nnode = 0;
+    }
+    if (tid < kCandMax) L.mask[tid] = 0ull;
+    __syncthreads();
+    // thresholds come from gain bins, or exactly by rank when bins cannot split
+    bool ok = false;
+    auto group_key = [&](uint32_t i) { return g.m2[i]; };
+    unsigned long long t0 = block_gain_cut(group_key, g.n2, g.want, L, ok);
+    if (!ok) t0 = block_kth_largest(group_key, g.n2, g.want + 1u, L);
+    for (uint32_t d = tid; d < g.n2; d += blockDim.x)
+        if (g.m2[d] > t0) L.groups[atomicAdd(&L.ngroups, 1u)] = d;
+    __syncthreads();
+    const uint32_t ng = L.ngroups;
+    for (uint32_t i = tid; i < (ng << kL2Shift); i += blockDim.x) {
+        const uint32_t c = (L.groups[i >> kL2Shift] << kL2Shift) | (i & 63u);
+        if (c < g.n1 && g.m1[c] > t0) L.list[atomicAdd(&L.nlist, 1u)] = c;
+    }
+    __syncthreads();
+    const uint32_t nl = L.nlist;
+    unsigned long long thresh = t0;
+    if (nl > kCandMax) {
+        auto chunk_key = [&](uint32_t i) { return g.m1[L.list[i]]; };
+        unsigned long long t1 = block_gain_cut(chunk_key, nl, kCandMax, L, ok);
+        if (!ok) t1 = block_kth_largest(chunk_key, nl, kCandMax + 1u, L);
+        thresh = t1 > thresh ? t1 : thresh;
+    }
+    for (uint32_t i = tid; i < nl; i += blockDim.x) {
+        const uint32_t c = L.list[i];
+        if (g.m1[c] > thresh) L.cand[atomicAdd(&L.ncand, 1u)] = c;
+    }
+    __syncthreads();
+    const uint32_t nc = L.ncand;
+    // nodes of the chosen chunks above the threshold
+    for (uint32_t i = tid; i < (nc << kL1Shift); i += blockDim.x) {
+        const uint32_t v = (L.cand[i >> kL1Shift] << kL1Shift) | (i & 63u);
+        if (v < g.n && node_key<false>(g.gain, v) > thresh) L.list[atomicAdd(&L.nnode, 1u)] = i;
+    }
+    __syncthreads();
+    const uint32_t nn = L.nnode;
+    auto key_at = [&](uint32_t idx) {
+        const uint32_t i = L.list[idx];
+        return node_key<false>(g.gain, (L.cand[i >> kL1Shift] << kL1Shift) | (i & 63u));
+    };
+    if (nn > kCandNodes) {
+        unsigned long long t2 = block_gain_cut(key_at, nn, kCandNodes, L, ok);
+        if (!ok) t2 = block_kth_largest(key_at, nn, kCandNodes + 1u, L);
+        thresh = t2 > thresh ? t2 : thresh;
+    }
+    for (uint32_t idx = tid; idx < nn; idx += blockDim.x) {
+        const uint32_t i = L.list[idx];
+        if (key_at(idx) > thresh) atomicOr(&L.mask[i >> kL1Shift], 1ull << (i & 63u));
+    }
+    __syncthreads();
+    // slots follow chunk order, then bit order
+    if (tid < kWave) {
+        const uint64_t cnt = tid < nc ? static_cast<uint64_t>(__popcll(L.mask[tid])) : 0ull;
+        uint64_t inc = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint64_t y = __shfl_up(inc, d, kWave);
+            if (tid >= static_cast<uint32_t>(d)) inc += y;
+        }
+        L.start[tid] = static_cast<uint32_t>(inc - cnt);
+        if (tid == kWave - 1) L.nnode = static_cast<uint32_t>(inc);
+    }
+    __syncthreads();
+    const uint32_t slots = L.nnode;
+    uint32_t *base = g.cbase + (h.r & 1u) * kCandNodes;
+    uint32_t *dec_prev = g.cdec + ((h.r + 2u) % 3u) * kCandNodes;
+    uint32_t *dec_cur = g.cdec + (h.r % 3u) * kCandNodes;
+    for (uint32_t i = tid; i < (nc << kL1Shift); i += blockDim.x) {
+        const uint32_t ci = i >> kL1Shift, j = i & 63u;
+        const unsigned long long m = L.mask[ci];
+        if ((m >> j) & 1ull) {
+            const uint32_t slot = L.start[ci] + static_cast<uint32_t>(__popcll(m & ((1ull << j) - 1ull)));
+            const uint32_t v = (L.cand[ci] << kL1Shift) | j;
+            g.cnode[slot] = v;
+            base[slot] = g.gain[v];
+            dec_prev[slot] = 0u;
+            dec_cur[slot] = 0u;
+        }
+    }
+    if (tid == 0) {
+        StepHdr o = h;
+        o.phase = kStepRound;
+        o.nnode = slots;
+        o.thresh = thresh;
+        *out = o;
+    }
+}
+
+// ROUND (grid-wide over one job's blocks).
+__device__ void step_round(const GreedyState &g, const StepHdr &h, StepHdr *out, uint32_t blk, uint32_t nblk,
+                           unsigned long long *smem, RoundLds &L) {
+    const uint32_t r = h.r;
+    const uint32_t nn = h.nnode;
+    const uint32_t *base = g.cbase + (r & 1u) * kCandNodes;
+    const uint32_t *dec_prev = g.cdec + ((r + 2u) % 3u) * kCandNodes;
+    constexpr uint32_t kMask = (1u << kCandHashBits) - 1u;
+    for (uint32_t i = threadIdx.x; i <= kMask; i += blockDim.x) L.key[i] = kNoCand;
+    for (uint32_t i = threadIdx.x; i < nn; i += blockDim.x) L.dec[i] = 0u;
+    __syncthreads();
+    // the largest candidate key; the candidates' slots go into the LDS map
+    unsigned long long best = 0;
+    for (uint32_t s = threadIdx.x; s < nn; s += blockDim.x) {
+        const uint32_t x = base[s] - dec_prev[s];
+        const uint32_t u = g.cnode[s];
+        uint32_t hh = (u * 2654435761u) >> (32 - kCandHashBits);
+        for (uint32_t p = 0; p <= kMask; ++p) {
+            if (atomicCAS(&L.key[hh], kNoCand, u) == kNoCand) {
+                L.slot[hh] = s;
+                break;
+            }
+            hh = (hh + 1u) & kMask;
+        }
+        if (!(x & kChosen)) {
+            const unsigned long long key = (static_cast<unsigned long long>(x) << 32) | static_cast<unsigned long long>(~u);
+            best = key > best ? key : best;
+        }
+    }
+    best = block_max_u64(best, smem);  // its barriers also publish the map
+    if (best <= h.thresh) {
+        // a node outside the candidates may lead now: refresh and re-select
+        if (blk == 0 && threadIdx.x == 0) {
+            StepHdr o = h;
+            o.phase = kStepRefresh;
+            ++o.stalls;
+            *out = o;
+        }
+        return;
+    }
+    const uint32_t v = ~static_cast<uint32_t>(best & 0xFFFFFFFFull);
+    uint32_t *base_next = g.cbase + ((r + 1u) & 1u) * kCandNodes;
+    uint32_t *dec_next = g.cdec + ((r + 1u) % 3u) * kCandNodes;
+    for (uint32_t s = blk * blockDim.x + threadIdx.x; s < nn; s += nblk * blockDim.x) {
+        base_next[s] = (base[s] - dec_prev[s]) | (g.cnode[s] == v ? kChosen : 0u);
+        dec_next[s] = 0u;
+    }
+    if (blk == 0 && threadIdx.x == 0) {
+        g.seeds[r] = v;
+        atomicOr(&g.gain[v], kChosen);
+        const uint32_t c = v >> kL1Shift;
+        if (g.mark) atomicOr(&g.dirty[c >> 5], 1u << (c & 31u));
+        StepHdr o = h;
+        o.r = r + 1u;
+        o.phase = r + 1u >= g.k ? kStepDone : kStepRound;
+        *out = o;
+    }
+    cover_seed<true>(g, r, v, blk, nblk, nn, &L);
+}
+
+// One step of every job (blockIdx.y = job). REFRESH uses the first nbmax
+// blocks of a job, SELECT its block 0, ROUND all of them.
+__global__ __launch_bounds__(kThreads) void greedy_step_kernel(const GreedyState *jobs, uint32_t step) {
+    __shared__ unsigned long long smem[kThreads / kWave];
+    __shared__ union {
+        SelectLds sel;
+        RoundLds rnd;
+    } lds;
+    const GreedyState &g = jobs[blockIdx.y];
+    const StepHdr h = g.hdr[step & 1u];
+    StepHdr *out = g.hdr + ((step + 1u) & 1u);
+    const uint32_t blk = blockIdx.x, nblk = gridDim.x;
+    if (h.phase == kStepRound) {
+        step_round(g, h, out, blk, nblk, smem, lds.rnd);
+    } else if (h.phase == kStepRefresh) {
+        if (blk < g.nbmax) refresh_block(g, h.r, blk, g.nbmax, smem);
+        if (blk == 0 && threadIdx.x == 0) {
+            StepHdr o = h;
+            o.phase = kStepSelect;
+            *out = o;
+        }
+    } else if (h.phase == kStepSelect) {
+        if (blk == 0) step_select(g, h, out, lds.sel);
+    } else if (blk == 0 && threadIdx.x == 0) {
+        *out = h;
+    }
 }
 
 // LDS of the one-workgroup rounds.
@@ -831,6 +1224,60 @@ im_status coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const u
     return IM_OK;
 }
 
+__global__ void step_init_kernel(const GreedyState *jobs, uint32_t nj) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nj) return;
+    StepHdr h{};
+    h.phase = jobs[j].k ? kStepRefresh : kStepDone;
+    jobs[j].hdr[0] = h;
+}
+
+// Launch greedy steps on `dgs` (nj jobs, the step headers of job j at
+// dhdr[2j], [2j+1]) until every job has its k seeds. Each pass launches
+// what the slowest job needs at the context's running refresh rate, then
+// reads the headers back once.
+static im_status run_steps(im_ctx *ctx, const GreedyState *dgs, StepHdr *dhdr, const uint32_t *ks, uint32_t nj,
+                           dim3 grid) {
+    hipStream_t st = ctx->stream;
+    step_init_kernel<<<(nj + 255) / 256, 256, 0, st>>>(dgs, nj);
+    std::vector<StepHdr> hh(2ull * nj);
+    uint32_t max_k = 0;
+    for (uint32_t j = 0; j < nj; ++j) max_k = std::max(max_k, ks[j]);
+    const uint64_t cap = 3ull * max_k + 64;  // a refresh pair always leads to a round
+    uint32_t step = 0, remaining = max_k;
+    bool first = true;
+    for (;;) {
+        const double rate = ctx->greedy_stall_rate;
+        const uint32_t est = remaining + static_cast<uint32_t>(2.0 * rate * remaining + 0.999) + (first ? 4u : 2u);
+        first = false;
+        for (uint32_t i = 0; i < est; ++i) greedy_step_kernel<<<grid, kThreads, 0, st>>>(dgs, step++);
+        IM_HIP(hipGetLastError());
+        IM_HIP(hipMemcpyAsync(hh.data(), dhdr, sizeof(StepHdr) * 2 * nj, hipMemcpyDeviceToHost, st));
+        IM_HIP(hipStreamSynchronize(st));
+        remaining = 0;
+        uint64_t stalls = 0, rounds = 0;
+        for (uint32_t j = 0; j < nj; ++j) {
+            const StepHdr &x = hh[2ull * j + (step & 1u)];
+            if (x.phase != kStepDone) remaining = std::max<uint32_t>(remaining, ks[j] - std::min(ks[j], x.r));
+            stalls += x.stalls;
+            rounds += x.r;
+        }
+        if (remaining == 0) {
+            bool all_done = true;
+            for (uint32_t j = 0; j < nj; ++j) all_done = all_done && hh[2ull * j + (step & 1u)].phase == kStepDone;
+            if (all_done) {
+                if (rounds) ctx->greedy_stall_rate = 0.5 * ctx->greedy_stall_rate + 0.5 * double(stalls) / double(rounds);
+                return IM_OK;
+            }
+            remaining = 1;
+        }
+        if (step > cap) {
+            set_error("max coverage: greedy steps did not finish");
+            return IM_E_DEVICE;
+        }
+    }
+}
+
 im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k, uint32_t *seeds_host,
                        uint64_t *cov) {
     im_ctx *ctx = p->ctx;
@@ -859,7 +1306,9 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
                  o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
                  o_m2 = take(8ull * n2), o_job = take(sizeof(GreedyState)),
-                 o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096);
+                 o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096),
+                 o_hdr = take(2 * sizeof(StepHdr)), o_cnode = take(4ull * kCandNodes),
+                 o_cbase = take(8ull * kCandNodes), o_cdec = take(12ull * kCandNodes);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
@@ -923,9 +1372,21 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     if (big)
         fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
     g.nbmax = rgrid;
-    for (uint32_t r = 0; r < big; ++r) {
-        refresh_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
-        cover_kernel<<<cgrid, kThreads, 0, st>>>(g, r);
+    const uint32_t want = std::min<uint32_t>(ctx->greedy_candidates, kCandMax);
+    if (big && want) {
+        g.hdr = reinterpret_cast<StepHdr *>(base + o_hdr);
+        g.cnode = at32(o_cnode);
+        g.cbase = at32(o_cbase);
+        g.cdec = at32(o_cdec);
+        g.want = want;
+        auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
+        IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
+        IM_TRY(run_steps(ctx, dg, g.hdr, &k, 1, dim3(std::max(rgrid, cgrid), 1)));
+    } else {
+        for (uint32_t r = 0; r < big; ++r) {
+            refresh_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
+            cover_kernel<<<cgrid, kThreads, 0, st>>>(g, r);
+        }
     }
     if (big < k) {
         fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32, 0u);
@@ -1029,7 +1490,8 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
                  o_cov = take(8ull * nj), o_covc = take(8ull * nj), o_bits = take(4 * words * nj),
                  o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj),
                  o_dirty = take(4ull * nj * ((n1 + 31) / 32)),
-                 o_bmax = take(8ull * nj * 1024);
+                 o_bmax = take(8ull * nj * 1024), o_hdr = take(2 * sizeof(StepHdr) * nj),
+                 o_cnode = take(4ull * kCandNodes * nj), o_cbase = take(8ull * kCandNodes * nj), o_cdec = take(12ull * kCandNodes * nj);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto *gains = reinterpret_cast<uint32_t *>(base + o_gain);
@@ -1074,6 +1536,11 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.cov = covs + j;
         g.dirty = reinterpret_cast<uint32_t *>(base + o_dirty) + uint64_t(j) * ((n1 + 31) / 32);
         g.nsets = cj.end - cj.begin;
+        g.hdr = reinterpret_cast<StepHdr *>(base + o_hdr) + 2ull * j;
+        g.cnode = reinterpret_cast<uint32_t *>(base + o_cnode) + uint64_t(kCandNodes) * j;
+        g.cbase = reinterpret_cast<uint32_t *>(base + o_cbase) + 2ull * kCandNodes * j;
+        g.cdec = reinterpret_cast<uint32_t *>(base + o_cdec) + 3ull * kCandNodes * j;
+        g.want = std::min<uint32_t>(ctx->greedy_candidates_batch, kCandMax);
     }
     IM_HIP(hipMemcpyAsync(djt, jt.data(), sizeof(JobTable) * nj, hipMemcpyHostToDevice, st));
     IM_HIP(hipMemcpyAsync(dgs, gs.data(), sizeof(GreedyState) * nj, hipMemcpyHostToDevice, st));
@@ -1109,9 +1576,16 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         const uint32_t per = batch_blocks_per_job(cu, nj);
         const uint32_t rx = batch_refresh_blocks(cu, nj, n1);
         const uint32_t cx = std::min<uint32_t>(per, std::max<uint32_t>(1, grid_of(max_entries * 16, kThreads, cu * 4)));
-        for (uint32_t r = 0; r < max_k; ++r) {
-            batch_refresh_kernel<<<dim3(rx, nj), kThreads, 0, st>>>(dgs, r);
-            batch_cover_kernel<<<dim3(cx, nj), kThreads, 0, st>>>(dgs, r);
+        if (ctx->greedy_candidates_batch) {
+            std::vector<uint32_t> ks(nj);
+            for (uint32_t j = 0; j < nj; ++j) ks[j] = jobs[j].k;
+            IM_TRY(run_steps(ctx, dgs, reinterpret_cast<StepHdr *>(base + o_hdr), ks.data(), nj,
+                             dim3(std::max(rx, cx), nj)));
+        } else {
+            for (uint32_t r = 0; r < max_k; ++r) {
+                batch_refresh_kernel<<<dim3(rx, nj), kThreads, 0, st>>>(dgs, r);
+                batch_cover_kernel<<<dim3(cx, nj), kThreads, 0, st>>>(dgs, r);
+            }
         }
     }
     if (tot_stare) {

@@ -74,6 +74,9 @@ struct im_ctx {
     uint64_t greedy_mark_min_chunks = 1u << 16;
     uint32_t greedy_cover_blocks = 0;  // 0: automatic
     uint32_t ic_edge_budget = 16384;
+    uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
+    uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
+    double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
 
     // optional event timing of the main sampler launches
     bool timing = false;

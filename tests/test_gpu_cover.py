@@ -110,25 +110,29 @@ def test_estimate_inf_matches_oracle(im, ctx, oracle_lib, name, model):
     assert T == math.ceil(lam2)
 
 
-@pytest.mark.parametrize("limit,mark", [(0, 1 << 62), (0, 0), (1 << 62, 1 << 62)])
+@pytest.mark.parametrize("limit,mark,cand", [(0, 1 << 62, 0), (0, 0, 0), (1 << 62, 1 << 62, 0),
+                                             (0, 1 << 62, 32), (0, 0, 32), (0, 1 << 62, 1), (0, 0, 1),
+                                             (0, 1 << 62, 64), (0, 0, 5)])
 @pytest.mark.parametrize("name", ["nethept", "rmat16", "cl_small"])
-def test_greedy_paths_agree(im, ctx, pools, name, limit, mark):
-    """Every greedy schedule (per-round grid launches re-checking holders or
-    re-deriving marked chunks, all rounds in one workgroup) gives the
-    oracle's seeds."""
+def test_greedy_paths_agree(im, ctx, pools, name, limit, mark, cand):
+    """Every greedy schedule gives the oracle's seeds: grid-wide rounds over
+    candidate chunks (cand > 0; 1 re-selects after nearly every round) or
+    two launches per round (cand = 0), re-checking holders or re-deriving
+    marked chunks (mark = 0), or all rounds in one workgroup."""
     g, dg, og, p, op = pools[name]
-    note(f"greedy path limit={limit} mark={mark} {name}")
-    old = ctx.get_param("greedy_wg_max_entries"), ctx.get_param("greedy_mark_min_chunks")
-    ctx.set_param("greedy_wg_max_entries", limit)
-    ctx.set_param("greedy_mark_min_chunks", mark)
+    note(f"greedy path limit={limit} mark={mark} cand={cand} {name}")
+    names = ("greedy_wg_max_entries", "greedy_mark_min_chunks", "greedy_candidates")
+    old = [ctx.get_param(x) for x in names]
+    for x, v in zip(names, (limit, mark, cand)):
+        ctx.set_param(x, v)
     try:
         for k in (1, 50, 300):
             seeds, cov = p.max_coverage(k)
             oseeds, ocov = op.max_coverage(k)
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
     finally:
-        ctx.set_param("greedy_wg_max_entries", old[0])
-        ctx.set_param("greedy_mark_min_chunks", old[1])
+        for x, v in zip(names, old):
+            ctx.set_param(x, v)
 
 
 def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):

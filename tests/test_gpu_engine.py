@@ -90,22 +90,25 @@ def _engine(im, ctx, graphs, cases, budget=16 << 30, max_active=64):
     return res, steps
 
 
-@pytest.mark.parametrize("limit,mark", [(None, None), (0, None), (0, 0), (1 << 62, None)])
-def test_engine_mix_matches_single(im, ctx, graphs, limit, mark):
+@pytest.mark.parametrize("limit,mark,cand", [(None, None, None), (0, None, None), (0, 0, None),
+                                             (1 << 62, None, None), (0, None, 0), (0, 0, 1), (0, 1 << 62, 64)])
+def test_engine_mix_matches_single(im, ctx, graphs, limit, mark, cand):
     """limit: the one-workgroup greedy threshold (None = default; 0 forces
-    the batched per-round launches, 2^62 one workgroup per job); mark: the
-    chunk count above which the cover step marks touched chunks (0: always)."""
-    note(f"engine mix of {len(MIX)} queries vs single-query runs, greedy limit {limit} mark {mark}")
-    old = ctx.get_param("greedy_wg_max_entries"), ctx.get_param("greedy_mark_min_chunks")
-    if limit is not None:
-        ctx.set_param("greedy_wg_max_entries", limit)
-    if mark is not None:
-        ctx.set_param("greedy_mark_min_chunks", mark)
+    the batched grid-wide rounds, 2^62 one workgroup per job); mark: the
+    chunk count above which the cover step marks touched chunks (0: always);
+    cand: candidate chunks of the grid-wide rounds (0: two launches per
+    round). The single-query runs use the defaults."""
+    note(f"engine mix of {len(MIX)} queries vs single-query runs, greedy limit {limit} mark {mark} cand {cand}")
+    names = ("greedy_wg_max_entries", "greedy_mark_min_chunks", "greedy_candidates_batch")
+    old = [ctx.get_param(x) for x in names]
+    for x, v in zip(names, (limit, mark, cand)):
+        if v is not None:
+            ctx.set_param(x, v)
     try:
         res, _ = _engine(im, ctx, graphs, MIX)
     finally:
-        ctx.set_param("greedy_wg_max_entries", old[0])
-        ctx.set_param("greedy_mark_min_chunks", old[1])
+        for x, v in zip(names, old):
+            ctx.set_param(x, v)
     for case, r in zip(MIX, res):
         note(f"compare {case}")
         _same(r, _single(graphs, case))
