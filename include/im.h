@@ -310,7 +310,12 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       and the candidates when it does not); 0: two launches every round
  *       (default 0);
  *   IM_PARAM_GREEDY_CANDIDATES_BATCH the same for the engine's batched
- *       Max-Coverage of many queries (default 32).
+ *       Max-Coverage of many queries (default 32);
+ *   IM_PARAM_DSSA_DRAW_AHEAD        when im_dssa on the LT model must draw
+ *       the RR sets of iteration t, it draws up to this many times 2 N_t
+ *       sets in the same launches (the sets of later iterations are
+ *       identical whenever they are drawn; a launch lasts about as long as
+ *       its longest walk), 1..64 (default 4; IC draws are not affected).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -321,7 +326,8 @@ typedef enum {
     IM_PARAM_GREEDY_COVER_BLOCKS = 4,
     IM_PARAM_IC_EDGE_BUDGET = 5,
     IM_PARAM_GREEDY_CANDIDATES = 6,
-    IM_PARAM_GREEDY_CANDIDATES_BATCH = 7
+    IM_PARAM_GREEDY_CANDIDATES_BATCH = 7,
+    IM_PARAM_DSSA_DRAW_AHEAD = 8
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -343,6 +343,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 64) break;
         c->greedy_candidates_batch = static_cast<uint32_t>(value);
         return IM_OK;
+    case IM_PARAM_DSSA_DRAW_AHEAD:
+        if (value < 1 || value > 64) break;
+        c->dssa_draw_ahead = static_cast<uint32_t>(value);
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -375,6 +379,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_GREEDY_CANDIDATES_BATCH:
         *value = c->greedy_candidates_batch;
+        return IM_OK;
+    case IM_PARAM_DSSA_DRAW_AHEAD:
+        *value = c->dssa_draw_ahead;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
@@ -870,6 +877,9 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     double ms_draw = 0.0, ms_cover_last = 0.0;  // wall time of the last own draw of N_t sets / last cover
     std::vector<uint32_t> seeds(k);
     const uint64_t n1 = uint64_t(std::ceil(c.lambda));
+    // sets the last possible iteration uses: 2 N_t for the first N_t >= N_max
+    uint64_t most = 2 * n1;
+    while (double(most / 2) < c.n_max && most < (1ull << 62)) most *= 2;
     im_status rc = IM_OK;
     for (uint32_t t = 1;; ++t) {
         const uint64_t nt = n1 << (t - 1);
@@ -883,7 +893,13 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
             }
         }
         const double t_fresh = now_ms();
-        if ((rc = pool_extend_to(pool, 2 * nt, nullptr))) break;
+        // an LT sampler launch of one query lasts about as long as its
+        // longest walk whatever its size, so a draw may also take the next
+        // iterations' sets (identical sets: they depend only on their index)
+        uint64_t target = 2 * nt;
+        if (model == IM_LT && pool->count < target && ctx->dssa_draw_ahead > 1)
+            target = std::max(target, std::min(most, 2 * nt * ctx->dssa_draw_ahead));
+        if ((rc = pool_extend_to(pool, target, nullptr))) break;
         const double ms_fresh = now_ms() - t_fresh;  // this iteration's own draw, if any
         st->ms_sample += now_ms() - t0;
         // draw the next iteration's new sets [2 N_t, 4 N_t) while this one is
@@ -892,8 +908,9 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         // last iteration's cover time, or about 15 us per greedy round
         if (ms_fresh > 0) ms_draw = ms_fresh;
         const double est_cover = std::max(ms_cover_last, 0.015 * k);
-        if (aux && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw)
-            spec.start(aux, pool, 2 * nt, 2 * nt);
+        if (aux && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw &&
+            pool->count < 4 * nt)
+            spec.start(aux, pool, pool->count, 4 * nt - pool->count);
         uint64_t cov = 0, cov_c = 0;
         t0 = now_ms();
         if ((rc = max_coverage(pool, 0, nt, k, seeds.data(), &cov))) break;
@@ -940,6 +957,11 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     if (rc == IM_OK) rc = rs;
     if (rc == IM_OK) {
         st->edges = pool->edges;
+        if (pool->count > st->n_sets) {
+            // drawn ahead (LT only): an LT walk examines one in-edge list
+            // per node it holds, so the used sets' edges are their sizes
+            rc = to_host_sync(ctx, &st->edges, static_cast<const uint64_t *>(pool->poff.ptr) + st->n_sets, 8);
+        }
         std::memcpy(seeds_out, seeds.data(), 4ull * k);
     }
     im_pool_free(pool);

@@ -76,6 +76,7 @@ struct im_ctx {
     uint32_t ic_edge_budget = 16384;
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
+    uint32_t dssa_draw_ahead = 4;           // im_dssa on LT: a draw takes up to this many iterations' sets
     double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
 
     // optional event timing of the main sampler launches

@@ -90,3 +90,28 @@ def test_dssa_speculation_changes_nothing(im, ctx, name, model, k):
         assert s1.tolist() == s0.tolist()
         for key in ("iterations", "n_sets", "cov", "cov_c", "edges", "it_cov", "it_cov_c", "eps_t", "i_hat"):
             assert st1[key] == st0[key], key
+
+
+@pytest.mark.parametrize("name,k", [("rmat16", 40), ("cl_small", 5), ("rmat20", 100)])
+@pytest.mark.parametrize("ahead", [1, 2, 64])
+def test_dssa_draw_ahead_changes_nothing(im, ctx, oracle_lib, name, k, ahead):
+    """LT D-SSA drawing later iterations' sets early gives the oracle's run,
+    edges included (they count only the sets the query used)."""
+    g = synth.make(name)
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_lt=g.w_lt)
+    og = oracle_lib.Graph(1, g.n, g.src, g.dst, g.w_lt)
+    note(f"dssa draw-ahead {ahead} {name} k={k}")
+    old = ctx.get_param("dssa_draw_ahead"), ctx.get_param("dssa_speculate")
+    try:
+        ctx.set_param("dssa_draw_ahead", ahead)
+        for spec in (1, 0):
+            ctx.set_param("dssa_speculate", spec)
+            for key in (0, 3):
+                seeds, st = dg.dssa(1, k, 0.1, 1.0 / g.n, key)
+                oseeds, ost = og.dssa(k, 0.1, 1.0 / g.n, key)
+                assert seeds.tolist() == oseeds.tolist()
+                for kk in ("iterations", "n_sets", "cov", "cov_c", "edges", "it_sets", "it_cov", "it_cov_c"):
+                    assert st[kk] == ost[kk], (kk, st[kk], ost[kk])
+    finally:
+        ctx.set_param("dssa_draw_ahead", old[0])
+        ctx.set_param("dssa_speculate", old[1])
