@@ -25,6 +25,7 @@ CANDIDATES = {
     "ic_edge_budget": [512, 1024, 2048, 4096, 8192, 16384, 65536],
     "greedy_candidates": [0, 8, 16, 32, 64],
     "greedy_candidates_batch": [0, 8, 16, 32, 64],
+    "dssa_draw_ahead": [1, 2, 4, 8],
 }
 
 
