@@ -315,7 +315,12 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       the RR sets of iteration t, it draws up to this many times 2 N_t
  *       sets in the same launches (the sets of later iterations are
  *       identical whenever they are drawn; a launch lasts about as long as
- *       its longest walk), 1..64 (default 4; IC draws are not affected).
+ *       its longest walk), 1..64 (default 4; IC draws are not affected);
+ *   IM_PARAM_GREEDY_GRAPH           1: the k rounds of a grid-wide
+ *       Max-Coverage of one range (two launches per round) are replayed
+ *       from a HIP graph built the second time the same round count and
+ *       launch shape recur (kept per context, at most 32); 0: launched one
+ *       by one (default 1).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -327,7 +332,8 @@ typedef enum {
     IM_PARAM_IC_EDGE_BUDGET = 5,
     IM_PARAM_GREEDY_CANDIDATES = 6,
     IM_PARAM_GREEDY_CANDIDATES_BATCH = 7,
-    IM_PARAM_DSSA_DRAW_AHEAD = 8
+    IM_PARAM_DSSA_DRAW_AHEAD = 8,
+    IM_PARAM_GREEDY_GRAPH = 9
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -347,6 +347,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value < 1 || value > 64) break;
         c->dssa_draw_ahead = static_cast<uint32_t>(value);
         return IM_OK;
+    case IM_PARAM_GREEDY_GRAPH:
+        if (value > 1) break;
+        c->greedy_graph = value != 0;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -383,6 +387,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
     case IM_PARAM_DSSA_DRAW_AHEAD:
         *value = c->dssa_draw_ahead;
         return IM_OK;
+    case IM_PARAM_GREEDY_GRAPH:
+        *value = c->greedy_graph ? 1 : 0;
+        return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
     return IM_E_ARG;
@@ -418,6 +425,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     if (c->ev_group) (void)hipEventDestroy(c->ev_group);
+    free_round_graphs(c);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits,
                       &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);

@@ -1278,6 +1278,92 @@ static im_status run_steps(im_ctx *ctx, const GreedyState *dgs, StepHdr *dhdr, c
     }
 }
 
+}  // namespace im
+
+// Cached HIP graphs of the per-round launch pairs (refresh, cover) of one
+// range: the kernels read the greedy state through a fixed device address,
+// so a graph replays for any range with the same round count and launch
+// shape. A shape is built into a graph the second time it is asked for.
+struct RoundGraphCache {
+    struct Entry {
+        const void *dg;
+        uint32_t k, rgrid, cgrid;
+        uint64_t last;
+        hipGraphExec_t exec;  // null: seen once
+    };
+    std::vector<Entry> e;
+    uint64_t tick = 0;
+};
+
+void free_round_graphs(im_ctx *ctx) {
+    if (!ctx->round_graphs) return;
+    for (auto &x : ctx->round_graphs->e)
+        if (x.exec) (void)hipGraphExecDestroy(x.exec);
+    delete ctx->round_graphs;
+    ctx->round_graphs = nullptr;
+}
+
+namespace im {
+
+// The graph of rounds [0, k) for state dg, or null when this shape has not
+// been seen before (the caller then launches the rounds itself).
+static im_status round_graph(im_ctx *ctx, const GreedyState *dg, uint32_t k, uint32_t rgrid, uint32_t cgrid,
+                      hipGraphExec_t *out) {
+    constexpr size_t kMaxGraphs = 32;
+    *out = nullptr;
+    if (!ctx->round_graphs) ctx->round_graphs = new RoundGraphCache();
+    RoundGraphCache &c = *ctx->round_graphs;
+    ++c.tick;
+    RoundGraphCache::Entry *hit = nullptr;
+    for (auto &x : c.e)
+        if (x.dg == dg && x.k == k && x.rgrid == rgrid && x.cgrid == cgrid) hit = &x;
+    if (!hit) {
+        if (c.e.size() >= kMaxGraphs) {
+            auto old = std::min_element(c.e.begin(), c.e.end(),
+                                        [](const auto &a, const auto &b) { return a.last < b.last; });
+            if (old->exec) (void)hipGraphExecDestroy(old->exec);
+            c.e.erase(old);
+        }
+        c.e.push_back({dg, k, rgrid, cgrid, c.tick, nullptr});
+        return IM_OK;
+    }
+    hit->last = c.tick;
+    if (!hit->exec) {
+        hipGraph_t graph = nullptr;
+        IM_HIP(hipGraphCreate(&graph, 0));
+        hipGraphNode_t prev = nullptr;
+        hipError_t e = hipSuccess;
+        for (uint32_t r = 0; r < k && e == hipSuccess; ++r) {
+            for (int step = 0; step < 2 && e == hipSuccess; ++step) {
+                const GreedyState *arg_dg = dg;
+                uint32_t arg_r = r;
+                void *args[] = {&arg_dg, &arg_r};
+                hipKernelNodeParams kp{};
+                kp.func = step == 0 ? reinterpret_cast<void *>(batch_refresh_kernel)
+                                    : reinterpret_cast<void *>(batch_cover_kernel);
+                kp.gridDim = dim3(step == 0 ? rgrid : cgrid, 1, 1);
+                kp.blockDim = dim3(kThreads, 1, 1);
+                kp.sharedMemBytes = 0;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                hipGraphNode_t node = nullptr;
+                e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+                prev = node;
+            }
+        }
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            set_error("max coverage round graph: %s", hipGetErrorString(e));
+            return IM_E_DEVICE;
+        }
+        hit->exec = exec;
+    }
+    *out = hit->exec;
+    return IM_OK;
+}
+
 im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k, uint32_t *seeds_host,
                        uint64_t *cov) {
     im_ctx *ctx = p->ctx;
@@ -1382,10 +1468,20 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
         IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
         IM_TRY(run_steps(ctx, dg, g.hdr, &k, 1, dim3(std::max(rgrid, cgrid), 1)));
-    } else {
-        for (uint32_t r = 0; r < big; ++r) {
-            refresh_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
-            cover_kernel<<<cgrid, kThreads, 0, st>>>(g, r);
+    } else if (big) {
+        hipGraphExec_t exec = nullptr;
+        auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
+        if (ctx->greedy_graph) {
+            IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
+            IM_TRY(round_graph(ctx, dg, big, rgrid, cgrid, &exec));
+        }
+        if (exec) {
+            IM_HIP(hipGraphLaunch(exec, st));
+        } else {
+            for (uint32_t r = 0; r < big; ++r) {
+                refresh_kernel<<<rgrid, kThreads, 0, st>>>(g, r);
+                cover_kernel<<<cgrid, kThreads, 0, st>>>(g, r);
+            }
         }
     }
     if (big < k) {

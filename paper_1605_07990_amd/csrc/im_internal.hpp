@@ -78,6 +78,8 @@ struct im_ctx {
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 4;           // im_dssa on LT: a draw takes up to this many iterations' sets
     double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
+    bool greedy_graph = true;         // replay cached graphs of a range's per-round launches
+    struct RoundGraphCache *round_graphs = nullptr;
 
     // optional event timing of the main sampler launches
     bool timing = false;
@@ -92,6 +94,9 @@ struct im_ctx {
     size_t slot_budget = 8ull << 30;  // long-path slot memory cap
     bool speculate = true;
 };
+
+// Destroys the cached greedy round graphs of a context (cover.hip).
+void free_round_graphs(im_ctx *ctx);
 
 struct im_graph {
     im_ctx *ctx = nullptr;

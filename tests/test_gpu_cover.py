@@ -155,3 +155,27 @@ def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
     finally:
         ctx.set_param("greedy_wg_max_entries", old)
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_greedy_round_graph_replays(im, ctx, pools, graph):
+    """The per-round launches of one range replayed from the cached graph
+    (built the second time a round count and launch shape recur) give the
+    oracle's seeds on every call, across ranges of one shape and of several
+    and across pools."""
+    note(f"greedy round graph {graph}")
+    old = ctx.get_param("greedy_graph"), ctx.get_param("greedy_candidates")
+    ctx.set_param("greedy_graph", graph)
+    ctx.set_param("greedy_candidates", 0)
+    try:
+        for rep in range(3):
+            for name in ("nethept", "rmat16"):
+                g, dg, og, p, op = pools[name]
+                c = p.count
+                for b, e, k in ((0, c, 50), (0, c // 2, 50), (c // 2, c, 50), (0, c, 7), (3, c - 5, 50)):
+                    seeds, cov = p.max_coverage(k, b, e)
+                    oseeds, ocov = op.max_coverage(k, b, e)
+                    assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (rep, name, b, e, k)
+    finally:
+        ctx.set_param("greedy_graph", old[0])
+        ctx.set_param("greedy_candidates", old[1])
