@@ -83,10 +83,10 @@ def measured_traffic(kernel: str):
     return rec["hbm_bytes_per_dispatch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
-def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_gib: int = 16, trials: int = 3) -> dict:
+def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_bytes: int = 16 << 30, trials: int = 3) -> dict:
     """Measured random-gather bandwidth (GB/s of segment bytes) per segment
     size, from the probe library: hashed random segment-aligned reads of a
-    buffer far larger than the last-level cache."""
+    buffer (by default far larger than the 256 MB last-level cache)."""
     import ctypes
 
     lib = ctypes.CDLL(str(ROOT / "paper_1605_07990_amd" / "libimprobe.so"))
@@ -96,7 +96,7 @@ def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_gib: int = 16, trials:
     out = {}
     for seg in segs:
         g = ctypes.c_double(0.0)
-        if lib.im_probe_gather(0, buffer_gib << 30, seg, trials, ctypes.byref(g)) != 0:
+        if lib.im_probe_gather(0, buffer_bytes, seg, trials, ctypes.byref(g)) != 0:
             raise RuntimeError(f"gather probe failed for {seg}-byte segments")
         out[seg] = round(g.value, 1)
     return out
@@ -137,10 +137,16 @@ def roofline(kt: dict, model: int) -> dict:
         out["gather_gbs"] = GATHER
         out["gather_segment_bytes"] = seg
         out["gather_frac"] = round(achieved / GATHER[seg], 5)
+        if seg in GATHER_MALL:
+            # the same probe on a buffer the last-level cache holds, the
+            # roofline of graphs that fit there (R-MAT-20: 143 MB)
+            out["gather_cache_resident_gbs"] = GATHER_MALL[seg]
+            out["gather_cache_resident_frac"] = round(achieved / GATHER_MALL[seg], 5)
     return out
 
 
 GATHER = {}
+GATHER_MALL = {}
 
 
 def log_uniform_k(rng, hi: int, n: int) -> int:
@@ -393,8 +399,20 @@ def run_twitter(args, im, ctx, sync):
     ctx.read_timing(reset=True)
     sync()
     lat, sets, edges, per_k = [], 0, 0, {}
+    budget = int(args.pool_budget_gb * (1 << 30))
     t0 = time.perf_counter()
     for step in range(args.steps):
+        if args.engine:
+            res, l_ = run_engine_batch(im, ctx, dg, im.IM_IC, "dssa", [(k, 0.1, delta, step) for k in ks], budget,
+                                       len(ks))
+            lat += l_
+            for k, (_, st), ms in zip(ks, res, l_):
+                progress(f"step {step} k={k}: {ms:.1f} ms (engine), {st['n_sets']} sets")
+                sets += st["n_sets"]
+                edges += st["edges"]
+                per_k.setdefault(k, []).append({"ms": round(ms, 3), "n_sets": st["n_sets"], "edges": st["edges"],
+                                                "iterations": st["iterations"]})
+            continue
         for k in ks:
             q0 = time.perf_counter()
             _, st = dg.dssa(im.IM_IC, k, 0.1, delta, step)
@@ -411,7 +429,6 @@ def run_twitter(args, im, ctx, sync):
     dt = time.perf_counter() - t0
     kt = ctx.read_timing(reset=True)
     ctx.set_timing(False)
-    dg.close()
     out = {"value": round(sets / dt, 1), "ms_per_step": round(dt * 1e3 / args.steps, 4),
            "config": {"workload": "Twitter-shaped IC weighted cascade D-SSA, k in {1, 100, 1000}", "n": n,
                       "m": g.m, "k": ks, "eps": 0.1, "delta": "1/n", "queries_per_step": len(ks)},
@@ -419,6 +436,21 @@ def run_twitter(args, im, ctx, sync):
            "p99_ms": round(percentile(lat, 99), 3), "per_k": per_k,
            "graph_generate_s": round(t_gen, 1), "graph_load_s": round(t_load, 2),
            "roofline": roofline(kt, 0)}
+    if args.engine:
+        out["config"]["workload"] += ", concurrent through the engine"
+    if args.compare_plain:
+        # the same step-0 queries one after another through im_dssa
+        sync()
+        p0 = time.perf_counter()
+        psets = 0
+        for k in ks:
+            _, st = dg.dssa(im.IM_IC, k, 0.1, delta, 0)
+            psets += st["n_sets"]
+        sync()
+        pdt = time.perf_counter() - p0
+        out["one_query_at_a_time"] = {"ms": round(pdt * 1e3, 3), "rr_sets_per_s": round(psets / pdt, 1),
+                                      "speedup_of_this_run": round(pdt / (dt / args.steps), 3)}
+    dg.close()
 
     def cpu(budget_s):
         import oracle
@@ -456,6 +488,8 @@ def main() -> int:
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--compare-plain", action="store_true", help="also time the queries one at a time")
+    ap.add_argument("--engine", action="store_true",
+                    help="Twitter-shaped workload: run each step's queries concurrently through the engine")
     ap.add_argument("--ks", type=int, nargs="*", default=None, help="Twitter-shaped workload: the k values")
     ap.add_argument("--queries-per-step", type=int, default=1,
                     help="R-MAT-20: concurrent D-SSA queries per step through the multi-query engine")
@@ -487,6 +521,7 @@ def main() -> int:
 
     if not args.no_gather_probe:
         GATHER.update(gather_bandwidth())
+        GATHER_MALL.update(gather_bandwidth(segs=(64, 128, 256), buffer_bytes=128 << 20))
     ctx = im.Context(0)
     if args.greedy_wg_max_entries is not None:
         ctx.set_param("greedy_wg_max_entries", args.greedy_wg_max_entries)

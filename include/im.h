@@ -320,7 +320,7 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       Max-Coverage of one range (two launches per round) are replayed
  *       from a HIP graph built the second time the same round count and
  *       launch shape recur (kept per context, at most 32); 0: launched one
- *       by one (default 1).
+ *       by one (default 0: replay measured slower than stream launches).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {

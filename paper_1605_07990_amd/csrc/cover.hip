@@ -1388,10 +1388,13 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         off = (off + bytes + 255) & ~size_t(255);
         return at;
     };
+    // the greedy state first: its address stays put from call to call, so
+    // cached round graphs that read it through that address replay
+    const size_t o_job = take(sizeof(GreedyState));
     const size_t o_gain = take(4ull * n), o_fill = take(4ull * n), o_ioff = take(8ull * (n + 1)),
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
                  o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
-                 o_m2 = take(8ull * n2), o_job = take(sizeof(GreedyState)),
+                 o_m2 = take(8ull * n2),
                  o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096),
                  o_hdr = take(2 * sizeof(StepHdr)), o_cnode = take(4ull * kCandNodes),
                  o_cbase = take(8ull * kCandNodes), o_cdec = take(12ull * kCandNodes);

@@ -78,7 +78,7 @@ struct im_ctx {
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 4;           // im_dssa on LT: a draw takes up to this many iterations' sets
     double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
-    bool greedy_graph = true;         // replay cached graphs of a range's per-round launches
+    bool greedy_graph = false;        // replay cached graphs of a range's per-round launches
     struct RoundGraphCache *round_graphs = nullptr;
 
     // optional event timing of the main sampler launches
