@@ -102,9 +102,12 @@ def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_bytes: int = 16 << 30,
     return out
 
 
-def roofline(kt: dict, model: int) -> dict:
+def roofline(kt: dict, model: int, traffic_measured_here: bool = False) -> dict:
     """Roofline of the main sampler kernel from its event timing: algorithmic
-    bytes per launch over the mean launch duration, against HBM peak."""
+    bytes per launch over the mean launch duration, against HBM peak.
+    `traffic` (HBM bytes per launch from the committed counter runs) is
+    reported only for the configuration those runs measured, since bytes
+    per launch follow the launch size."""
     launches = max(kt["sample_launches"], 1)
     if model == 1:
         total = lt_bytes(kt["sample_steps"], kt["sample_sets"])
@@ -116,7 +119,7 @@ def roofline(kt: dict, model: int) -> dict:
     ms_per_launch = kt["sample_ms"] / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
     sec = kt["sample_ms"] * 1e-3
-    traffic = measured_traffic("lt_main_kernel" if model == 1 else "ic_main_kernel")
+    traffic = measured_traffic("lt_main_kernel" if model == 1 else "ic_main_kernel") if traffic_measured_here else None
     out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "launches": kt["sample_launches"],
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
@@ -235,7 +238,8 @@ def run_rmat20(args, im, ctx, sync):
            "p99_ms": round(percentile(lat, 99), 3), "rr_sets_per_query": sets // max(args.steps * B, 1),
            "iterations_per_query": sorted(set(iters)),
            "stage_ms_per_query": {k_: round(v_ / args.steps, 3) for k_, v_ in stage.items()},
-           "roofline": roofline(kt, 1)}
+           "roofline": roofline(kt, 1, traffic_measured_here=(B == 1 and not args.param and not args.no_speculate
+                                                               and args.greedy_wg_max_entries is None))}
 
     def cpu(budget_s):
         import oracle
@@ -371,7 +375,9 @@ def run_serving(args, im, ctx, sync):
            "edges_per_s": round(r["edges_per_s"], 1), "p50_ms": round(r["p50_ms"], 3),
            "p99_ms": round(r["p99_ms"], 3), "achieved_qps": round(r["achieved_qps"], 3),
            "offered_qps": round(r["offered_qps"], 3), "engine_steps": r["engine_steps"],
-           "max_active": r["max_active"], "roofline": roofline(kt, kt.get("model", 0))}
+           "max_active": r["max_active"], "roofline": None,
+           "roofline_note": "none: the stream mixes IC and LT queries on three graphs, two of them cache-resident, "
+                            "so no single kernel or byte model applies; see the per-workload bench lines"}
     return out, None
 
 
