@@ -375,7 +375,7 @@ def run_serving(args, im, ctx, sync):
            "edges_per_s": round(r["edges_per_s"], 1), "p50_ms": round(r["p50_ms"], 3),
            "p99_ms": round(r["p99_ms"], 3), "achieved_qps": round(r["achieved_qps"], 3),
            "offered_qps": round(r["offered_qps"], 3), "engine_steps": r["engine_steps"],
-           "max_active": r["max_active"], "roofline": None,
+           "max_active": r["max_active"], "slowest": r["slowest"], "roofline": None,
            "roofline_note": "none: the stream mixes IC and LT queries on three graphs, two of them cache-resident, "
                             "so no single kernel or byte model applies; see the per-workload bench lines"}
     return out, None

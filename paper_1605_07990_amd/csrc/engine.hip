@@ -284,16 +284,23 @@ im_status sample_phase(im_engine *e) {
         const im_graph *g = kv.first.first;
         const im_model model = im_model(kv.first.second);
         const uint64_t cap = max_batch(model);
-        std::vector<Query *> short_of = kv.second;
-        while (!short_of.empty()) {
-            // one fused launch: as many queries' demands as fit the batch cap
+        // each query draws at most an eighth of a launch per step, so one
+        // that needs many sets spreads them over several steps and the
+        // queries beside it finish in between (its sets are the same either
+        // way: set j depends only on its key and j)
+        const uint64_t quota = std::max<uint64_t>(1, cap / 8);
+        const std::vector<Query *> &qs = kv.second;
+        size_t i = 0;
+        while (i < qs.size()) {
+            // one fused launch: as many queries' next chunks as fit the batch cap
             const double t0 = now_ms();
             std::vector<SampleItem> items;
             std::vector<Query *> members;
             uint64_t total = 0;
             double hint = 0;
-            for (Query *q : short_of) {
-                const uint64_t take = std::min<uint64_t>(q->target - q->pool->count, cap);
+            for (; i < qs.size(); ++i) {
+                Query *q = qs[i];
+                const uint64_t take = std::min<uint64_t>(q->target - q->pool->count, quota);
                 if (!members.empty() && total + take > cap) break;
                 items.push_back(SampleItem{q->pool->key, q->pool->count, take, nullptr});
                 members.push_back(q);
@@ -309,12 +316,10 @@ im_status sample_phase(im_engine *e) {
                 app[j] = AppendItem{members[j]->pool, items[j].count, tot[j].nodes, tot[j].edges};
             IM_TRY(pool_append_items(e->ctx, app.data(), uint32_t(app.size())));
             const double dt = now_ms() - t0;
-            for (Query *q : members) q->st.ms_sample += dt;
-            std::vector<Query *> rest;
-            for (Query *q : short_of)
-                if (q->pool->count < q->target) rest.push_back(q);
-                else q->phase = kCover;
-            short_of.swap(rest);
+            for (Query *q : members) {
+                q->st.ms_sample += dt;
+                if (q->pool->count >= q->target) q->phase = kCover;
+            }
         }
     }
     return IM_OK;

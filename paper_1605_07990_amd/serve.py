@@ -82,6 +82,7 @@ def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_resul
     latency = [0.0] * len(requests)
     results = [None] * len(requests) if keep_results else None
     sets = edges = 0
+    sizes = [0] * len(requests)  # RR sets each query drew (main plus verification)
     steps = 0
     max_active = 0
     nxt = 0
@@ -110,6 +111,7 @@ def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_resul
             seeds, st = engine.result(t)
             latency[i] = (done_at - requests[i].arrival) * 1e3
             sets += st["n_sets"] + st["n_verify"]
+            sizes[i] = int(st["n_sets"] + st["n_verify"])
             edges += st["edges"]
             if keep_results:
                 results[i] = (seeds, st)
@@ -117,7 +119,11 @@ def serve(engine: "im.Engine", graphs: dict, requests: list[Request], keep_resul
             progress(len(requests) - len(outstanding) - (len(reqs) - nxt), len(requests), active)
     wall = time.perf_counter() - t0
     span = requests[reqs[-1]].arrival if reqs else 0.0
+    slowest = sorted(range(len(requests)), key=lambda i: -latency[i])[:10]
     out = {"queries": len(requests), "wall_s": wall, "arrival_span_s": span,
+           "slowest": [{"graph": requests[i].graph, "model": "IC" if requests[i].model == im.IM_IC else "LT",
+                        "algo": "D-SSA" if requests[i].algo == im.ALGOS["dssa"] else "SSA", "k": requests[i].k,
+                        "eps": requests[i].eps, "ms": round(latency[i], 1), "rr_sets": sizes[i]} for i in slowest],
            "offered_qps": len(requests) / span if span > 0 else float("inf"),
            "achieved_qps": len(requests) / wall if wall > 0 else 0.0,
            "p50_ms": percentile(latency, 50), "p99_ms": percentile(latency, 99),
