@@ -320,7 +320,17 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       Max-Coverage of one range (two launches per round) are replayed
  *       from a HIP graph built the second time the same round count and
  *       launch shape recur (kept per context, at most 32); 0: launched one
- *       by one (default 0: replay measured slower than stream launches).
+ *       by one (default 0: replay measured slower than stream launches);
+ *   IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES a Max-Coverage range of one query
+ *       with at most this many (set, node) entries runs its rounds in one
+ *       workgroup over up to 512 candidate nodes, keeping only their gains
+ *       current; when no candidate beats the bound on the other keys, the
+ *       grid recounts every gain from the covered sets and picks new
+ *       candidates (default 0: off). Takes precedence over the two
+ *       parameters above and IM_PARAM_GREEDY_WG_MAX_ENTRIES;
+ *   IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS the first this many rounds of such
+ *       a range run grid-wide, two launches each (they cover the most sets),
+ *       before the one-workgroup rounds take over (default 0).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -333,7 +343,9 @@ typedef enum {
     IM_PARAM_GREEDY_CANDIDATES = 6,
     IM_PARAM_GREEDY_CANDIDATES_BATCH = 7,
     IM_PARAM_DSSA_DRAW_AHEAD = 8,
-    IM_PARAM_GREEDY_GRAPH = 9
+    IM_PARAM_GREEDY_GRAPH = 9,
+    IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES = 10,
+    IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 11
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -26,6 +26,8 @@ CANDIDATES = {
     "greedy_candidates": [0, 8, 16, 32, 64],
     "greedy_candidates_batch": [0, 8, 16, 32, 64],
     "dssa_draw_ahead": [1, 2, 4, 8],
+    "greedy_wg_cand_max_entries": [0, 1 << 20, 1 << 22, 1 << 24, 1 << 62],
+    "greedy_wg_cand_grid_rounds": [0, 4, 8, 16, 32],
 }
 
 

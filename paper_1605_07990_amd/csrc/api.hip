@@ -201,6 +201,8 @@ im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
     a->greedy_candidates = ctx->greedy_candidates;
     a->greedy_candidates_batch = ctx->greedy_candidates_batch;
     a->ic_ticket_block = ctx->ic_ticket_block;
+    a->greedy_wg_cand_max_entries = ctx->greedy_wg_cand_max_entries;
+    a->greedy_wg_cand_grid_rounds = ctx->greedy_wg_cand_grid_rounds;
     *out = a;
     return IM_OK;
 }
@@ -351,6 +353,13 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 1) break;
         c->greedy_graph = value != 0;
         return IM_OK;
+    case IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES:
+        c->greedy_wg_cand_max_entries = value;
+        return IM_OK;
+    case IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS:
+        if (value > (1ull << 31)) break;
+        c->greedy_wg_cand_grid_rounds = static_cast<uint32_t>(value);
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -389,6 +398,12 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_GREEDY_GRAPH:
         *value = c->greedy_graph ? 1 : 0;
+        return IM_OK;
+    case IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES:
+        *value = c->greedy_wg_cand_max_entries;
+        return IM_OK;
+    case IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS:
+        *value = c->greedy_wg_cand_grid_rounds;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));

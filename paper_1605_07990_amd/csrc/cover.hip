@@ -173,6 +173,9 @@ struct GreedyState {
     uint32_t *cbase;      // [2][kCandNodes] candidate gains at the start of the round before
     uint32_t *cdec;       // [3][kCandNodes] drops of candidate nodes in one round
     uint32_t want;        // candidate chunks asked for
+    // one-workgroup candidate rounds
+    uint32_t *hist;       // [kSelBins] unchosen nodes per gain bin
+    uint32_t *ccount;     // candidates listed
 };
 
 // Load flavours. State written by earlier kernels is read with plain loads.
@@ -935,6 +938,344 @@ __global__ __launch_bounds__(kPersistThreads) void persist_kernel(const GreedySt
     }
 }
 
+// ---- rounds in one workgroup over candidate nodes ----
+//
+// The same candidate rule as the step launches (keys only fall, so the
+// largest candidate key is the argmax while it beats a bound on every other
+// node's key), with all the rounds of one candidate set inside one
+// workgroup. Only the candidates' gains are kept current, in LDS: covering a
+// set walks its members and drops the ones that are candidates. The other
+// nodes' global gains go stale, so when the test fails the grid recounts
+// every gain from the covered-set bits (clear, recount), bins the gains
+// (hist), finds the bin cut that keeps at most kCandNodes nodes (cut) and
+// lists them (collect). Between re-selections a round costs its own chain of
+// loads and no launch. Every launch reads the job's header and does nothing
+// unless the header is in its phase, so the host can queue cycles ahead.
+
+constexpr int kWgThreads = 1024;
+constexpr uint32_t kWgCovWords = 8192;  // covered-set bits kept in LDS (262,144 sets)
+constexpr uint32_t kStepCollect = 4;     // header phase: candidates listed under thresh
+constexpr uint32_t kSelExact = 2048;     // gains below this have a bin of their own
+constexpr uint32_t kSelBins = kSelExact + 8 * 20;  // then eight bins per power of two, up to 2^31
+
+// Bin of a gain in [1, 2^31), non-decreasing in the gain.
+__device__ __forceinline__ uint32_t sel_bin(uint32_t gain) {
+    if (gain < kSelExact) return gain;
+    const uint32_t lz = 31u - static_cast<uint32_t>(__clz(gain));  // 11..30
+    return kSelExact + 8u * (lz - 11u) + ((gain >> (lz - 3u)) & 7u);
+}
+
+// The smallest gain of bin b >= 1.
+__device__ __forceinline__ uint32_t sel_bin_low(uint32_t b) {
+    if (b < kSelExact) return b;
+    const uint32_t q = b - kSelExact, lz = 11u + q / 8u;
+    return (8u + (q & 7u)) << (lz - 3u);
+}
+
+constexpr uint32_t kWgFilterShift = 16;  // candidate filter: 2^16 bits, one per hash value
+
+__device__ __forceinline__ uint32_t wg_filter_bit(uint32_t u) { return (u * 2654435761u) >> (32 - kWgFilterShift); }
+
+struct WgLds {
+    unsigned long long smem[kWgThreads / kWave];
+    uint32_t filter[(1u << kWgFilterShift) / 32];  // set for every candidate's hash value
+    uint32_t key[1u << kCandHashBits];
+    uint16_t slot[1u << kCandHashBits];
+    uint32_t node[kCandNodes];
+    uint32_t cg[kCandNodes];      // candidate gains, bit 31 = chosen
+    uint64_t ia[kCandNodes];      // candidate's first incidence entry
+    uint32_t ilen[kCandNodes];    // and entry count
+    uint64_t fstart[kWgThreads];  // newly covered sets of one batch of entries: first member
+    uint32_t fsize[kWgThreads];   // and size
+    uint32_t cov[kWgCovWords];
+    uint32_t nfresh;
+};
+
+__device__ __forceinline__ uint32_t wg_slot(const WgLds &L, uint32_t u) {
+    constexpr uint32_t kMask = (1u << kCandHashBits) - 1u;
+    uint32_t h = (u * 2654435761u) >> (32 - kCandHashBits);
+    for (uint32_t p = 0; p <= kMask; ++p) {
+        const uint32_t k = L.key[h];
+        if (k == u) return L.slot[h];
+        if (k == kNoCand) break;
+        h = (h + 1u) & kMask;
+    }
+    return kNoCand;
+}
+
+template <bool kLdsCov>
+__device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words, WgLds &L) {
+    constexpr uint32_t kMask = (1u << kCandHashBits) - 1u;
+    const uint32_t tid = threadIdx.x, bd = blockDim.x;
+    uint32_t *covbits = kLdsCov ? L.cov : g.covbits;
+    if constexpr (kLdsCov)
+        for (uint64_t w = tid; w < words; w += bd) L.cov[w] = g.covbits[w];
+    for (uint32_t i = tid; i <= kMask; i += bd) L.key[i] = kNoCand;
+    for (uint32_t i = tid; i < (1u << kWgFilterShift) / 32; i += bd) L.filter[i] = 0u;
+    __syncthreads();
+    const uint32_t nn = min(*g.ccount, kCandNodes);
+    for (uint32_t s = tid; s < nn; s += bd) {
+        const uint32_t u = g.cnode[s];
+        const uint32_t fb = wg_filter_bit(u);
+        atomicOr(&L.filter[fb >> 5], 1u << (fb & 31u));
+        L.node[s] = u;
+        L.cg[s] = g.cbase[s];
+        const uint64_t ia = g.ioff[u];
+        L.ia[s] = ia;
+        L.ilen[s] = static_cast<uint32_t>(g.ioff[u + 1] - ia);
+        uint32_t hh = (u * 2654435761u) >> (32 - kCandHashBits);
+        for (uint32_t q = 0; q <= kMask; ++q) {
+            if (atomicCAS(&L.key[hh], kNoCand, u) == kNoCand) {
+                L.slot[hh] = static_cast<uint16_t>(s);
+                break;
+            }
+            hh = (hh + 1u) & kMask;
+        }
+    }
+    __syncthreads();
+    unsigned long long newly = 0;
+    uint32_t r = h.r;
+    bool stalled = false;
+    const uint32_t grp = tid >> 4, sub = tid & 15u, ngrp = bd >> 4;
+    for (; r < g.k; ++r) {
+        unsigned long long best = 0;
+        for (uint32_t s = tid; s < nn; s += bd) {
+            const uint32_t x = L.cg[s];
+            if (!(x & kChosen)) {
+                const unsigned long long key = (static_cast<unsigned long long>(x) << 32) | static_cast<unsigned long long>(~L.node[s]);
+                best = key > best ? key : best;
+            }
+        }
+        best = block_max_u64(best, L.smem);
+        if (best <= h.thresh) {  // the same value in every thread
+            stalled = true;
+            break;
+        }
+        const uint32_t v = ~static_cast<uint32_t>(best & 0xFFFFFFFFull);
+        const uint32_t sv = wg_slot(L, v);  // v is a candidate: best came from L.cg
+        if (sv == kNoCand) {  // cannot happen; leave the job for a re-selection
+            stalled = true;
+            break;
+        }
+        if (tid == 0) {
+            g.seeds[r] = v;
+            atomicOr(&g.gain[v], kChosen);
+            L.cg[sv] |= kChosen;
+        }
+        // cover v's sets, one batch of incidence entries at a time: first the
+        // newly covered sets are listed, then 16 lanes walk each one's members
+        const uint64_t a = L.ia[sv], b = a + L.ilen[sv];
+        for (uint64_t e0 = a; e0 < b; e0 += bd) {
+            if (tid == 0) L.nfresh = 0u;
+            __syncthreads();
+            const uint64_t i = e0 + tid;
+            if (i < b) {
+                const uint32_t j = g.isets[i];
+                const uint32_t bit = 1u << (j & 31u);
+                if (!(atomicOr(&covbits[j >> 5], bit) & bit)) {
+                    const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
+                    const uint32_t f = atomicAdd(&L.nfresh, 1u);
+                    L.fstart[f] = sa;
+                    L.fsize[f] = static_cast<uint32_t>(sb - sa);
+                    ++newly;
+                }
+            }
+            __syncthreads();
+            const uint32_t nf = L.nfresh;
+            for (uint32_t f = grp; f < nf; f += ngrp) {
+                const uint64_t sa = L.fstart[f];
+                const uint32_t sz = L.fsize[f];
+                // a lane's members of the set are all in flight before any is used
+                for (uint32_t q0 = 0; q0 < sz; q0 += 128) {
+                    uint32_t u[8];
+#pragma unroll
+                    for (uint32_t t = 0; t < 8; ++t) {
+                        const uint32_t q = q0 + sub + 16u * t;
+                        u[t] = q < sz ? g.pnodes[sa + q] : kNoCand;
+                    }
+#pragma unroll
+                    for (uint32_t t = 0; t < 8; ++t) {
+                        if (u[t] == kNoCand) continue;
+                        const uint32_t fb = wg_filter_bit(u[t]);
+                        if (!((L.filter[fb >> 5] >> (fb & 31u)) & 1u)) continue;
+                        const uint32_t slot = wg_slot(L, u[t]);
+                        if (slot != kNoCand) atomicSub(&L.cg[slot], 1u);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    if constexpr (kLdsCov) {
+        if (stalled)
+            for (uint64_t w = tid; w < words; w += bd) g.covbits[w] = L.cov[w];
+    }
+    newly = wave_sum_u64(newly);
+    if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
+    if (tid == 0) {
+        StepHdr o = h;
+        o.r = r;
+        if (stalled) {
+            o.phase = kStepRefresh;
+            ++o.stalls;
+        } else {
+            o.phase = kStepDone;
+        }
+        g.hdr[0] = o;
+    }
+}
+
+// Job blockIdx.x: rounds over its listed candidates until done or the test fails.
+__global__ __launch_bounds__(kWgThreads) void wg_round_kernel(const GreedyState *jobs) {
+    __shared__ WgLds L;
+    const GreedyState &g = jobs[blockIdx.x];
+    const StepHdr h = g.hdr[0];
+    if (h.phase != kStepCollect) return;
+    const uint64_t words = (g.nsets + 31) / 32;
+    if (words <= kWgCovWords) wg_rounds<true>(g, h, words, L);
+    else wg_rounds<false>(g, h, words, L);
+}
+
+// Re-selection, step 1 (grid, blockIdx.y = job): keep only the chosen bits.
+__global__ __launch_bounds__(kThreads) void wg_clear_kernel(const GreedyState *jobs) {
+    const GreedyState &g = jobs[blockIdx.y];
+    if (g.hdr[0].phase != kStepRefresh) return;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x)
+        g.gain[v] &= kChosen;
+}
+
+// Re-selection, step 2: every set not covered adds one to each member's
+// gain, 16 lanes per set (a chosen node has no such set left).
+__global__ __launch_bounds__(kThreads) void wg_recount_kernel(const GreedyState *jobs) {
+    const GreedyState &g = jobs[blockIdx.y];
+    if (g.hdr[0].phase != kStepRefresh) return;
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t step = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (uint64_t j = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4; j < g.nsets; j += step) {
+        if ((g.covbits[j >> 5] >> (j & 31u)) & 1u) continue;
+        const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
+        for (uint64_t q = sa + sub; q < sb; q += 16) atomicAdd(&g.gain[g.pnodes[q]], 1u);
+    }
+}
+
+// Re-selection, step 3: how many unchosen nodes have a gain in each bin
+// (into g.hist, which the cut step leaves zeroed).
+__global__ __launch_bounds__(kThreads) void wg_hist_kernel(const GreedyState *jobs) {
+    __shared__ uint32_t hl[kSelBins];
+    const GreedyState &g = jobs[blockIdx.y];
+    if (g.hdr[0].phase != kStepRefresh) return;
+    for (uint32_t i = threadIdx.x; i < kSelBins; i += blockDim.x) hl[i] = 0u;
+    __syncthreads();
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const uint32_t x = g.gain[v];
+        if (x && !(x & kChosen)) atomicAdd(&hl[sel_bin(x)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kSelBins; i += blockDim.x)
+        if (hl[i]) atomicAdd(&g.hist[i], hl[i]);
+}
+
+// Re-selection, step 4 (job blockIdx.x, one 256-thread block): the bound
+// thresh on the keys left out. Normally the lowest bin b whose nodes, with
+// those of the bins above, number at most kCandNodes, and thresh = the
+// largest key a gain below bin b can have. If the top bin alone holds more,
+// thresh is the (kCandNodes + 1)-th largest key, exactly (eight passes over
+// every node: slow, and only reachable with more than kCandNodes nodes in one
+// bin of gains >= 2048). If every unchosen gain is zero, the candidates are
+// the lowest unchosen ids (the argmax then picks them in id order) and thresh
+// is the key of the next one. Leaves the header in COLLECT.
+__global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *jobs) {
+    constexpr uint32_t kPer = (kSelBins + kThreads - 1) / kThreads;
+    __shared__ SelectLds L;
+    __shared__ uint32_t s_cut;
+    __shared__ unsigned long long s_t;
+    const GreedyState &g = jobs[blockIdx.x];
+    const StepHdr h = g.hdr[0];
+    if (h.phase != kStepRefresh) return;
+    const uint32_t tid = threadIdx.x;
+    // thread tid holds bins [c kPer, c kPer + kPer) with c = 255 - tid, so a
+    // prefix over threads counts the bins above
+    const uint32_t c = kThreads - 1u - tid;
+    uint32_t cnt[kPer];
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) {
+        const uint32_t b = c * kPer + i;
+        cnt[i] = (b >= 1u && b < kSelBins) ? g.hist[b] : 0u;
+        sum += cnt[i];
+    }
+    if (tid == 0) s_cut = kNoCand;
+    uint64_t total = 0;
+    const uint64_t above = block_scan_excl(sum, L.scan, total);
+    uint64_t run = above;
+#pragma unroll
+    for (int i = static_cast<int>(kPer) - 1; i >= 0; --i) {
+        const uint32_t b = c * kPer + static_cast<uint32_t>(i);
+        run += cnt[i];
+        if (b >= 1u && b < kSelBins && run <= kCandNodes) atomicMin(&s_cut, b);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < kSelBins; i += blockDim.x) g.hist[i] = 0u;
+    const uint32_t cut = s_cut;
+    // nodes in the bins from cut up
+    uint64_t mine = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i)
+        if (c * kPer + i >= cut) mine += cnt[i];
+    uint64_t kept = 0;
+    (void)block_scan_excl(mine, L.scan, kept);
+    unsigned long long thresh = 0;
+    if (total == 0) {
+        // every unchosen gain is zero: find the (kCandNodes + 1)-th unchosen id
+        if (tid == 0) s_t = 0ull;
+        __syncthreads();
+        uint64_t seen = 0;
+        for (uint32_t base = 0; base < g.n; base += blockDim.x) {
+            const uint32_t v = base + tid;
+            const uint64_t f = (v < g.n && !(g.gain[v] & kChosen)) ? 1u : 0u;
+            uint64_t tot = 0;
+            const uint64_t pre = block_scan_excl(f, L.scan, tot);
+            if (f && seen + pre == kCandNodes) s_t = static_cast<unsigned long long>(~v);
+            seen += tot;
+            __syncthreads();
+            if (seen > kCandNodes) break;  // the same in every thread
+        }
+        thresh = s_t;
+    } else if (cut == kNoCand || kept == 0) {
+        auto key_of = [&](uint32_t v) { return node_key<false>(g.gain, v); };
+        thresh = block_kth_largest(key_of, g.n, kCandNodes + 1u, L);
+    } else {
+        thresh = (static_cast<unsigned long long>(sel_bin_low(cut) - 1u) << 32) | 0xFFFFFFFFull;
+    }
+    if (tid == 0) {
+        *g.ccount = 0u;
+        StepHdr o = h;
+        o.phase = kStepCollect;
+        o.thresh = thresh;
+        g.hdr[0] = o;
+    }
+}
+
+// Re-selection, step 5 (grid): list every unchosen node whose key beats thresh.
+__global__ __launch_bounds__(kThreads) void wg_collect_kernel(const GreedyState *jobs) {
+    const GreedyState &g = jobs[blockIdx.y];
+    const StepHdr h = g.hdr[0];
+    if (h.phase != kStepCollect) return;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const uint32_t x = g.gain[v];
+        if (x & kChosen) continue;
+        const unsigned long long key = (static_cast<unsigned long long>(x) << 32) | static_cast<unsigned long long>(~v);
+        if (key > h.thresh) {
+            const uint32_t s = atomicAdd(g.ccount, 1u);
+            if (s < kCandNodes) {
+                g.cnode[s] = v;
+                g.cbase[s] = x;
+            }
+        }
+    }
+}
+
 // Sets in [begin, end) that contain a node of the seed bitmap.
 __global__ __launch_bounds__(kThreads) void coverage_kernel(const uint64_t *poff, const uint32_t *pnodes, uint64_t begin,
                                                             uint64_t end, const uint32_t *seedbits,
@@ -1278,6 +1619,75 @@ static im_status run_steps(im_ctx *ctx, const GreedyState *dgs, StepHdr *dhdr, c
     }
 }
 
+__global__ void wg_start_kernel(const GreedyState *jobs, uint32_t nj, uint32_t r0) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nj) return;
+    StepHdr h{};
+    h.r = r0;
+    h.phase = r0 < jobs[j].k ? kStepRefresh : kStepDone;
+    jobs[j].hdr[0] = h;
+}
+
+// One-workgroup candidate rounds [r0, k) for nj jobs (job j's header at
+// hdrs[j]), whose gains are exact. The first cut, collect and rounds run
+// at once; then cycles (clear, recount, hist, cut, collect, rounds) are
+// queued at the context's running re-selection rate and the headers read
+// back once per batch of cycles, until every job has its k seeds.
+static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *const *hdrs, const uint32_t *ks,
+                               uint32_t nj, uint32_t n, uint64_t max_sets, uint32_t r0) {
+    hipStream_t st = ctx->stream;
+    const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+    const dim3 gn(grid_of(n, kThreads, cu * 8), nj), gh(grid_of(n, kThreads * 8, cu * 2), nj),
+        gs(grid_of(max_sets * 16, kThreads, cu * 16), nj);
+    wg_start_kernel<<<(nj + 255) / 256, 256, 0, st>>>(dgs, nj, r0);
+    wg_hist_kernel<<<gh, kThreads, 0, st>>>(dgs);
+    wg_cut_kernel<<<nj, kThreads, 0, st>>>(dgs);
+    wg_collect_kernel<<<gn, kThreads, 0, st>>>(dgs);
+    wg_round_kernel<<<nj, kWgThreads, 0, st>>>(dgs);
+    uint32_t max_k = 0;
+    for (uint32_t j = 0; j < nj; ++j) max_k = std::max(max_k, ks[j]);
+    std::vector<StepHdr> hh(nj);
+    uint64_t cycles = 1;
+    uint32_t remaining = max_k - std::min(max_k, r0);
+    for (;;) {
+        const uint32_t est = 1u + static_cast<uint32_t>(ctx->greedy_wg_resel_rate * remaining);
+        for (uint32_t i = 0; i < est; ++i) {
+            wg_clear_kernel<<<gn, kThreads, 0, st>>>(dgs);
+            wg_recount_kernel<<<gs, kThreads, 0, st>>>(dgs);
+            wg_hist_kernel<<<gh, kThreads, 0, st>>>(dgs);
+            wg_cut_kernel<<<nj, kThreads, 0, st>>>(dgs);
+            wg_collect_kernel<<<gn, kThreads, 0, st>>>(dgs);
+            wg_round_kernel<<<nj, kWgThreads, 0, st>>>(dgs);
+        }
+        cycles += est;
+        IM_HIP(hipGetLastError());
+        for (uint32_t j = 0; j < nj; ++j)
+            IM_HIP(hipMemcpyAsync(&hh[j], hdrs[j], sizeof(StepHdr), hipMemcpyDeviceToHost, st));
+        IM_HIP(hipStreamSynchronize(st));
+        remaining = 0;
+        uint64_t stalls = 0, rounds = 0;
+        bool done = true;
+        for (uint32_t j = 0; j < nj; ++j) {
+            if (hh[j].phase != kStepDone) {
+                done = false;
+                remaining = std::max<uint32_t>(remaining, ks[j] - std::min(ks[j], hh[j].r));
+            }
+            stalls += hh[j].stalls;
+            rounds += hh[j].r;
+        }
+        if (done) {
+            if (rounds)
+                ctx->greedy_wg_resel_rate = 0.5 * ctx->greedy_wg_resel_rate + 0.5 * double(stalls) / double(rounds);
+            return IM_OK;
+        }
+        // every cycle chooses at least one seed: the cut keeps only keys above its bound
+        if (cycles > uint64_t(max_k) + 2) {
+            set_error("max coverage: one-workgroup rounds did not finish");
+            return IM_E_DEVICE;
+        }
+    }
+}
+
 }  // namespace im
 
 // Cached HIP graphs of the per-round launch pairs (refresh, cover) of one
@@ -1397,7 +1807,8 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
                  o_m2 = take(8ull * n2),
                  o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096),
                  o_hdr = take(2 * sizeof(StepHdr)), o_cnode = take(4ull * kCandNodes),
-                 o_cbase = take(8ull * kCandNodes), o_cdec = take(12ull * kCandNodes);
+                 o_cbase = take(8ull * kCandNodes), o_cdec = take(12ull * kCandNodes),
+                 o_hist = take(4ull * kSelBins), o_ccount = take(4);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
@@ -1445,6 +1856,41 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     if (nsets)
         scatter_kernel<<<grid_of(nsets * 16, kThreads, cu * 16), kThreads, 0, st>>>(poff, pnodes, begin, nsets, ioff,
                                                                                      fill, isets);
+    if (k && entries <= ctx->greedy_wg_cand_max_entries) {
+        // the first rounds (the large covers) on the grid, two launches each,
+        // which keep every gain exact; the rest in one workgroup over
+        // candidate nodes
+        const uint32_t lead = std::min<uint32_t>(k, ctx->greedy_wg_cand_grid_rounds);
+        if (lead) {
+            init_m1_kernel<<<grid_of(n1, kThreads, cu * 8), kThreads, 0, st>>>(g);
+            const uint32_t rg = grid_of(uint64_t(n1), kThreads, cu * 4);
+            const uint32_t cg =
+                ctx->greedy_cover_blocks
+                    ? ctx->greedy_cover_blocks
+                    : std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
+            g.nbmax = rg;
+            if (g.mark)
+                fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32,
+                                                                                           0u);
+            for (uint32_t r = 0; r < lead; ++r) {
+                refresh_kernel<<<rg, kThreads, 0, st>>>(g, r);
+                cover_kernel<<<cg, kThreads, 0, st>>>(g, r);
+            }
+        }
+        g.hdr = reinterpret_cast<StepHdr *>(base + o_hdr);
+        g.cnode = at32(o_cnode);
+        g.cbase = at32(o_cbase);
+        g.hist = at32(o_hist);
+        g.ccount = at32(o_ccount);
+        fill_u32_kernel<<<grid_of(kSelBins, kThreads, 64), kThreads, 0, st>>>(g.hist, kSelBins, 0u);
+        auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
+        IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
+        StepHdr *hdr = g.hdr;
+        IM_TRY(run_wg_cycles(ctx, dg, &hdr, &k, 1, n, nsets, lead));
+        IM_HIP(hipMemcpyAsync(seeds_host, g.seeds, 4ull * k, hipMemcpyDeviceToHost, st));
+        IM_TRY(to_host_sync(ctx, cov, dcov, 8));
+        return IM_OK;
+    }
     // maximum index, then the rounds
     init_m1_kernel<<<grid_of(n1, kThreads, cu * 8), kThreads, 0, st>>>(g);
     // per-round launches pay for themselves once the cover work per round is

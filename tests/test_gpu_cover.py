@@ -135,6 +135,67 @@ def test_greedy_paths_agree(im, ctx, pools, name, limit, mark, cand):
             ctx.set_param(x, v)
 
 
+@pytest.mark.parametrize("lead", [0, 3, 64])
+@pytest.mark.parametrize("name", ["nethept", "rmat16", "cl_small"])
+def test_wg_candidate_rounds_agree(im, ctx, pools, name, lead):
+    """Rounds in one workgroup over candidate nodes, after `lead` grid-wide
+    rounds, give the oracle's seeds, on whole pools and sub-ranges, from one
+    seed to more seeds than one candidate set holds (several re-selections,
+    the zero-gain tail)."""
+    g, dg, og, p, op = pools[name]
+    c = p.count
+    note(f"one-workgroup candidate rounds {name} lead={lead}")
+    old = ctx.get_param("greedy_wg_cand_max_entries"), ctx.get_param("greedy_wg_cand_grid_rounds")
+    ctx.set_param("greedy_wg_cand_max_entries", 1 << 62)
+    ctx.set_param("greedy_wg_cand_grid_rounds", lead)
+    try:
+        for begin, end, k in ((0, c, 1), (0, c, 50), (0, c, 700), (0, c, 2000), (c // 2, c, 20),
+                              (1234, 1234 + 4097, 5), (7, 8, 3), (100, 100, 2)):
+            seeds, cov = p.max_coverage(k, begin, end)
+            oseeds, ocov = op.max_coverage(k, begin, end)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (begin, end, k)
+    finally:
+        ctx.set_param("greedy_wg_cand_max_entries", old[0])
+        ctx.set_param("greedy_wg_cand_grid_rounds", old[1])
+
+
+@pytest.mark.parametrize("lead", [0, 2])
+def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead):
+    """k = n on a graph without edges (every gain reaches zero), and more
+    sets than the LDS covered-set bitmap holds."""
+    note(f"one-workgroup candidate rounds: k = n, 400k sets, lead={lead}")
+    old = ctx.get_param("greedy_wg_cand_max_entries"), ctx.get_param("greedy_wg_cand_grid_rounds")
+    ctx.set_param("greedy_wg_cand_max_entries", 1 << 62)
+    ctx.set_param("greedy_wg_cand_grid_rounds", lead)
+    try:
+        n = 40
+        e = np.array([], np.uint32)
+        dg = im.Graph(ctx, n, e, e, w_ic=np.array([], np.float32))
+        og = oracle_lib.Graph(0, n, e, e, np.array([], np.float32))
+        p = im.Pool(dg, 0, 5)
+        p.sample(300)
+        op = oracle_lib.Pool(og, 5)
+        op.extend(300)
+        for k in (1, 39, n):
+            seeds, cov = p.max_coverage(k)
+            oseeds, ocov = op.max_coverage(k)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
+        g = synth.make("cl_20k")
+        dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+        og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+        p = im.Pool(dg, 0, 9)
+        p.sample(400_000)
+        op = oracle_lib.Pool(og, 9)
+        op.extend(400_000)
+        for k in (5, 600):
+            seeds, cov = p.max_coverage(k)
+            oseeds, ocov = op.max_coverage(k)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
+    finally:
+        ctx.set_param("greedy_wg_cand_max_entries", old[0])
+        ctx.set_param("greedy_wg_cand_grid_rounds", old[1])
+
+
 def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):
     """More sets than the LDS covered-set bitmap holds and more dirty chunks
     per round than the list holds, in one workgroup."""

@@ -115,3 +115,25 @@ def test_dssa_draw_ahead_changes_nothing(im, ctx, oracle_lib, name, k, ahead):
     finally:
         ctx.set_param("dssa_draw_ahead", old[0])
         ctx.set_param("dssa_speculate", old[1])
+
+
+@pytest.mark.parametrize("algo,name,model,k", [("dssa", "rmat16", 1, 40), ("ssa", "nethept", 0, 50),
+                                               ("dssa", "rmat20", 1, 100)])
+def test_wg_candidate_rounds_runs_match_oracle(im, ctx, oracle_lib, algo, name, model, k):
+    """Whole SSA / D-SSA runs with every Max-Coverage in one workgroup over
+    candidate nodes give the oracle's runs."""
+    g = synth.make(name)
+    w = g.w_ic if model == 0 else g.w_lt
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
+    og = oracle_lib.Graph(model, g.n, g.src, g.dst, w)
+    note(f"{algo} with one-workgroup candidate rounds {name} k={k}")
+    old = ctx.get_param("greedy_wg_cand_max_entries")
+    ctx.set_param("greedy_wg_cand_max_entries", 1 << 62)
+    try:
+        for key in (0, 3):
+            seeds, st = getattr(dg, algo)(model, k, 0.1, 1.0 / g.n, key)
+            oseeds, ost = getattr(og, algo)(k, 0.1, 1.0 / g.n, key)
+            assert seeds.tolist() == oseeds.tolist()
+            _compare(st, ost, algo)
+    finally:
+        ctx.set_param("greedy_wg_cand_max_entries", old)
