@@ -500,7 +500,8 @@ def main() -> int:
     ap.add_argument("--queries-per-step", type=int, default=1,
                     help="R-MAT-20: concurrent D-SSA queries per step through the multi-query engine")
     ap.add_argument("--greedy-wg-max-entries", type=int, default=None,
-                    help="launch parameter: largest Max-Coverage range run in one workgroup")
+                    help="launch parameter: largest Max-Coverage range whose rounds all run in one "
+                         "workgroup over the full max index (with --param greedy_wg_cand_max_entries 0)")
     ap.add_argument("--param", nargs=2, action="append", default=[], metavar=("NAME", "VALUE"),
                     help="set a launch parameter (im_ctx_set_param) before the run")
     ap.add_argument("--no-speculate", action="store_true",

@@ -326,11 +326,13 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       workgroup over up to 512 candidate nodes, keeping only their gains
  *       current; when no candidate beats the bound on the other keys, the
  *       grid recounts every gain from the covered sets and picks new
- *       candidates (default 0: off). Takes precedence over the two
- *       parameters above and IM_PARAM_GREEDY_WG_MAX_ENTRIES;
+ *       candidates; if a re-selection keeps fewer than 64 candidates (and
+ *       fewer than the rounds left), the remaining rounds run grid-wide, two
+ *       launches each (default: every range; 0: off). Takes precedence over
+ *       the two parameters above and IM_PARAM_GREEDY_WG_MAX_ENTRIES;
  *   IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS the first this many rounds of such
  *       a range run grid-wide, two launches each (they cover the most sets),
- *       before the one-workgroup rounds take over (default 0).
+ *       before the one-workgroup rounds take over (default 16).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {

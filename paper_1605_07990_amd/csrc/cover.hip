@@ -955,6 +955,8 @@ __global__ __launch_bounds__(kPersistThreads) void persist_kernel(const GreedySt
 constexpr int kWgThreads = 1024;
 constexpr uint32_t kWgCovWords = 8192;  // covered-set bits kept in LDS (262,144 sets)
 constexpr uint32_t kStepCollect = 4;     // header phase: candidates listed under thresh
+constexpr uint32_t kStepGrid = 5;        // header phase: the remaining rounds go to the grid-wide path
+constexpr uint32_t kWgMinCand = 64;      // fewer candidates than this (and than rounds left): grid rounds
 constexpr uint32_t kSelExact = 2048;     // gains below this have a bin of their own
 constexpr uint32_t kSelBins = kSelExact + 8 * 20;  // then eight bins per power of two, up to 2^31
 
@@ -1114,15 +1116,12 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
     newly = wave_sum_u64(newly);
     if (lane_id() == 0 && newly) atomicAdd(g.cov, newly);
     if (tid == 0) {
-        StepHdr o = h;
-        o.r = r;
+        g.hdr[0].r = r;
         if (stalled) {
-            o.phase = kStepRefresh;
-            ++o.stalls;
-        } else {
-            o.phase = kStepDone;
+            g.hdr[0].stalls = h.stalls + 1u;
+            *g.ccount = 0u;  // for the next collect
         }
-        g.hdr[0] = o;
+        g.hdr[0].phase = stalled ? kStepRefresh : kStepDone;
     }
 }
 
@@ -1177,17 +1176,18 @@ __global__ __launch_bounds__(kThreads) void wg_hist_kernel(const GreedyState *jo
 }
 
 // Re-selection, step 4 (job blockIdx.x, one 256-thread block): the bound
-// thresh on the keys left out. Normally the lowest bin b whose nodes, with
-// those of the bins above, number at most kCandNodes, and thresh = the
-// largest key a gain below bin b can have. If the top bin alone holds more,
-// thresh is the (kCandNodes + 1)-th largest key, exactly (eight passes over
-// every node: slow, and only reachable with more than kCandNodes nodes in one
-// bin of gains >= 2048). If every unchosen gain is zero, the candidates are
-// the lowest unchosen ids (the argmax then picks them in id order) and thresh
-// is the key of the next one. Leaves the header in COLLECT.
+// thresh on the keys left out, from the lowest bin b whose nodes, with those
+// of the bins above, number at most kCandNodes; thresh is then the largest
+// key a gain below bin b can have. If every unchosen gain is zero, the
+// candidates are the lowest unchosen ids (the argmax then takes them in id
+// order) and thresh is the key of the next one. Leaves the header in
+// COLLECT, or in GRID when the cut keeps fewer than kWgMinCand nodes and
+// fewer than the rounds left (flat gains: many nodes share the gain at the
+// cut), so that the host finishes the range with grid-wide rounds, which
+// need no candidates.
 __global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *jobs) {
     constexpr uint32_t kPer = (kSelBins + kThreads - 1) / kThreads;
-    __shared__ SelectLds L;
+    __shared__ uint64_t scan[kThreads / kWave];
     __shared__ uint32_t s_cut;
     __shared__ unsigned long long s_t;
     const GreedyState &g = jobs[blockIdx.x];
@@ -1207,7 +1207,7 @@ __global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *job
     }
     if (tid == 0) s_cut = kNoCand;
     uint64_t total = 0;
-    const uint64_t above = block_scan_excl(sum, L.scan, total);
+    const uint64_t above = block_scan_excl(sum, scan, total);
     uint64_t run = above;
 #pragma unroll
     for (int i = static_cast<int>(kPer) - 1; i >= 0; --i) {
@@ -1224,7 +1224,12 @@ __global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *job
     for (uint32_t i = 0; i < kPer; ++i)
         if (c * kPer + i >= cut) mine += cnt[i];
     uint64_t kept = 0;
-    (void)block_scan_excl(mine, L.scan, kept);
+    (void)block_scan_excl(mine, scan, kept);
+    const uint32_t left = g.k - h.r;
+    if (total != 0 && (cut == kNoCand || (kept < kWgMinCand && kept < left))) {
+        if (tid == 0) g.hdr[0].phase = kStepGrid;
+        return;
+    }
     unsigned long long thresh = 0;
     if (total == 0) {
         // every unchosen gain is zero: find the (kCandNodes + 1)-th unchosen id
@@ -1235,25 +1240,19 @@ __global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *job
             const uint32_t v = base + tid;
             const uint64_t f = (v < g.n && !(g.gain[v] & kChosen)) ? 1u : 0u;
             uint64_t tot = 0;
-            const uint64_t pre = block_scan_excl(f, L.scan, tot);
+            const uint64_t pre = block_scan_excl(f, scan, tot);
             if (f && seen + pre == kCandNodes) s_t = static_cast<unsigned long long>(~v);
             seen += tot;
             __syncthreads();
             if (seen > kCandNodes) break;  // the same in every thread
         }
         thresh = s_t;
-    } else if (cut == kNoCand || kept == 0) {
-        auto key_of = [&](uint32_t v) { return node_key<false>(g.gain, v); };
-        thresh = block_kth_largest(key_of, g.n, kCandNodes + 1u, L);
     } else {
         thresh = (static_cast<unsigned long long>(sel_bin_low(cut) - 1u) << 32) | 0xFFFFFFFFull;
     }
     if (tid == 0) {
-        *g.ccount = 0u;
-        StepHdr o = h;
-        o.phase = kStepCollect;
-        o.thresh = thresh;
-        g.hdr[0] = o;
+        g.hdr[0].thresh = thresh;
+        g.hdr[0].phase = kStepCollect;
     }
 }
 
@@ -1626,16 +1625,20 @@ __global__ void wg_start_kernel(const GreedyState *jobs, uint32_t nj, uint32_t r
     h.r = r0;
     h.phase = r0 < jobs[j].k ? kStepRefresh : kStepDone;
     jobs[j].hdr[0] = h;
+    *jobs[j].ccount = 0u;
 }
 
 // One-workgroup candidate rounds [r0, k) for nj jobs (job j's header at
 // hdrs[j]), whose gains are exact. The first cut, collect and rounds run
 // at once; then cycles (clear, recount, hist, cut, collect, rounds) are
 // queued at the context's running re-selection rate and the headers read
-// back once per batch of cycles, until every job has its k seeds.
+// back once per batch of cycles, until every job has its k seeds or (one
+// job only) the cut asks for grid-wide rounds: then *grid_from is the first
+// round left to them, with every gain exact.
 static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *const *hdrs, const uint32_t *ks,
-                               uint32_t nj, uint32_t n, uint64_t max_sets, uint32_t r0) {
+                               uint32_t nj, uint32_t n, uint64_t max_sets, uint32_t r0, uint32_t *grid_from) {
     hipStream_t st = ctx->stream;
+    *grid_from = ks[0];
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
     const dim3 gn(grid_of(n, kThreads, cu * 8), nj), gh(grid_of(n, kThreads * 8, cu * 2), nj),
         gs(grid_of(max_sets * 16, kThreads, cu * 16), nj);
@@ -1678,6 +1681,16 @@ static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *con
         if (done) {
             if (rounds)
                 ctx->greedy_wg_resel_rate = 0.5 * ctx->greedy_wg_resel_rate + 0.5 * double(stalls) / double(rounds);
+            return IM_OK;
+        }
+        bool grid = false;
+        for (uint32_t j = 0; j < nj; ++j) grid = grid || hh[j].phase == kStepGrid;
+        if (grid) {
+            if (nj != 1) {
+                set_error("max coverage: grid-wide fallback of batched one-workgroup rounds");
+                return IM_E_DEVICE;
+            }
+            *grid_from = hh[0].r;
             return IM_OK;
         }
         // every cycle chooses at least one seed: the cut keeps only keys above its bound
@@ -1861,22 +1874,24 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         // which keep every gain exact; the rest in one workgroup over
         // candidate nodes
         const uint32_t lead = std::min<uint32_t>(k, ctx->greedy_wg_cand_grid_rounds);
-        if (lead) {
+        const uint32_t rg = grid_of(uint64_t(n1), kThreads, cu * 4);
+        const uint32_t cg =
+            ctx->greedy_cover_blocks
+                ? ctx->greedy_cover_blocks
+                : std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
+        g.nbmax = rg;
+        // grid-wide rounds [r0, r1) from exact gains
+        auto grid_rounds = [&](uint32_t r0, uint32_t r1) {
             init_m1_kernel<<<grid_of(n1, kThreads, cu * 8), kThreads, 0, st>>>(g);
-            const uint32_t rg = grid_of(uint64_t(n1), kThreads, cu * 4);
-            const uint32_t cg =
-                ctx->greedy_cover_blocks
-                    ? ctx->greedy_cover_blocks
-                    : std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(nsets * 16, kThreads, cu * 4)));
-            g.nbmax = rg;
             if (g.mark)
                 fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32,
                                                                                            0u);
-            for (uint32_t r = 0; r < lead; ++r) {
+            for (uint32_t r = r0; r < r1; ++r) {
                 refresh_kernel<<<rg, kThreads, 0, st>>>(g, r);
                 cover_kernel<<<cg, kThreads, 0, st>>>(g, r);
             }
-        }
+        };
+        if (lead) grid_rounds(0, lead);
         g.hdr = reinterpret_cast<StepHdr *>(base + o_hdr);
         g.cnode = at32(o_cnode);
         g.cbase = at32(o_cbase);
@@ -1886,7 +1901,10 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
         IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
         StepHdr *hdr = g.hdr;
-        IM_TRY(run_wg_cycles(ctx, dg, &hdr, &k, 1, n, nsets, lead));
+        uint32_t grid_from = k;
+        IM_TRY(run_wg_cycles(ctx, dg, &hdr, &k, 1, n, nsets, lead, &grid_from));
+        if (grid_from < k) grid_rounds(grid_from, k);
+        IM_HIP(hipGetLastError());
         IM_HIP(hipMemcpyAsync(seeds_host, g.seeds, 4ull * k, hipMemcpyDeviceToHost, st));
         IM_TRY(to_host_sync(ctx, cov, dcov, 8));
         return IM_OK;

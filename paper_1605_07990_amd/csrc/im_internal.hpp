@@ -79,9 +79,9 @@ struct im_ctx {
     uint32_t dssa_draw_ahead = 4;           // im_dssa on LT: a draw takes up to this many iterations' sets
     double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
     bool greedy_graph = false;        // replay cached graphs of a range's per-round launches
-    uint64_t greedy_wg_cand_max_entries = 0;  // ranges up to this many entries: one-workgroup candidate rounds
-    double greedy_wg_resel_rate = 0.02;       // running re-selections per round of those rounds
-    uint32_t greedy_wg_cand_grid_rounds = 0;  // of which the first this many run on the grid
+    uint64_t greedy_wg_cand_max_entries = ~0ull;  // ranges up to this many entries: one-workgroup candidate rounds
+    double greedy_wg_resel_rate = 0.02;           // running re-selections per round of those rounds
+    uint32_t greedy_wg_cand_grid_rounds = 16;     // of which the first this many run on the grid
     struct RoundGraphCache *round_graphs = nullptr;
 
     // optional event timing of the main sampler launches

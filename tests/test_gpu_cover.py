@@ -121,9 +121,9 @@ def test_greedy_paths_agree(im, ctx, pools, name, limit, mark, cand):
     marked chunks (mark = 0), or all rounds in one workgroup."""
     g, dg, og, p, op = pools[name]
     note(f"greedy path limit={limit} mark={mark} cand={cand} {name}")
-    names = ("greedy_wg_max_entries", "greedy_mark_min_chunks", "greedy_candidates")
+    names = ("greedy_wg_max_entries", "greedy_mark_min_chunks", "greedy_candidates", "greedy_wg_cand_max_entries")
     old = [ctx.get_param(x) for x in names]
-    for x, v in zip(names, (limit, mark, cand)):
+    for x, v in zip(names, (limit, mark, cand, 0)):
         ctx.set_param(x, v)
     try:
         for k in (1, 50, 300):
@@ -161,8 +161,9 @@ def test_wg_candidate_rounds_agree(im, ctx, pools, name, lead):
 
 @pytest.mark.parametrize("lead", [0, 2])
 def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead):
-    """k = n on a graph without edges (every gain reaches zero), and more
-    sets than the LDS covered-set bitmap holds."""
+    """k = n on a graph without edges (every gain reaches zero), flat gains
+    (the grid-wide rounds take over), and more sets than the LDS covered-set
+    bitmap holds."""
     note(f"one-workgroup candidate rounds: k = n, 400k sets, lead={lead}")
     old = ctx.get_param("greedy_wg_cand_max_entries"), ctx.get_param("greedy_wg_cand_grid_rounds")
     ctx.set_param("greedy_wg_cand_max_entries", 1 << 62)
@@ -177,6 +178,20 @@ def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead):
         op = oracle_lib.Pool(og, 5)
         op.extend(300)
         for k in (1, 39, n):
+            seeds, cov = p.max_coverage(k)
+            oseeds, ocov = op.max_coverage(k)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
+        # flat gains: every set is one node of 200k, so many nodes share each
+        # gain and a bin cut soon keeps too few candidates (grid-wide rounds
+        # finish the range)
+        n = 200_000
+        dg = im.Graph(ctx, n, e, e, w_ic=np.array([], np.float32))
+        og = oracle_lib.Graph(0, n, e, e, np.array([], np.float32))
+        p = im.Pool(dg, 0, 6)
+        p.sample(200_000)
+        op = oracle_lib.Pool(og, 6)
+        op.extend(200_000)
+        for k in (50, 300, 1500):
             seeds, cov = p.max_coverage(k)
             oseeds, ocov = op.max_coverage(k)
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
@@ -207,15 +222,17 @@ def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):
     p.sample(400_000)
     op = oracle_lib.Pool(og, 9)
     op.extend(400_000)
-    old = ctx.get_param("greedy_wg_max_entries")
+    old = ctx.get_param("greedy_wg_max_entries"), ctx.get_param("greedy_wg_cand_max_entries")
     ctx.set_param("greedy_wg_max_entries", 1 << 62)
+    ctx.set_param("greedy_wg_cand_max_entries", 0)
     try:
         for k in (5, 120):
             seeds, cov = p.max_coverage(k)
             oseeds, ocov = op.max_coverage(k)
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
     finally:
-        ctx.set_param("greedy_wg_max_entries", old)
+        ctx.set_param("greedy_wg_max_entries", old[0])
+        ctx.set_param("greedy_wg_cand_max_entries", old[1])
 
 
 @pytest.mark.parametrize("graph", [1, 0])
@@ -225,9 +242,10 @@ def test_greedy_round_graph_replays(im, ctx, pools, graph):
     oracle's seeds on every call, across ranges of one shape and of several
     and across pools."""
     note(f"greedy round graph {graph}")
-    old = ctx.get_param("greedy_graph"), ctx.get_param("greedy_candidates")
+    old = ctx.get_param("greedy_graph"), ctx.get_param("greedy_candidates"), ctx.get_param("greedy_wg_cand_max_entries")
     ctx.set_param("greedy_graph", graph)
     ctx.set_param("greedy_candidates", 0)
+    ctx.set_param("greedy_wg_cand_max_entries", 0)
     try:
         for rep in range(3):
             for name in ("nethept", "rmat16"):
@@ -240,3 +258,4 @@ def test_greedy_round_graph_replays(im, ctx, pools, graph):
     finally:
         ctx.set_param("greedy_graph", old[0])
         ctx.set_param("greedy_candidates", old[1])
+        ctx.set_param("greedy_wg_cand_max_entries", old[2])
