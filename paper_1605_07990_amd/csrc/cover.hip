@@ -99,10 +99,13 @@ __global__ __launch_bounds__(kThreads) void tile_apply_kernel(const uint32_t *in
     }
 }
 
-// 16 lanes per set: scatter the set's index into each member's list.
+// 16 lanes per set: scatter the set's index into each member's list, alone
+// (isets) or with the set's pool extent (iext: index, size, first member as
+// two words), which spares a round the load of the extent.
+template <bool kExt>
 __global__ __launch_bounds__(kThreads) void scatter_kernel(const uint64_t *poff, const uint32_t *pnodes, uint64_t begin,
                                                            uint64_t nsets, const uint64_t *ioff, uint32_t *fill,
-                                                           uint32_t *isets) {
+                                                           uint32_t *isets, uint4 *iext) {
     const uint32_t sub = threadIdx.x & 15u;
     const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
     const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
@@ -111,7 +114,11 @@ __global__ __launch_bounds__(kThreads) void scatter_kernel(const uint64_t *poff,
         for (uint64_t q = a + sub; q < b; q += 16) {
             const uint32_t v = pnodes[q];
             const uint32_t pos = atomicAdd(&fill[v], 1u);
-            isets[ioff[v] + pos] = static_cast<uint32_t>(j);
+            if constexpr (kExt)
+                iext[ioff[v] + pos] = make_uint4(static_cast<uint32_t>(j), static_cast<uint32_t>(b - a),
+                                                 static_cast<uint32_t>(a), static_cast<uint32_t>(a >> 32));
+            else
+                isets[ioff[v] + pos] = static_cast<uint32_t>(j);
         }
     }
 }
@@ -156,6 +163,7 @@ struct GreedyState {
     uint32_t *covbits;  // covered flag per set of the range
     const uint64_t *ioff;
     const uint32_t *isets;
+    const uint4 *iext;  // when set, the entries with their sets' extents (and isets is unused)
     const uint64_t *poff;
     const uint32_t *pnodes;
     uint64_t begin;
@@ -432,10 +440,20 @@ __device__ void cover_seed(const GreedyState &g, uint32_t r, uint32_t v, uint32_
     const uint64_t ngrp = (static_cast<uint64_t>(nblk) * blockDim.x) >> 4;
     unsigned long long newly = 0;
     for (uint64_t i = a + grp; i < b; i += ngrp) {
-        const uint32_t j = g.isets[i];
+        uint32_t j;
+        uint64_t sa, sb;
+        if (g.iext) {
+            const uint4 x = g.iext[i];
+            j = x.x;
+            sa = static_cast<uint64_t>(x.z) | (static_cast<uint64_t>(x.w) << 32);
+            sb = sa + x.y;
+        } else {
+            j = g.isets[i];
+            sa = g.poff[g.begin + j];
+            sb = g.poff[g.begin + j + 1];
+        }
         // the set's extent, its covered flag and its first members are in
         // flight together; the flag decides whether they are used
-        const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
         const uint32_t u0 = sa + sub < sb ? g.pnodes[sa + sub] : 0u;
         const uint32_t bit = 1u << (j & 31u);
         uint32_t prior = bit;
@@ -990,7 +1008,7 @@ struct WgLds {
     uint64_t fstart[kWgThreads];  // newly covered sets of one batch of entries: first member
     uint32_t fsize[kWgThreads];   // and size
     uint32_t cov[kWgCovWords];
-    uint32_t nfresh;
+    uint32_t nfresh[2];  // newly covered sets of a batch, by batch parity
 };
 
 __device__ __forceinline__ uint32_t wg_slot(const WgLds &L, uint32_t u) {
@@ -1014,6 +1032,8 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
         for (uint64_t w = tid; w < words; w += bd) L.cov[w] = g.covbits[w];
     for (uint32_t i = tid; i <= kMask; i += bd) L.key[i] = kNoCand;
     for (uint32_t i = tid; i < (1u << kWgFilterShift) / 32; i += bd) L.filter[i] = 0u;
+    if (tid < 2) L.nfresh[tid] = 0u;
+    uint32_t bp = 0;
     __syncthreads();
     const uint32_t nn = min(*g.ccount, kCandNodes);
     for (uint32_t s = tid; s < nn; s += bd) {
@@ -1067,23 +1087,23 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
         // cover v's sets, one batch of incidence entries at a time: first the
         // newly covered sets are listed, then 16 lanes walk each one's members
         const uint64_t a = L.ia[sv], b = a + L.ilen[sv];
-        for (uint64_t e0 = a; e0 < b; e0 += bd) {
-            if (tid == 0) L.nfresh = 0u;
-            __syncthreads();
+        for (uint64_t e0 = a; e0 < b; e0 += bd, bp ^= 1u) {
+            // the count of this batch (parity bp) was cleared during the one before
             const uint64_t i = e0 + tid;
             if (i < b) {
-                const uint32_t j = g.isets[i];
+                const uint4 x = g.iext[i];
+                const uint32_t j = x.x;
                 const uint32_t bit = 1u << (j & 31u);
                 if (!(atomicOr(&covbits[j >> 5], bit) & bit)) {
-                    const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
-                    const uint32_t f = atomicAdd(&L.nfresh, 1u);
-                    L.fstart[f] = sa;
-                    L.fsize[f] = static_cast<uint32_t>(sb - sa);
+                    const uint32_t f = atomicAdd(&L.nfresh[bp], 1u);
+                    L.fstart[f] = static_cast<uint64_t>(x.z) | (static_cast<uint64_t>(x.w) << 32);
+                    L.fsize[f] = x.y;
                     ++newly;
                 }
             }
             __syncthreads();
-            const uint32_t nf = L.nfresh;
+            const uint32_t nf = L.nfresh[bp];
+            if (tid == 0) L.nfresh[bp ^ 1u] = 0u;
             for (uint32_t f = grp; f < nf; f += ngrp) {
                 const uint64_t sa = L.fstart[f];
                 const uint32_t sz = L.fsize[f];
@@ -1107,7 +1127,7 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
             }
             __syncthreads();
         }
-        __syncthreads();
+        if (a == b) __syncthreads();  // the seed's chosen bit before the next argmax
     }
     if constexpr (kLdsCov) {
         if (stalled)
@@ -1805,6 +1825,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const uint32_t n1 = (n + (1u << kL1Shift) - 1) >> kL1Shift;
     const uint32_t n2 = (n1 + (1u << kL2Shift) - 1) >> kL2Shift;
     const uint64_t covwords = (nsets + 31) / 32 + 1;
+    const bool wgc = k && entries <= ctx->greedy_wg_cand_max_entries;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -1816,7 +1837,8 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     const size_t o_job = take(sizeof(GreedyState));
     const size_t o_gain = take(4ull * n), o_fill = take(4ull * n), o_ioff = take(8ull * (n + 1)),
                  o_tsum = take(8ull * (tiles + 1)), o_cov = take(8), o_seeds = take(4ull * k),
-                 o_covbits = take(4ull * covwords), o_isets = take(4ull * (entries + 1)), o_m1 = take(8ull * n1),
+                 o_covbits = take(4ull * covwords), o_isets = take((wgc ? 16ull : 4ull) * (entries + 1)),
+                 o_m1 = take(8ull * n1),
                  o_m2 = take(8ull * n2),
                  o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096),
                  o_hdr = take(2 * sizeof(StepHdr)), o_cnode = take(4ull * kCandNodes),
@@ -1866,10 +1888,14 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     tile_sums_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gain, n, tsum);
     tile_scan_kernel<<<1, 1024, 0, st>>>(tsum, tiles);
     tile_apply_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gain, n, tsum, ioff);
-    if (nsets)
-        scatter_kernel<<<grid_of(nsets * 16, kThreads, cu * 16), kThreads, 0, st>>>(poff, pnodes, begin, nsets, ioff,
-                                                                                     fill, isets);
-    if (k && entries <= ctx->greedy_wg_cand_max_entries) {
+    if (wgc) g.iext = reinterpret_cast<const uint4 *>(isets);
+    if (nsets && wgc)
+        scatter_kernel<true><<<grid_of(nsets * 16, kThreads, cu * 16), kThreads, 0, st>>>(
+            poff, pnodes, begin, nsets, ioff, fill, nullptr, reinterpret_cast<uint4 *>(isets));
+    else if (nsets)
+        scatter_kernel<false><<<grid_of(nsets * 16, kThreads, cu * 16), kThreads, 0, st>>>(
+            poff, pnodes, begin, nsets, ioff, fill, isets, nullptr);
+    if (wgc) {
         // the first rounds (the large covers) on the grid, two launches each,
         // which keep every gain exact; the rest in one workgroup over
         // candidate nodes
