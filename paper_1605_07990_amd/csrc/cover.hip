@@ -1059,34 +1059,43 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
     uint32_t r = h.r;
     bool stalled = false;
     const uint32_t grp = tid >> 4, sub = tid & 15u, ngrp = bd >> 4;
+    const uint32_t lane = lane_id();
     for (; r < g.k; ++r) {
+        // every wave finds the largest candidate key itself (they all read
+        // the same LDS, so they agree) and, from the lane holding it, its slot
         unsigned long long best = 0;
-        for (uint32_t s = tid; s < nn; s += bd) {
+        uint32_t bslot = kNoCand;
+        for (uint32_t s = lane; s < nn; s += kWave) {
             const uint32_t x = L.cg[s];
             if (!(x & kChosen)) {
                 const unsigned long long key = (static_cast<unsigned long long>(x) << 32) | static_cast<unsigned long long>(~L.node[s]);
-                best = key > best ? key : best;
+                if (key > best) {
+                    best = key;
+                    bslot = s;
+                }
             }
         }
-        best = block_max_u64(best, L.smem);
-        if (best <= h.thresh) {  // the same value in every thread
+        const unsigned long long wbest = wave_max_u64(best);
+        if (wbest <= h.thresh) {  // the same value in every wave
             stalled = true;
             break;
         }
-        const uint32_t v = ~static_cast<uint32_t>(best & 0xFFFFFFFFull);
-        const uint32_t sv = wg_slot(L, v);  // v is a candidate: best came from L.cg
-        if (sv == kNoCand) {  // cannot happen; leave the job for a re-selection
-            stalled = true;
-            break;
-        }
+        const unsigned long long holder = __ballot(best == wbest);
+        const uint32_t sv = __shfl(bslot, static_cast<int>(__ffsll(holder)) - 1, kWave);
+        const uint32_t v = ~static_cast<uint32_t>(wbest & 0xFFFFFFFFull);
         if (tid == 0) {
             g.seeds[r] = v;
             atomicOr(&g.gain[v], kChosen);
-            L.cg[sv] |= kChosen;
+        }
+        const uint64_t a = L.ia[sv], b = a + L.ilen[sv];
+        if (a == b) {  // v is in no set (every gain left is zero): only its chosen bit
+            __syncthreads();
+            if (tid == 0) L.cg[sv] |= kChosen;
+            __syncthreads();
+            continue;
         }
         // cover v's sets, one batch of incidence entries at a time: first the
         // newly covered sets are listed, then 16 lanes walk each one's members
-        const uint64_t a = L.ia[sv], b = a + L.ilen[sv];
         for (uint64_t e0 = a; e0 < b; e0 += bd, bp ^= 1u) {
             // the count of this batch (parity bp) was cleared during the one before
             const uint64_t i = e0 + tid;
@@ -1103,7 +1112,11 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
             }
             __syncthreads();
             const uint32_t nf = L.nfresh[bp];
-            if (tid == 0) L.nfresh[bp ^ 1u] = 0u;
+            if (tid == 0) {
+                L.nfresh[bp ^ 1u] = 0u;
+                // every wave has read the candidates for this round's argmax
+                if (e0 == a) atomicOr(&L.cg[sv], kChosen);
+            }
             for (uint32_t f = grp; f < nf; f += ngrp) {
                 const uint64_t sa = L.fstart[f];
                 const uint32_t sz = L.fsize[f];
@@ -1127,7 +1140,6 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
             }
             __syncthreads();
         }
-        if (a == b) __syncthreads();  // the seed's chosen bit before the next argmax
     }
     if constexpr (kLdsCov) {
         if (stalled)
@@ -1148,7 +1160,7 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
 // Job blockIdx.x: rounds over its listed candidates until done or the test fails.
 __global__ __launch_bounds__(kWgThreads) void wg_round_kernel(const GreedyState *jobs) {
     __shared__ WgLds L;
-    const GreedyState &g = jobs[blockIdx.x];
+    const GreedyState g = jobs[blockIdx.x];  // a copy: the rounds' loads must not wait on its fields
     const StepHdr h = g.hdr[0];
     if (h.phase != kStepCollect) return;
     const uint64_t words = (g.nsets + 31) / 32;
