@@ -182,7 +182,7 @@ struct GreedyState {
     uint32_t *cdec;       // [3][kCandNodes] drops of candidate nodes in one round
     uint32_t want;        // candidate chunks asked for
     // one-workgroup candidate rounds
-    uint32_t *hist;       // [kSelBins] unchosen nodes per gain bin
+    uint32_t *hist;       // [2][kSelBins] unchosen nodes per gain bin, by re-selection parity
     uint32_t *ccount;     // candidates listed
 };
 
@@ -974,6 +974,7 @@ constexpr int kWgThreads = 1024;
 constexpr uint32_t kWgCovWords = 8192;  // covered-set bits kept in LDS (262,144 sets)
 constexpr uint32_t kStepCollect = 4;     // header phase: candidates listed under thresh
 constexpr uint32_t kStepGrid = 5;        // header phase: the remaining rounds go to the grid-wide path
+constexpr uint32_t kStepZero = 6;        // header phase: every unchosen gain is zero
 constexpr uint32_t kWgMinCand = 64;      // fewer candidates than this (and than rounds left): grid rounds
 constexpr uint32_t kSelExact = 2048;     // gains below this have a bin of their own
 constexpr uint32_t kSelBins = kSelExact + 8 * 20;  // then eight bins per power of two, up to 2^31
@@ -1117,24 +1118,55 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
                 // every wave has read the candidates for this round's argmax
                 if (e0 == a) atomicOr(&L.cg[sv], kChosen);
             }
-            for (uint32_t f = grp; f < nf; f += ngrp) {
-                const uint64_t sa = L.fstart[f];
-                const uint32_t sz = L.fsize[f];
-                // a lane's members of the set are all in flight before any is used
-                for (uint32_t q0 = 0; q0 < sz; q0 += 128) {
-                    uint32_t u[8];
+            // a candidate among a set's members loses one gain
+            auto drop = [&](uint32_t u) {
+                if (u == kNoCand) return;
+                const uint32_t fb = wg_filter_bit(u);
+                if (!((L.filter[fb >> 5] >> (fb & 31u)) & 1u)) return;
+                const uint32_t slot = wg_slot(L, u);
+                if (slot != kNoCand) atomicSub(&L.cg[slot], 1u);
+            };
+            if (nf > ngrp) {
+                // many sets: four per group at a time, so that a lane has the
+                // members of all four in flight before any is used
+                for (uint32_t f = grp; f < nf; f += 4 * ngrp) {
+                    uint64_t sa[4];
+                    uint32_t sz[4];
+                    uint32_t mx = 0;
 #pragma unroll
-                    for (uint32_t t = 0; t < 8; ++t) {
-                        const uint32_t q = q0 + sub + 16u * t;
-                        u[t] = q < sz ? g.pnodes[sa + q] : kNoCand;
+                    for (uint32_t w = 0; w < 4; ++w) {
+                        const uint32_t ff = f + w * ngrp;
+                        sa[w] = ff < nf ? L.fstart[ff] : 0ull;
+                        sz[w] = ff < nf ? L.fsize[ff] : 0u;
+                        mx = sz[w] > mx ? sz[w] : mx;
                     }
+                    for (uint32_t q0 = 0; q0 < mx; q0 += 64) {
+                        uint32_t u[16];
 #pragma unroll
-                    for (uint32_t t = 0; t < 8; ++t) {
-                        if (u[t] == kNoCand) continue;
-                        const uint32_t fb = wg_filter_bit(u[t]);
-                        if (!((L.filter[fb >> 5] >> (fb & 31u)) & 1u)) continue;
-                        const uint32_t slot = wg_slot(L, u[t]);
-                        if (slot != kNoCand) atomicSub(&L.cg[slot], 1u);
+                        for (uint32_t w = 0; w < 4; ++w)
+#pragma unroll
+                            for (uint32_t t = 0; t < 4; ++t) {
+                                const uint32_t q = q0 + sub + 16u * t;
+                                u[4 * w + t] = q < sz[w] ? g.pnodes[sa[w] + q] : kNoCand;
+                            }
+#pragma unroll
+                        for (uint32_t t = 0; t < 16; ++t) drop(u[t]);
+                    }
+                }
+            } else {
+                for (uint32_t f = grp; f < nf; f += ngrp) {
+                    const uint64_t sa = L.fstart[f];
+                    const uint32_t sz = L.fsize[f];
+                    // a lane's members of the set are all in flight before any is used
+                    for (uint32_t q0 = 0; q0 < sz; q0 += 128) {
+                        uint32_t u[8];
+#pragma unroll
+                        for (uint32_t t = 0; t < 8; ++t) {
+                            const uint32_t q = q0 + sub + 16u * t;
+                            u[t] = q < sz ? g.pnodes[sa + q] : kNoCand;
+                        }
+#pragma unroll
+                        for (uint32_t t = 0; t < 8; ++t) drop(u[t]);
                     }
                 }
             }
@@ -1161,8 +1193,36 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
 __global__ __launch_bounds__(kWgThreads) void wg_round_kernel(const GreedyState *jobs) {
     __shared__ WgLds L;
     const GreedyState g = jobs[blockIdx.x];  // a copy: the rounds' loads must not wait on its fields
-    const StepHdr h = g.hdr[0];
-    if (h.phase != kStepCollect) return;
+    StepHdr h = g.hdr[0];
+    if (h.phase == kStepZero) {
+        // every unchosen gain is zero: the argmax takes the unchosen ids in
+        // order, so the candidates are the kCandNodes lowest and the bound is
+        // the key of the next one (0 if there is none)
+        __shared__ uint64_t zscan[kWgThreads / kWave];
+        __shared__ unsigned long long s_t;
+        if (threadIdx.x == 0) s_t = 0ull;
+        uint64_t seen = 0;
+        for (uint32_t base = 0; base < g.n; base += blockDim.x) {
+            const uint32_t v = base + threadIdx.x;
+            const uint64_t f = (v < g.n && !(g.gain[v] & kChosen)) ? 1u : 0u;
+            uint64_t tot = 0;
+            const uint64_t pre = block_scan_excl(f, zscan, tot);
+            if (f && seen + pre < kCandNodes) {
+                g.cnode[seen + pre] = v;
+                g.cbase[seen + pre] = 0u;
+            }
+            if (f && seen + pre == kCandNodes) s_t = static_cast<unsigned long long>(~v);
+            seen += tot;
+            if (seen > kCandNodes) break;  // the same in every thread
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *g.ccount = static_cast<uint32_t>(min<uint64_t>(seen, kCandNodes));
+        h.thresh = s_t;
+        __threadfence_block();
+        __syncthreads();
+    } else if (h.phase != kStepCollect) {
+        return;
+    }
     const uint64_t words = (g.nsets + 31) / 32;
     if (words <= kWgCovWords) wg_rounds<true>(g, h, words, L);
     else wg_rounds<false>(g, h, words, L);
@@ -1190,12 +1250,15 @@ __global__ __launch_bounds__(kThreads) void wg_recount_kernel(const GreedyState 
     }
 }
 
-// Re-selection, step 3: how many unchosen nodes have a gain in each bin
-// (into g.hist, which the cut step leaves zeroed).
+// Re-selection, step 3: how many unchosen nodes have a gain in each bin,
+// into the histogram of this re-selection's parity (the collect step of the
+// one before left it zeroed).
 __global__ __launch_bounds__(kThreads) void wg_hist_kernel(const GreedyState *jobs) {
     __shared__ uint32_t hl[kSelBins];
     const GreedyState &g = jobs[blockIdx.y];
-    if (g.hdr[0].phase != kStepRefresh) return;
+    const StepHdr h = g.hdr[0];
+    if (h.phase != kStepRefresh) return;
+    uint32_t *hist = g.hist + (h.stalls & 1u) * kSelBins;
     for (uint32_t i = threadIdx.x; i < kSelBins; i += blockDim.x) hl[i] = 0u;
     __syncthreads();
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
@@ -1204,28 +1267,31 @@ __global__ __launch_bounds__(kThreads) void wg_hist_kernel(const GreedyState *jo
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kSelBins; i += blockDim.x)
-        if (hl[i]) atomicAdd(&g.hist[i], hl[i]);
+        if (hl[i]) atomicAdd(&hist[i], hl[i]);
 }
 
-// Re-selection, step 4 (job blockIdx.x, one 256-thread block): the bound
-// thresh on the keys left out, from the lowest bin b whose nodes, with those
-// of the bins above, number at most kCandNodes; thresh is then the largest
-// key a gain below bin b can have. If every unchosen gain is zero, the
-// candidates are the lowest unchosen ids (the argmax then takes them in id
-// order) and thresh is the key of the next one. Leaves the header in
-// COLLECT, or in GRID when the cut keeps fewer than kWgMinCand nodes and
-// fewer than the rounds left (flat gains: many nodes share the gain at the
-// cut), so that the host finishes the range with grid-wide rounds, which
-// need no candidates.
-__global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *jobs) {
+// Re-selection, step 4 (grid, blockIdx.y = job): every block reads the
+// histogram and finds the same cut: the lowest bin b whose nodes, with those
+// of the bins above, number at most kCandNodes. The bound on the keys left
+// out is then the largest key a gain below bin b can have, and each block
+// lists its nodes whose key beats it. If every unchosen gain is zero the
+// header goes to ZERO (the round kernel lists the lowest unchosen ids
+// itself); if the cut keeps fewer than kWgMinCand nodes and fewer than the
+// rounds left (flat gains: many nodes share the gain at the cut), to GRID,
+// and the host finishes the range with grid-wide rounds, which need no
+// candidates. Block 0 writes the header and clears the other parity's
+// histogram for the next re-selection.
+__global__ __launch_bounds__(kThreads) void wg_collect_kernel(const GreedyState *jobs) {
     constexpr uint32_t kPer = (kSelBins + kThreads - 1) / kThreads;
     __shared__ uint64_t scan[kThreads / kWave];
     __shared__ uint32_t s_cut;
-    __shared__ unsigned long long s_t;
-    const GreedyState &g = jobs[blockIdx.x];
+    const GreedyState &g = jobs[blockIdx.y];
     const StepHdr h = g.hdr[0];
-    if (h.phase != kStepRefresh) return;
+    // block 0 may already have moved the header on
+    if (h.phase != kStepRefresh && h.phase != kStepCollect) return;
     const uint32_t tid = threadIdx.x;
+    const uint32_t par = h.stalls & 1u;
+    const uint32_t *hist = g.hist + par * kSelBins;
     // thread tid holds bins [c kPer, c kPer + kPer) with c = 255 - tid, so a
     // prefix over threads counts the bins above
     const uint32_t c = kThreads - 1u - tid;
@@ -1234,7 +1300,7 @@ __global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *job
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i) {
         const uint32_t b = c * kPer + i;
-        cnt[i] = (b >= 1u && b < kSelBins) ? g.hist[b] : 0u;
+        cnt[i] = (b >= 1u && b < kSelBins) ? hist[b] : 0u;
         sum += cnt[i];
     }
     if (tid == 0) s_cut = kNoCand;
@@ -1248,60 +1314,36 @@ __global__ __launch_bounds__(kThreads) void wg_cut_kernel(const GreedyState *job
         if (b >= 1u && b < kSelBins && run <= kCandNodes) atomicMin(&s_cut, b);
     }
     __syncthreads();
-    for (uint32_t i = tid; i < kSelBins; i += blockDim.x) g.hist[i] = 0u;
     const uint32_t cut = s_cut;
-    // nodes in the bins from cut up
     uint64_t mine = 0;
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i)
         if (c * kPer + i >= cut) mine += cnt[i];
     uint64_t kept = 0;
     (void)block_scan_excl(mine, scan, kept);
-    const uint32_t left = g.k - h.r;
-    if (total != 0 && (cut == kNoCand || (kept < kWgMinCand && kept < left))) {
-        if (tid == 0) g.hdr[0].phase = kStepGrid;
-        return;
-    }
-    unsigned long long thresh = 0;
-    if (total == 0) {
-        // every unchosen gain is zero: find the (kCandNodes + 1)-th unchosen id
-        if (tid == 0) s_t = 0ull;
-        __syncthreads();
-        uint64_t seen = 0;
-        for (uint32_t base = 0; base < g.n; base += blockDim.x) {
-            const uint32_t v = base + tid;
-            const uint64_t f = (v < g.n && !(g.gain[v] & kChosen)) ? 1u : 0u;
-            uint64_t tot = 0;
-            const uint64_t pre = block_scan_excl(f, scan, tot);
-            if (f && seen + pre == kCandNodes) s_t = static_cast<unsigned long long>(~v);
-            seen += tot;
-            __syncthreads();
-            if (seen > kCandNodes) break;  // the same in every thread
+    uint32_t phase = kStepCollect;
+    if (total == 0) phase = kStepZero;
+    else if (cut == kNoCand || (kept < kWgMinCand && kept < g.k - h.r)) phase = kStepGrid;
+    const unsigned long long thresh =
+        phase == kStepCollect ? (static_cast<unsigned long long>(sel_bin_low(cut) - 1u) << 32) | 0xFFFFFFFFull : 0ull;
+    if (blockIdx.x == 0) {
+        uint32_t *other = g.hist + (par ^ 1u) * kSelBins;
+        for (uint32_t i = tid; i < kSelBins; i += blockDim.x) other[i] = 0u;
+        if (tid == 0) {
+            g.hdr[0].thresh = thresh;
+            g.hdr[0].phase = phase;
         }
-        thresh = s_t;
-    } else {
-        thresh = (static_cast<unsigned long long>(sel_bin_low(cut) - 1u) << 32) | 0xFFFFFFFFull;
     }
-    if (tid == 0) {
-        g.hdr[0].thresh = thresh;
-        g.hdr[0].phase = kStepCollect;
-    }
-}
-
-// Re-selection, step 5 (grid): list every unchosen node whose key beats thresh.
-__global__ __launch_bounds__(kThreads) void wg_collect_kernel(const GreedyState *jobs) {
-    const GreedyState &g = jobs[blockIdx.y];
-    const StepHdr h = g.hdr[0];
-    if (h.phase != kStepCollect) return;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+    if (phase != kStepCollect) return;
+    for (uint32_t v = blockIdx.x * blockDim.x + tid; v < g.n; v += gridDim.x * blockDim.x) {
         const uint32_t x = g.gain[v];
         if (x & kChosen) continue;
         const unsigned long long key = (static_cast<unsigned long long>(x) << 32) | static_cast<unsigned long long>(~v);
-        if (key > h.thresh) {
-            const uint32_t s = atomicAdd(g.ccount, 1u);
-            if (s < kCandNodes) {
-                g.cnode[s] = v;
-                g.cbase[s] = x;
+        if (key > thresh) {
+            const uint32_t slot = atomicAdd(g.ccount, 1u);
+            if (slot < kCandNodes) {
+                g.cnode[slot] = v;
+                g.cbase[slot] = x;
             }
         }
     }
@@ -1661,8 +1703,8 @@ __global__ void wg_start_kernel(const GreedyState *jobs, uint32_t nj, uint32_t r
 }
 
 // One-workgroup candidate rounds [r0, k) for nj jobs (job j's header at
-// hdrs[j]), whose gains are exact. The first cut, collect and rounds run
-// at once; then cycles (clear, recount, hist, cut, collect, rounds) are
+// hdrs[j]), whose gains are exact. The first hist, collect and rounds run
+// at once; then cycles (clear, recount, hist, collect, rounds) are
 // queued at the context's running re-selection rate and the headers read
 // back once per batch of cycles, until every job has its k seeds or (one
 // job only) the cut asks for grid-wide rounds: then *grid_from is the first
@@ -1672,12 +1714,12 @@ static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *con
     hipStream_t st = ctx->stream;
     *grid_from = ks[0];
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+    // the collect blocks each derive the cut from the whole histogram, so a few
     const dim3 gn(grid_of(n, kThreads, cu * 8), nj), gh(grid_of(n, kThreads * 8, cu * 2), nj),
-        gs(grid_of(max_sets * 16, kThreads, cu * 16), nj);
+        gs(grid_of(max_sets * 16, kThreads, cu * 16), nj), gc(grid_of(n, kThreads * 16, cu), nj);
     wg_start_kernel<<<(nj + 255) / 256, 256, 0, st>>>(dgs, nj, r0);
     wg_hist_kernel<<<gh, kThreads, 0, st>>>(dgs);
-    wg_cut_kernel<<<nj, kThreads, 0, st>>>(dgs);
-    wg_collect_kernel<<<gn, kThreads, 0, st>>>(dgs);
+    wg_collect_kernel<<<gc, kThreads, 0, st>>>(dgs);
     wg_round_kernel<<<nj, kWgThreads, 0, st>>>(dgs);
     uint32_t max_k = 0;
     for (uint32_t j = 0; j < nj; ++j) max_k = std::max(max_k, ks[j]);
@@ -1690,8 +1732,7 @@ static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *con
             wg_clear_kernel<<<gn, kThreads, 0, st>>>(dgs);
             wg_recount_kernel<<<gs, kThreads, 0, st>>>(dgs);
             wg_hist_kernel<<<gh, kThreads, 0, st>>>(dgs);
-            wg_cut_kernel<<<nj, kThreads, 0, st>>>(dgs);
-            wg_collect_kernel<<<gn, kThreads, 0, st>>>(dgs);
+            wg_collect_kernel<<<gc, kThreads, 0, st>>>(dgs);
             wg_round_kernel<<<nj, kWgThreads, 0, st>>>(dgs);
         }
         cycles += est;
@@ -1855,7 +1896,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
                  o_dirty = take(4ull * ((n1 + 31) / 32)), o_bmax = take(8ull * 4096),
                  o_hdr = take(2 * sizeof(StepHdr)), o_cnode = take(4ull * kCandNodes),
                  o_cbase = take(8ull * kCandNodes), o_cdec = take(12ull * kCandNodes),
-                 o_hist = take(4ull * kSelBins), o_ccount = take(4);
+                 o_hist = take(8ull * kSelBins), o_ccount = take(4);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto at32 = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
@@ -1935,7 +1976,7 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
         g.cbase = at32(o_cbase);
         g.hist = at32(o_hist);
         g.ccount = at32(o_ccount);
-        fill_u32_kernel<<<grid_of(kSelBins, kThreads, 64), kThreads, 0, st>>>(g.hist, kSelBins, 0u);
+        fill_u32_kernel<<<grid_of(2 * kSelBins, kThreads, 64), kThreads, 0, st>>>(g.hist, 2 * kSelBins, 0u);
         auto *dg = reinterpret_cast<GreedyState *>(base + o_job);
         IM_HIP(hipMemcpyAsync(dg, &g, sizeof(g), hipMemcpyHostToDevice, st));
         StepHdr *hdr = g.hdr;
