@@ -332,7 +332,13 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       the two parameters above and IM_PARAM_GREEDY_WG_MAX_ENTRIES;
  *   IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS the first this many rounds of such
  *       a range run grid-wide, two launches each (they cover the most sets),
- *       before the one-workgroup rounds take over (default 16).
+ *       before the one-workgroup rounds take over (default 16);
+ *   IM_PARAM_DSSA_GREEDY_AHEAD    im_dssa covers up to this many later
+ *       iterations (0..2) at once, each on a helper context with its own
+ *       stream and thread, once the pool holds their sets: iteration t's
+ *       Max-Coverage reads only R_t, so the result is the one the iteration
+ *       would compute, and it is dropped if the run stops first. The pool
+ *       never grows while a helper runs (default 2).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -347,7 +353,8 @@ typedef enum {
     IM_PARAM_DSSA_DRAW_AHEAD = 8,
     IM_PARAM_GREEDY_GRAPH = 9,
     IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES = 10,
-    IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 11
+    IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 11,
+    IM_PARAM_DSSA_GREEDY_AHEAD = 12
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -28,6 +28,7 @@ CANDIDATES = {
     "dssa_draw_ahead": [1, 2, 4, 8],
     "greedy_wg_cand_max_entries": [0, 1 << 20, 1 << 22, 1 << 24, 1 << 62],
     "greedy_wg_cand_grid_rounds": [0, 4, 8, 16, 32],
+    "dssa_greedy_ahead": [0, 1, 2],
 }
 
 

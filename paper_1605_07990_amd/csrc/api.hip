@@ -161,32 +161,56 @@ im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps,
 // Largest batch drawn at once: LT reserves a staging region per sample.
 uint64_t max_batch(im_model model) { return model == IM_LT ? (1ull << 20) : (1ull << 24); }
 
-im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
-    if (!ctx->aux) {
-        auto *a = new (std::nothrow) im_ctx();
-        if (!a) return IM_E_OOM;
-        a->device = ctx->device;
-        a->alloc = ctx->alloc;
-        a->free_ = ctx->free_;
-        a->user = ctx->user;
-        a->cu_count = ctx->cu_count;
-        a->total_mem = ctx->total_mem;
-        a->slot_budget = ctx->slot_budget;
-        a->speculate = false;
-        if (hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete a;
-            set_error("auxiliary stream creation failed");
-            return IM_E_DEVICE;
-        }
-        a->owns_stream = true;
-        if (hipHostMalloc(&a->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
-            (void)hipStreamDestroy(a->stream);
-            delete a;
-            set_error("pinned host allocation failed");
-            return IM_E_OOM;
-        }
-        ctx->aux = a;
+// A context on the same device and allocator with its own stream and work
+// buffers (its launch parameters are copied from ctx on each use).
+static im_status new_side_ctx(im_ctx *ctx, im_ctx **out) {
+    auto *a = new (std::nothrow) im_ctx();
+    if (!a) return IM_E_OOM;
+    a->device = ctx->device;
+    a->alloc = ctx->alloc;
+    a->free_ = ctx->free_;
+    a->user = ctx->user;
+    a->cu_count = ctx->cu_count;
+    a->total_mem = ctx->total_mem;
+    a->slot_budget = ctx->slot_budget;
+    a->speculate = false;
+    if (hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete a;
+        set_error("helper stream creation failed");
+        return IM_E_DEVICE;
     }
+    a->owns_stream = true;
+    if (hipHostMalloc(&a->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        (void)hipStreamDestroy(a->stream);
+        delete a;
+        set_error("pinned host allocation failed");
+        return IM_E_OOM;
+    }
+    *out = a;
+    return IM_OK;
+}
+
+static void copy_greedy_params(const im_ctx *from, im_ctx *to) {
+    to->greedy_wg_max_entries = from->greedy_wg_max_entries;
+    to->greedy_mark_min_chunks = from->greedy_mark_min_chunks;
+    to->greedy_cover_blocks = from->greedy_cover_blocks;
+    to->greedy_candidates = from->greedy_candidates;
+    to->greedy_candidates_batch = from->greedy_candidates_batch;
+    to->greedy_graph = from->greedy_graph;
+    to->greedy_wg_cand_max_entries = from->greedy_wg_cand_max_entries;
+    to->greedy_wg_cand_grid_rounds = from->greedy_wg_cand_grid_rounds;
+}
+
+// Helper context i (0 or 1) of ctx for later iterations' Max-Coverage.
+static im_status helper_ctx(im_ctx *ctx, int i, im_ctx **out) {
+    if (!ctx->helpers[i]) IM_TRY(new_side_ctx(ctx, &ctx->helpers[i]));
+    copy_greedy_params(ctx, ctx->helpers[i]);
+    *out = ctx->helpers[i];
+    return IM_OK;
+}
+
+im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
+    if (!ctx->aux) IM_TRY(new_side_ctx(ctx, &ctx->aux));
     im_ctx *a = ctx->aux;
     if (ctx->timing && !a->ev_begin) {
         IM_HIP(hipEventCreate(&a->ev_begin));
@@ -360,6 +384,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > (1ull << 31)) break;
         c->greedy_wg_cand_grid_rounds = static_cast<uint32_t>(value);
         return IM_OK;
+    case IM_PARAM_DSSA_GREEDY_AHEAD:
+        if (value > 2) break;
+        c->dssa_greedy_ahead = static_cast<uint32_t>(value);
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -405,6 +433,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
     case IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS:
         *value = c->greedy_wg_cand_grid_rounds;
         return IM_OK;
+    case IM_PARAM_DSSA_GREEDY_AHEAD:
+        *value = c->dssa_greedy_ahead;
+        return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
     return IM_E_ARG;
@@ -436,6 +467,8 @@ extern "C" im_status im_ctx_read_timing(im_ctx *c, im_kernel_times *out, int res
 extern "C" void im_ctx_free(im_ctx *c) {
     if (!c) return;
     if (c->aux) im_ctx_free(c->aux);
+    for (im_ctx *h : c->helpers)
+        if (h) im_ctx_free(h);
     (void)hipStreamSynchronize(c->stream);
     if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
@@ -875,6 +908,43 @@ struct Speculation {
     }
 };
 
+// Max-Coverage of a later D-SSA iteration's R_t = [0, N_t) and its stare
+// count over [N_t, 2 N_t), on a helper context in a thread of its own. The
+// result depends only on those sets, so it is the iteration's own whenever
+// the loop gets there; if the loop stops first it is dropped.
+struct AheadCover {
+    std::thread th;
+    bool running = false;
+    im_status rc = IM_OK;
+    std::string err;
+    uint64_t nt = 0, cov = 0, cov_c = 0;
+    std::vector<uint32_t> seeds;
+
+    void start(im_ctx *h, const im_pool *p, uint64_t n_t, uint32_t k) {
+        nt = n_t;
+        seeds.assign(k, 0u);
+        rc = IM_OK;
+        running = true;
+        th = std::thread([this, h, p, k] {
+            if (hipSetDevice(h->device) != hipSuccess) {
+                rc = IM_E_DEVICE;
+                err = "hipSetDevice failed in the cover thread";
+                return;
+            }
+            rc = max_coverage_on(h, p, 0, nt, k, seeds.data(), &cov);
+            if (rc == IM_OK) rc = coverage_range_on(h, p, nt, 2 * nt, seeds.data(), k, &cov_c);
+            if (rc != IM_OK) err = im_last_error();
+        });
+    }
+    im_status join() {
+        if (!running) return IM_OK;
+        th.join();
+        running = false;
+        if (rc != IM_OK) set_error("%s", err.c_str());
+        return rc;
+    }
+};
+
 }  // namespace
 
 extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
@@ -904,6 +974,22 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     uint64_t most = 2 * n1;
     while (double(most / 2) < c.n_max && most < (1ull << 62)) most *= 2;
     im_status rc = IM_OK;
+    // later iterations' covers running on helper contexts (slot = helper)
+    AheadCover ahead[2];
+    const uint32_t n_ahead = ctx->dssa_greedy_ahead;
+    im_ctx *helpers[2] = {nullptr, nullptr};
+    for (uint32_t i = 0; i < n_ahead; ++i)
+        if (helper_ctx(ctx, int(i), &helpers[i]) != IM_OK) helpers[i] = nullptr;  // run without
+    clear_error();
+    // every helper is done before the pool's buffers may move
+    auto join_ahead = [&]() {
+        im_status r = IM_OK;
+        for (AheadCover &a : ahead) {
+            const im_status x = a.join();
+            if (r == IM_OK) r = x;
+        }
+        return r;
+    };
     for (uint32_t t = 1;; ++t) {
         const uint64_t nt = n1 << (t - 1);
         double t0 = now_ms();
@@ -911,6 +997,7 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
             // the previous iteration drew this one's new sets on the side
             if ((rc = spec.join())) break;
             if (spec.s0 == pool->count) {
+                if ((rc = join_ahead())) break;
                 AppendItem ap{pool, spec.count, spec.tot.nodes, spec.tot.edges};
                 if ((rc = pool_append_items(aux, &ap, 1))) break;
             }
@@ -922,6 +1009,7 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         uint64_t target = 2 * nt;
         if (model == IM_LT && pool->count < target && ctx->dssa_draw_ahead > 1)
             target = std::max(target, std::min(most, 2 * nt * ctx->dssa_draw_ahead));
+        if (pool->count < target && (rc = join_ahead())) break;
         if ((rc = pool_extend_to(pool, target, nullptr))) break;
         const double ms_fresh = now_ms() - t_fresh;  // this iteration's own draw, if any
         st->ms_sample += now_ms() - t0;
@@ -934,14 +1022,52 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         if (aux && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw &&
             pool->count < 4 * nt)
             spec.start(aux, pool, pool->count, 4 * nt - pool->count);
+        // the next iterations whose sets are all drawn are covered on the
+        // helper contexts meanwhile (at most one per helper)
+        bool synced = false;
+        for (uint32_t j = 1; j <= n_ahead; ++j) {
+            const uint64_t nj = nt << j;
+            if (double(nj >> 1) >= c.n_max || 2 * nj > pool->count) break;
+            bool have = false;
+            for (AheadCover &a : ahead) have = have || (a.running && a.nt == nj);
+            if (have) continue;
+            for (uint32_t i = 0; i < n_ahead; ++i) {
+                if (!helpers[i] || ahead[i].running) continue;
+                if (!synced) {
+                    // the pool's sets were written on this context's stream
+                    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                        set_error("stream synchronize failed");
+                        rc = IM_E_DEVICE;
+                    }
+                    synced = true;
+                }
+                if (rc == IM_OK) ahead[i].start(helpers[i], pool, nj, k);
+                break;
+            }
+            if (rc != IM_OK) break;
+        }
+        if (rc != IM_OK) break;
         uint64_t cov = 0, cov_c = 0;
+        AheadCover *mine = nullptr;
+        for (AheadCover &a : ahead)
+            if (a.running && a.nt == nt) mine = &a;
         t0 = now_ms();
-        if ((rc = max_coverage(pool, 0, nt, k, seeds.data(), &cov))) break;
-        ms_cover_last = now_ms() - t0;
-        st->ms_cover += ms_cover_last;
-        t0 = now_ms();
-        if ((rc = coverage_range(pool, nt, 2 * nt, seeds.data(), k, &cov_c))) break;
-        st->ms_verify += now_ms() - t0;
+        if (mine) {
+            // covered on a helper since an earlier iteration
+            if ((rc = mine->join())) break;
+            std::copy(mine->seeds.begin(), mine->seeds.end(), seeds.begin());
+            cov = mine->cov;
+            cov_c = mine->cov_c;
+            ms_cover_last = now_ms() - t0;
+            st->ms_cover += ms_cover_last;
+        } else {
+            if ((rc = max_coverage(pool, 0, nt, k, seeds.data(), &cov))) break;
+            ms_cover_last = now_ms() - t0;
+            st->ms_cover += ms_cover_last;
+            t0 = now_ms();
+            if ((rc = coverage_range(pool, nt, 2 * nt, seeds.data(), k, &cov_c))) break;
+            st->ms_verify += now_ms() - t0;
+        }
         const double i_hat = n * double(cov) / double(nt);
         st->iterations = t;
         st->n_sets = 2 * nt;
@@ -978,6 +1104,8 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     }
     const im_status rs = spec.join();  // a draw still running is waited for and dropped
     if (rc == IM_OK) rc = rs;
+    const im_status ra = join_ahead();  // so are covers of iterations not reached
+    if (rc == IM_OK) rc = ra;
     if (rc == IM_OK) {
         st->edges = pool->edges;
         if (pool->count > st->n_sets) {

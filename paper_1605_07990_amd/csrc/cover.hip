@@ -1622,7 +1622,11 @@ im_status seed_bits_into(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, ui
 
 im_status coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host, uint32_t k,
                          uint64_t *cov) {
-    im_ctx *ctx = p->ctx;
+    return coverage_range_on(p->ctx, p, begin, end, seeds_host, k, cov);
+}
+
+im_status coverage_range_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host,
+                            uint32_t k, uint64_t *cov) {
     IM_TRY(set_seed_bits(ctx, p->g->n, seeds_host, k));
     IM_TRY(dev_reserve(ctx, ctx->counters, 256));
     auto *out = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->counters.ptr) + 128);
@@ -1862,7 +1866,11 @@ static im_status round_graph(im_ctx *ctx, const GreedyState *dg, uint32_t k, uin
 
 im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k, uint32_t *seeds_host,
                        uint64_t *cov) {
-    im_ctx *ctx = p->ctx;
+    return max_coverage_on(p->ctx, p, begin, end, k, seeds_host, cov);
+}
+
+im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, uint32_t k,
+                          uint32_t *seeds_host, uint64_t *cov) {
     const uint32_t n = p->g->n;
     const uint64_t nsets = end - begin;
     const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);

@@ -93,6 +93,10 @@ struct im_ctx {
     // own work buffers), used by a helper thread to draw the next D-SSA
     // iteration's sets while the current one is covered; created on first use
     im_ctx *aux = nullptr;
+    // contexts on their own streams that run later D-SSA iterations'
+    // Max-Coverage while the current one is covered; created on first use
+    im_ctx *helpers[2] = {nullptr, nullptr};
+    uint32_t dssa_greedy_ahead = 2;  // later iterations covered at once (0..2)
     bool owns_stream = false;
     size_t slot_budget = 8ull << 30;  // long-path slot memory cap
     bool speculate = true;
@@ -197,6 +201,13 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
 // Cov of seeds over [begin, end).
 im_status coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host,
                          uint32_t k, uint64_t *cov);
+// The same two on another context of the pool's device (its stream and
+// buffers); the pool's sets in range must be complete and must not move
+// while they run.
+im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, uint32_t k,
+                          uint32_t *seeds_host, uint64_t *cov);
+im_status coverage_range_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host,
+                            uint32_t k, uint64_t *cov);
 // Build ctx->seedbits from host seeds.
 im_status set_seed_bits(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k);
 // First index in zflags[0..count) where the running hit count reaches

@@ -137,3 +137,32 @@ def test_wg_candidate_rounds_runs_match_oracle(im, ctx, oracle_lib, algo, name, 
             _compare(st, ost, algo)
     finally:
         ctx.set_param("greedy_wg_cand_max_entries", old)
+
+
+@pytest.mark.parametrize("name,model,k", [("rmat16", 1, 40), ("cl_small", 1, 5), ("nethept", 0, 50),
+                                          ("rmat20", 1, 100)])
+@pytest.mark.parametrize("ahead", [0, 1, 2])
+def test_dssa_greedy_ahead_matches_oracle(im, ctx, oracle_lib, name, model, k, ahead):
+    """D-SSA covering later iterations on helper contexts while the current
+    one is covered gives the oracle's run, with and without drawing ahead and
+    speculation (the helpers' results are used or dropped, never changed)."""
+    g = synth.make(name)
+    w = g.w_ic if model == 0 else g.w_lt
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
+    og = oracle_lib.Graph(model, g.n, g.src, g.dst, w)
+    note(f"dssa greedy ahead {ahead} {name} k={k}")
+    names = ("dssa_greedy_ahead", "dssa_draw_ahead", "dssa_speculate")
+    old = [ctx.get_param(x) for x in names]
+    try:
+        ctx.set_param("dssa_greedy_ahead", ahead)
+        for draw, spec in ((4, 1), (1, 0), (64, 1)):
+            ctx.set_param("dssa_draw_ahead", draw)
+            ctx.set_param("dssa_speculate", spec)
+            for key in (0, 3):
+                seeds, st = dg.dssa(model, k, 0.1, 1.0 / g.n, key)
+                oseeds, ost = og.dssa(k, 0.1, 1.0 / g.n, key)
+                assert seeds.tolist() == oseeds.tolist(), (draw, spec, key)
+                _compare(st, ost, "dssa")
+    finally:
+        for x, v in zip(names, old):
+            ctx.set_param(x, v)
