@@ -315,7 +315,9 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       the RR sets of iteration t, it draws up to this many times 2 N_t
  *       sets in the same launches (the sets of later iterations are
  *       identical whenever they are drawn; a launch lasts about as long as
- *       its longest walk), 1..64 (default 4; IC draws are not affected);
+ *       its longest walk), 1..64 (default 8; IC draws are not affected).
+ *       While it is above 1, LT runs do not draw the next iteration's sets
+ *       on the side (IM_PARAM_DSSA_SPECULATE applies to IC runs);
  *   IM_PARAM_GREEDY_GRAPH           1: the k rounds of a grid-wide
  *       Max-Coverage of one range (two launches per round) are replayed
  *       from a HIP graph built the second time the same round count and

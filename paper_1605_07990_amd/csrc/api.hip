@@ -1017,9 +1017,13 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         // covered (they are dropped if this iteration stops), when the cover
         // step is expected to take at least half as long as that draw: the
         // last iteration's cover time, or about 15 us per greedy round
+        // (not for LT drawing ahead: its next draw takes several iterations'
+        // sets at once, and a draw the run turns out not to need would still
+        // be waited for at the end)
         if (ms_fresh > 0) ms_draw = ms_fresh;
         const double est_cover = std::max(ms_cover_last, 0.015 * k);
-        if (aux && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw &&
+        const bool ahead_lt = model == IM_LT && ctx->dssa_draw_ahead > 1;
+        if (aux && !ahead_lt && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw &&
             pool->count < 4 * nt)
             spec.start(aux, pool, pool->count, 4 * nt - pool->count);
         // the next iterations whose sets are all drawn are covered on the
