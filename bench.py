@@ -68,7 +68,8 @@ def percentile(xs, q):
 def measured_traffic(kernel: str):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known size), or
-    None when the kernel's sources changed since the counters were taken."""
+    None when the kernel's sources, or the query loop that sizes its
+    launches, changed since the counters were taken."""
     import hashlib
 
     path = ROOT / "profiles" / "traffic.json"
