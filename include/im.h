@@ -340,7 +340,15 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       stream and thread, once the pool holds their sets: iteration t's
  *       Max-Coverage reads only R_t, so the result is the one the iteration
  *       would compute, and it is dropped if the run stops first. The pool
- *       never grows while a helper runs (default 2).
+ *       never grows while a helper runs (default 2);
+ *   IM_PARAM_GREEDY_WG_CAND_BATCH  the engine's batched Max-Coverage runs
+ *       IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS grid-wide rounds and then
+ *       one-workgroup rounds over candidate nodes, a workgroup per query,
+ *       when no range has more (set, node) entries than this (nor than
+ *       IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES) and the graph has no more
+ *       nodes than this (a re-selection passes over every node once per
+ *       query); other batches use the batched schedules above (default
+ *       2^21; 0: never).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -356,7 +364,8 @@ typedef enum {
     IM_PARAM_GREEDY_GRAPH = 9,
     IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES = 10,
     IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 11,
-    IM_PARAM_DSSA_GREEDY_AHEAD = 12
+    IM_PARAM_DSSA_GREEDY_AHEAD = 12,
+    IM_PARAM_GREEDY_WG_CAND_BATCH = 13
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -29,6 +29,7 @@ CANDIDATES = {
     "greedy_wg_cand_max_entries": [0, 1 << 20, 1 << 22, 1 << 24, 1 << 62],
     "greedy_wg_cand_grid_rounds": [0, 4, 8, 16, 32],
     "dssa_greedy_ahead": [0, 1, 2],
+    "greedy_wg_cand_batch": [0, 1 << 20, 1 << 21, 1 << 23, 1 << 62],
 }
 
 

@@ -199,6 +199,7 @@ static void copy_greedy_params(const im_ctx *from, im_ctx *to) {
     to->greedy_graph = from->greedy_graph;
     to->greedy_wg_cand_max_entries = from->greedy_wg_cand_max_entries;
     to->greedy_wg_cand_grid_rounds = from->greedy_wg_cand_grid_rounds;
+    to->greedy_wg_cand_batch = from->greedy_wg_cand_batch;
 }
 
 // Helper context i (0 or 1) of ctx for later iterations' Max-Coverage.
@@ -388,6 +389,9 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 2) break;
         c->dssa_greedy_ahead = static_cast<uint32_t>(value);
         return IM_OK;
+    case IM_PARAM_GREEDY_WG_CAND_BATCH:
+        c->greedy_wg_cand_batch = value;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -435,6 +439,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_DSSA_GREEDY_AHEAD:
         *value = c->dssa_greedy_ahead;
+        return IM_OK;
+    case IM_PARAM_GREEDY_WG_CAND_BATCH:
+        *value = c->greedy_wg_cand_batch;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));

@@ -1501,8 +1501,10 @@ __global__ __launch_bounds__(kThreads) void batch_histogram_kernel(const JobTabl
 
 // 16 lanes per set; isets positions come from the global prefix over all
 // jobs' counts (job j's counts occupy [j*n, j*n+n)).
+template <bool kExt>
 __global__ __launch_bounds__(kThreads) void batch_scatter_kernel(const JobTable *jt, uint32_t nj, uint64_t total_sets,
-                                                                 const uint64_t *prefix, uint32_t n, uint32_t *isets) {
+                                                                 const uint64_t *prefix, uint32_t n, uint32_t *isets,
+                                                                 uint4 *iext) {
     const uint32_t sub = threadIdx.x & 15u;
     const uint64_t grp = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
     const uint64_t ngrp = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
@@ -1514,7 +1516,12 @@ __global__ __launch_bounds__(kThreads) void batch_scatter_kernel(const JobTable 
         for (uint64_t q = a + sub; q < b; q += 16) {
             const uint32_t v = j.pnodes[q];
             const uint32_t pos = atomicAdd(&j.fill[v], 1u);
-            isets[prefix[uint64_t(ji) * n + v] + pos] = static_cast<uint32_t>(js);
+            if constexpr (kExt)
+                iext[prefix[uint64_t(ji) * n + v] + pos] = make_uint4(
+                    static_cast<uint32_t>(js), static_cast<uint32_t>(b - a), static_cast<uint32_t>(a),
+                    static_cast<uint32_t>(a >> 32));
+            else
+                isets[prefix[uint64_t(ji) * n + v] + pos] = static_cast<uint32_t>(js);
         }
     }
 }
@@ -1710,13 +1717,13 @@ __global__ void wg_start_kernel(const GreedyState *jobs, uint32_t nj, uint32_t r
 // hdrs[j]), whose gains are exact. The first hist, collect and rounds run
 // at once; then cycles (clear, recount, hist, collect, rounds) are
 // queued at the context's running re-selection rate and the headers read
-// back once per batch of cycles, until every job has its k seeds or (one
-// job only) the cut asks for grid-wide rounds: then *grid_from is the first
-// round left to them, with every gain exact.
+// back once per batch of cycles, until every job has its k seeds or its cut
+// asked for grid-wide rounds: then grid_from[j] is job j's first round left
+// to them, with every gain exact (else k).
 static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *const *hdrs, const uint32_t *ks,
                                uint32_t nj, uint32_t n, uint64_t max_sets, uint32_t r0, uint32_t *grid_from) {
     hipStream_t st = ctx->stream;
-    *grid_from = ks[0];
+    for (uint32_t j = 0; j < nj; ++j) grid_from[j] = ks[j];
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
     // the collect blocks each derive the cut from the whole histogram, so a few
     const dim3 gn(grid_of(n, kThreads, cu * 8), nj), gh(grid_of(n, kThreads * 8, cu * 2), nj),
@@ -1760,14 +1767,16 @@ static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *con
                 ctx->greedy_wg_resel_rate = 0.5 * ctx->greedy_wg_resel_rate + 0.5 * double(stalls) / double(rounds);
             return IM_OK;
         }
-        bool grid = false;
-        for (uint32_t j = 0; j < nj; ++j) grid = grid || hh[j].phase == kStepGrid;
-        if (grid) {
-            if (nj != 1) {
-                set_error("max coverage: grid-wide fallback of batched one-workgroup rounds");
-                return IM_E_DEVICE;
-            }
-            *grid_from = hh[0].r;
+        remaining = 0;
+        for (uint32_t j = 0; j < nj; ++j)
+            if (hh[j].phase != kStepDone && hh[j].phase != kStepGrid)
+                remaining = std::max<uint32_t>(remaining, ks[j] - std::min(ks[j], hh[j].r));
+        // jobs the cut handed to the grid-wide rounds are finished by the caller
+        bool left = false;
+        for (uint32_t j = 0; j < nj; ++j) left = left || (hh[j].phase != kStepDone && hh[j].phase != kStepGrid);
+        if (!left) {
+            for (uint32_t j = 0; j < nj; ++j)
+                if (hh[j].phase == kStepGrid) grid_from[j] = hh[j].r;
             return IM_OK;
         }
         // every cycle chooses at least one seed: the cut keeps only keys above its bound
@@ -2126,6 +2135,18 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         tot_seeds += cj.k;
         tot_cov += (cj.end - cj.begin + 31) / 32 + 1;
     }
+    uint64_t max_entries = 0, max_sets = 0;
+    uint32_t max_k = 0;
+    for (uint32_t j = 0; j < nj; ++j) {
+        max_entries = std::max<uint64_t>(max_entries, he[4 * j + 1] - he[4 * j]);
+        max_sets = std::max<uint64_t>(max_sets, jobs[j].end - jobs[j].begin);
+        max_k = std::max(max_k, jobs[j].k);
+    }
+    // one-workgroup rounds over candidate nodes, a workgroup per job (each
+    // re-selection passes over every node once per job, so the node count
+    // is held to the same limit as the ranges)
+    const bool wgc = max_k && max_entries <= ctx->greedy_wg_cand_batch && uint64_t(n) <= ctx->greedy_wg_cand_batch &&
+                     max_entries <= ctx->greedy_wg_cand_max_entries;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -2135,13 +2156,15 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
     const uint64_t cells = uint64_t(nj) * n;
     const uint64_t tiles = (cells + kTile - 1) / kTile;
     const size_t o_gain = take(4 * cells), o_fill = take(4 * cells), o_prefix = take(8 * (cells + 1)),
-                 o_tsum = take(8 * (tiles + 1)), o_isets = take(4 * (tot_entries + 1)), o_covbits = take(4 * tot_cov),
+                 o_tsum = take(8 * (tiles + 1)), o_isets = take((wgc ? 16 : 4) * (tot_entries + 1)),
+                 o_covbits = take(4 * tot_cov),
                  o_m1 = take(8ull * nj * n1), o_m2 = take(8ull * nj * n2), o_seeds = take(4 * (tot_seeds + 1)),
                  o_cov = take(8ull * nj), o_covc = take(8ull * nj), o_bits = take(4 * words * nj),
                  o_jt = take(sizeof(JobTable) * nj), o_gs = take(sizeof(GreedyState) * nj),
                  o_dirty = take(4ull * nj * ((n1 + 31) / 32)),
                  o_bmax = take(8ull * nj * 1024), o_hdr = take(2 * sizeof(StepHdr) * nj),
-                 o_cnode = take(4ull * kCandNodes * nj), o_cbase = take(8ull * kCandNodes * nj), o_cdec = take(12ull * kCandNodes * nj);
+                 o_cnode = take(4ull * kCandNodes * nj), o_cbase = take(8ull * kCandNodes * nj), o_cdec = take(12ull * kCandNodes * nj),
+                 o_hist = take(8ull * kSelBins * nj), o_ccount = take(4ull * nj);
     IM_TRY(dev_reserve(ctx, ctx->cover, off));
     char *base = static_cast<char *>(ctx->cover.ptr);
     auto *gains = reinterpret_cast<uint32_t *>(base + o_gain);
@@ -2191,6 +2214,11 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
         g.cbase = reinterpret_cast<uint32_t *>(base + o_cbase) + 2ull * kCandNodes * j;
         g.cdec = reinterpret_cast<uint32_t *>(base + o_cdec) + 3ull * kCandNodes * j;
         g.want = std::min<uint32_t>(ctx->greedy_candidates_batch, kCandMax);
+        if (wgc) {
+            g.iext = reinterpret_cast<const uint4 *>(isets);
+            g.hist = reinterpret_cast<uint32_t *>(base + o_hist) + 2ull * kSelBins * j;
+            g.ccount = reinterpret_cast<uint32_t *>(base + o_ccount) + j;
+        }
     }
     IM_HIP(hipMemcpyAsync(djt, jt.data(), sizeof(JobTable) * nj, hipMemcpyHostToDevice, st));
     IM_HIP(hipMemcpyAsync(dgs, gs.data(), sizeof(GreedyState) * nj, hipMemcpyHostToDevice, st));
@@ -2207,20 +2235,53 @@ im_status max_coverage_batch(im_ctx *ctx, const im_graph *gr, CoverJob *jobs, ui
     tile_sums_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gains, cells, tsum);
     tile_scan_kernel<<<1, 1024, 0, st>>>(tsum, tiles);
     tile_apply_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(gains, cells, tsum, prefix);
-    if (tot_sets)
-        batch_scatter_kernel<<<grid_of(tot_sets * 16, kThreads, cu * 16), kThreads, 0, st>>>(djt, nj, tot_sets, prefix, n,
-                                                                                             isets);
+    if (tot_sets && wgc)
+        batch_scatter_kernel<true><<<grid_of(tot_sets * 16, kThreads, cu * 16), kThreads, 0, st>>>(
+            djt, nj, tot_sets, prefix, n, nullptr, reinterpret_cast<uint4 *>(isets));
+    else if (tot_sets)
+        batch_scatter_kernel<false><<<grid_of(tot_sets * 16, kThreads, cu * 16), kThreads, 0, st>>>(
+            djt, nj, tot_sets, prefix, n, isets, nullptr);
     batch_init_m1_kernel<<<grid_of(uint64_t(nj) * n1, kThreads, cu * 8), kThreads, 0, st>>>(dgs, nj, n1);
     batch_init_m2_kernel<<<grid_of(uint64_t(nj) * n2, kThreads, cu * 8), kThreads, 0, st>>>(dgs, nj, n2);
     // ranges up to the one-workgroup limit all run their rounds in one
     // launch; beyond it every round is two grid launches shared by all jobs
-    uint64_t max_entries = 0;
-    uint32_t max_k = 0;
-    for (uint32_t j = 0; j < nj; ++j) {
-        max_entries = std::max<uint64_t>(max_entries, he[4 * j + 1] - he[4 * j]);
-        max_k = std::max(max_k, jobs[j].k);
-    }
-    if (max_entries <= ctx->greedy_wg_max_entries) {
+    if (wgc) {
+        // the first rounds grid-wide (two launches each, shared by all jobs),
+        // then a workgroup per job over candidate nodes; a job whose cut
+        // keeps too few candidates finishes with grid-wide rounds of its own
+        const uint32_t per = batch_blocks_per_job(cu, nj);
+        const uint32_t rx = batch_refresh_blocks(cu, nj, n1);
+        const uint32_t cx = std::min<uint32_t>(per, std::max<uint32_t>(1, grid_of(max_entries * 16, kThreads, cu * 4)));
+        const uint32_t lead = std::min<uint32_t>(max_k, ctx->greedy_wg_cand_grid_rounds);
+        for (uint32_t r = 0; r < lead; ++r) {
+            batch_refresh_kernel<<<dim3(rx, nj), kThreads, 0, st>>>(dgs, r);
+            batch_cover_kernel<<<dim3(cx, nj), kThreads, 0, st>>>(dgs, r);
+        }
+        fill_u32_kernel<<<grid_of(2ull * kSelBins * nj, kThreads, cu), kThreads, 0, st>>>(
+            reinterpret_cast<uint32_t *>(base + o_hist), 2ull * kSelBins * nj, 0u);
+        std::vector<StepHdr *> hdrs(nj);
+        std::vector<uint32_t> ks(nj), from(nj);
+        for (uint32_t j = 0; j < nj; ++j) {
+            hdrs[j] = gs[j].hdr;
+            ks[j] = jobs[j].k;
+        }
+        IM_TRY(run_wg_cycles(ctx, dgs, hdrs.data(), ks.data(), nj, n, max_sets, lead, from.data()));
+        for (uint32_t j = 0; j < nj; ++j) {
+            if (from[j] >= ks[j]) continue;
+            GreedyState g = gs[j];
+            const uint32_t rg = grid_of(uint64_t(n1), kThreads, cu * 4);  // at most 1024: bmax holds 1024 per job
+            const uint32_t cg = std::max<uint32_t>(1, std::min<uint32_t>(cu * 4, grid_of(g.nsets * 16, kThreads, cu * 4)));
+            g.nbmax = rg;
+            init_m1_kernel<<<grid_of(n1, kThreads, cu * 8), kThreads, 0, st>>>(g);
+            if (g.mark)
+                fill_u32_kernel<<<grid_of((n1 + 31) / 32, kThreads, cu), kThreads, 0, st>>>(g.dirty, (n1 + 31) / 32,
+                                                                                           0u);
+            for (uint32_t r = from[j]; r < ks[j]; ++r) {
+                refresh_kernel<<<rg, kThreads, 0, st>>>(g, r);
+                cover_kernel<<<cg, kThreads, 0, st>>>(g, r);
+            }
+        }
+    } else if (max_entries <= ctx->greedy_wg_max_entries) {
         persist_kernel<<<nj, kPersistThreads, 0, st>>>(dgs, 0);
     } else {
         const uint32_t per = batch_blocks_per_job(cu, nj);

@@ -82,6 +82,7 @@ struct im_ctx {
     uint64_t greedy_wg_cand_max_entries = ~0ull;  // ranges up to this many entries: one-workgroup candidate rounds
     double greedy_wg_resel_rate = 0.02;           // running re-selections per round of those rounds
     uint32_t greedy_wg_cand_grid_rounds = 16;     // of which the first this many run on the grid
+    uint64_t greedy_wg_cand_batch = 1ull << 21;    // batched Max-Coverage with every range up to this: a workgroup per job
     struct RoundGraphCache *round_graphs = nullptr;
 
     // optional event timing of the main sampler launches

@@ -93,15 +93,19 @@ def _engine(im, ctx, graphs, cases, budget=16 << 30, max_active=64):
 @pytest.mark.parametrize("limit,mark,cand", [(None, None, None), (0, None, None), (0, 0, None),
                                              (1 << 62, None, None), (0, None, 0), (0, 0, 1), (0, 1 << 62, 64)])
 def test_engine_mix_matches_single(im, ctx, graphs, limit, mark, cand):
-    """limit: the one-workgroup greedy threshold (None = default; 0 forces
-    the batched grid-wide rounds, 2^62 one workgroup per job); mark: the
+    """limit: the one-workgroup greedy threshold (None = default, which
+    runs one-workgroup rounds over candidate nodes; 0 forces the batched
+    grid-wide rounds, 2^62 all rounds in one workgroup per job); mark: the
     chunk count above which the cover step marks touched chunks (0: always);
     cand: candidate chunks of the grid-wide rounds (0: two launches per
     round). The single-query runs use the defaults."""
     note(f"engine mix of {len(MIX)} queries vs single-query runs, greedy limit {limit} mark {mark} cand {cand}")
-    names = ("greedy_wg_max_entries", "greedy_mark_min_chunks", "greedy_candidates_batch")
+    names = ("greedy_wg_max_entries", "greedy_mark_min_chunks", "greedy_candidates_batch", "greedy_wg_cand_batch")
     old = [ctx.get_param(x) for x in names]
-    for x, v in zip(names, (limit, mark, cand)):
+    # any schedule asked for is the batched one it names, not the
+    # one-workgroup candidate rounds (which the default case runs)
+    pinned = (limit, mark, cand) != (None, None, None)
+    for x, v in zip(names, (limit, mark, cand, 0 if pinned else None)):
         if v is not None:
             ctx.set_param(x, v)
     try:
@@ -112,6 +116,51 @@ def test_engine_mix_matches_single(im, ctx, graphs, limit, mark, cand):
     for case, r in zip(MIX, res):
         note(f"compare {case}")
         _same(r, _single(graphs, case))
+
+
+@pytest.mark.parametrize("lead", [16, 0, 3])
+def test_engine_wg_candidate_batch_matches_single(im, ctx, graphs, lead):
+    """The engine's batched Max-Coverage as one-workgroup rounds over
+    candidate nodes, a workgroup per query, after `lead` grid-wide rounds
+    shared by all queries, gives every query its single-query result."""
+    note(f"engine mix with one-workgroup batched rounds, lead {lead}")
+    names = ("greedy_wg_cand_batch", "greedy_wg_cand_grid_rounds")
+    old = [ctx.get_param(x) for x in names]
+    ctx.set_param("greedy_wg_cand_batch", 1 << 62)
+    ctx.set_param("greedy_wg_cand_grid_rounds", lead)
+    try:
+        res, _ = _engine(im, ctx, graphs, MIX)
+        single = [_single(graphs, case) for case in MIX]
+    finally:
+        for x, v in zip(names, old):
+            ctx.set_param(x, v)
+    for case, r, sr in zip(MIX, res, single):
+        note(f"compare {case}")
+        _same(r, sr)
+
+
+def test_engine_wg_candidate_batch_flat_gains(im, ctx):
+    """Flat gains (every RR set one node of an edgeless graph): some
+    queries' cuts keep too few candidates and finish with grid-wide rounds
+    of their own while the others go on in their workgroups."""
+    note("engine one-workgroup batched rounds, flat gains")
+    n = 200_000
+    e = np.array([], np.uint32)
+    dg = im.Graph(ctx, n, e, e, w_ic=np.array([], np.float32))
+    cases = [(0, "dssa", 300, 0.2, 1), (0, "dssa", 40, 0.2, 2), (0, "ssa", 1200, 0.3, 3)]
+    old = ctx.get_param("greedy_wg_cand_batch")
+    ctx.set_param("greedy_wg_cand_batch", 1 << 62)
+    try:
+        eng = im.Engine(ctx, pool_budget_bytes=16 << 30, max_active=64)
+        tickets = [eng.submit(dg, m, a, k, eps, 1.0 / n, key) for m, a, k, eps, key in cases]
+        eng.run()
+        res = [eng.result(t) for t in tickets]
+        eng.close()
+        single = [getattr(dg, a)(m, k, eps, 1.0 / n, key) for m, a, k, eps, key in cases]
+    finally:
+        ctx.set_param("greedy_wg_cand_batch", old)
+    for r, sr in zip(res, single):
+        _same(r, sr)
 
 
 def test_engine_matches_oracle(im, ctx, graphs, oracle_lib):
