@@ -1232,7 +1232,15 @@ __global__ __launch_bounds__(kWgThreads) void wg_round_kernel(const GreedyState 
 __global__ __launch_bounds__(kThreads) void wg_clear_kernel(const GreedyState *jobs) {
     const GreedyState &g = jobs[blockIdx.y];
     if (g.hdr[0].phase != kStepRefresh) return;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x)
+    // four gains per 16-byte access where the job's gain array allows it
+    const bool vec = (reinterpret_cast<uintptr_t>(g.gain) & 15u) == 0;
+    const uint32_t n4 = vec ? g.n / 4u : 0u;
+    uint4 *g4 = reinterpret_cast<uint4 *>(g.gain);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
+        const uint4 q = g4[i];
+        g4[i] = make_uint4(q.x & kChosen, q.y & kChosen, q.z & kChosen, q.w & kChosen);
+    }
+    for (uint32_t v = 4u * n4 + blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x)
         g.gain[v] &= kChosen;
 }
 
@@ -1261,7 +1269,17 @@ __global__ __launch_bounds__(kThreads) void wg_hist_kernel(const GreedyState *jo
     uint32_t *hist = g.hist + (h.stalls & 1u) * kSelBins;
     for (uint32_t i = threadIdx.x; i < kSelBins; i += blockDim.x) hl[i] = 0u;
     __syncthreads();
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+    const bool vec = (reinterpret_cast<uintptr_t>(g.gain) & 15u) == 0;
+    const uint32_t n4 = vec ? g.n / 4u : 0u;
+    const uint4 *g4 = reinterpret_cast<const uint4 *>(g.gain);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
+        const uint4 q = g4[i];
+        const uint32_t xs[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t)
+            if (xs[t] && !(xs[t] & kChosen)) atomicAdd(&hl[sel_bin(xs[t])], 1u);
+    }
+    for (uint32_t v = 4u * n4 + blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
         const uint32_t x = g.gain[v];
         if (x && !(x & kChosen)) atomicAdd(&hl[sel_bin(x)], 1u);
     }
@@ -1335,9 +1353,8 @@ __global__ __launch_bounds__(kThreads) void wg_collect_kernel(const GreedyState 
         }
     }
     if (phase != kStepCollect) return;
-    for (uint32_t v = blockIdx.x * blockDim.x + tid; v < g.n; v += gridDim.x * blockDim.x) {
-        const uint32_t x = g.gain[v];
-        if (x & kChosen) continue;
+    auto take = [&](uint32_t v, uint32_t x) {
+        if (x & kChosen) return;
         const unsigned long long key = (static_cast<unsigned long long>(x) << 32) | static_cast<unsigned long long>(~v);
         if (key > thresh) {
             const uint32_t slot = atomicAdd(g.ccount, 1u);
@@ -1346,7 +1363,19 @@ __global__ __launch_bounds__(kThreads) void wg_collect_kernel(const GreedyState 
                 g.cbase[slot] = x;
             }
         }
+    };
+    // four gains per 16-byte load where the job's gain array allows it
+    const bool vec = (reinterpret_cast<uintptr_t>(g.gain) & 15u) == 0;
+    const uint32_t n4 = vec ? g.n / 4u : 0u;
+    const uint4 *g4 = reinterpret_cast<const uint4 *>(g.gain);
+    for (uint32_t i = blockIdx.x * blockDim.x + tid; i < n4; i += gridDim.x * blockDim.x) {
+        const uint4 q = g4[i];
+        take(4u * i, q.x);
+        take(4u * i + 1u, q.y);
+        take(4u * i + 2u, q.z);
+        take(4u * i + 3u, q.w);
     }
+    for (uint32_t v = 4u * n4 + blockIdx.x * blockDim.x + tid; v < g.n; v += gridDim.x * blockDim.x) take(v, g.gain[v]);
 }
 
 // Sets in [begin, end) that contain a node of the seed bitmap.
@@ -1725,9 +1754,10 @@ static im_status run_wg_cycles(im_ctx *ctx, const GreedyState *dgs, StepHdr *con
     hipStream_t st = ctx->stream;
     for (uint32_t j = 0; j < nj; ++j) grid_from[j] = ks[j];
     const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
-    // the collect blocks each derive the cut from the whole histogram, so a few
-    const dim3 gn(grid_of(n, kThreads, cu * 8), nj), gh(grid_of(n, kThreads * 8, cu * 2), nj),
-        gs(grid_of(max_sets * 16, kThreads, cu * 16), nj), gc(grid_of(n, kThreads * 16, cu), nj);
+    // node passes: the collect blocks each derive the cut from the whole
+    // histogram, so they take more nodes per thread than the other passes
+    const dim3 gn(grid_of(n, kThreads * 4, cu * 8), nj), gh(grid_of(n, kThreads * 8, cu * 4), nj),
+        gs(grid_of(max_sets * 16, kThreads, cu * 16), nj), gc(grid_of(n, kThreads * 16, cu * 4), nj);
     wg_start_kernel<<<(nj + 255) / 256, 256, 0, st>>>(dgs, nj, r0);
     wg_hist_kernel<<<gh, kThreads, 0, st>>>(dgs);
     wg_collect_kernel<<<gc, kThreads, 0, st>>>(dgs);
