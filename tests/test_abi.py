@@ -79,3 +79,18 @@ def test_eps_presets_and_theta_host_only():
         im.ssa_eps_preset("moderate", 0.7)
     for args in ((15233, 50, 0.1, 1 / 15233), (1 << 20, 100, 0.1, 2 ** -20), (50, 50, 0.2, 0.1)):
         assert im.ris_theta(*args) == pytest.approx(oracle.ris_theta(*args), rel=1e-12)
+
+
+def test_binding_parameter_ids_match_header():
+    """Every launch parameter the header's im_param enum declares is in the
+    binding's name table under the same value, and every autotuner knob is a
+    declared parameter (host only)."""
+    text = (ROOT / "include" / "im.h").read_text()
+    body = re.search(r"typedef enum \{(.*?)\} im_param;", text, flags=re.S).group(1)
+    declared = {name: int(val) for name, val in re.findall(r"(IM_PARAM_[A-Z0-9_]+)\s*=\s*(\d+)", body)}
+    from paper_1605_07990_amd import autotune, binding
+    values = {getattr(binding, name) for name in declared}
+    assert {name: getattr(binding, name) for name in declared} == declared
+    assert sorted(binding.PARAMS.values()) == sorted(values)
+    assert len(set(declared.values())) == len(declared)
+    assert set(autotune.CANDIDATES) <= set(binding.PARAMS)
