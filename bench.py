@@ -523,14 +523,18 @@ def main() -> int:
     if os.environ.get("IM_NO_TORCH", "") != "1":
         import torch
 
-    def sync():
-        if torch is not None:
-            torch.cuda.synchronize()
-
     if not args.no_gather_probe:
         GATHER.update(gather_bandwidth())
         GATHER_MALL.update(gather_bandwidth(segs=(64, 128, 256), buffer_bytes=128 << 20))
     ctx = im.Context(0)
+
+    def sync():
+        # the context's own streams and any dropped D-SSA covers still running
+        # count in the timed region; then the device as torch sees it
+        ctx.sync()
+        if torch is not None:
+            torch.cuda.synchronize()
+
     if args.greedy_wg_max_entries is not None:
         ctx.set_param("greedy_wg_max_entries", args.greedy_wg_max_entries)
     if args.no_speculate:

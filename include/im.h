@@ -61,6 +61,13 @@ im_status im_ctx_create(int device, void *stream, im_alloc_fn alloc, im_free_fn 
 /* Free the context's own buffers. Every engine, pool and graph made on it
  * must be freed before (they use its allocator and stream). */
 void im_ctx_free(im_ctx *ctx);
+/* Wait until no work of the context is in flight: its stream, its
+ * side-sampling stream, and the covers of later D-SSA iterations that a run
+ * dropped when it stopped before them (im_dssa returns without waiting for
+ * those; their pools are freed here, or when their helper is next needed,
+ * their graph is freed, or the context is freed). Errors: IM_E_ARG,
+ * IM_E_DEVICE. */
+im_status im_ctx_sync(im_ctx *ctx);
 
 /*
  * Load G = (V, E, w) (Section 2) into device memory as a reverse adjacency.
@@ -339,8 +346,9 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       iterations (0..2) at once, each on a helper context with its own
  *       stream and thread, once the pool holds their sets: iteration t's
  *       Max-Coverage reads only R_t, so the result is the one the iteration
- *       would compute, and it is dropped if the run stops first. The pool
- *       never grows while a helper runs (default 2);
+ *       would compute; if the run stops first it is dropped and im_dssa
+ *       returns without waiting for it (see im_ctx_sync). The pool never
+ *       grows while a helper runs (default 2);
  *   IM_PARAM_GREEDY_WG_CAND_BATCH  the engine's batched Max-Coverage runs
  *       IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS grid-wide rounds and then
  *       one-workgroup rounds over candidate nodes, a workgroup per query,

@@ -31,7 +31,7 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing",
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
            "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param", "im_ssa_eps",
-           "im_ssa_eps_preset", "im_ris_theta", "im_ris", "im_engine_submit_estimate"]
+           "im_ssa_eps_preset", "im_ris_theta", "im_ris", "im_engine_submit_estimate", "im_ctx_sync"]
 
 IM_NET_SMALL, IM_NET_MODERATE, IM_NET_LARGE = 0, 1, 2
 REGIMES = {"small": IM_NET_SMALL, "moderate": IM_NET_MODERATE, "large": IM_NET_LARGE}
@@ -137,6 +137,7 @@ def load_library(path: Path | str | None = None):
     sig = {
         "im_ctx_create": (st, [ctypes.c_int, vp, ALLOC_FN, FREE_FN, vp, ctypes.POINTER(vp)]),
         "im_ctx_free": (None, [vp]),
+        "im_ctx_sync": (st, [vp]),
         "im_graph_load": (st, [vp, ctypes.c_uint32, ctypes.c_uint64, u32p, u32p, f32p, f32p, ctypes.POINTER(vp)]),
         "im_graph_set_source_weights": (st, [vp, u32p]),
         "im_graph_free": (None, [vp]),
@@ -255,6 +256,11 @@ class Context:
         fn = self._live.pop(h.value, None)
         if fn is not None and self.h is not None:
             getattr(load_library(), fn)(h)
+
+    def sync(self):
+        """Wait for all of the context's work in flight, including covers of
+        D-SSA iterations that runs dropped without waiting (im_ctx_sync)."""
+        _check(load_library().im_ctx_sync(self.h))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().im_ctx_set_timing(self.h, 1 if enable else 0))

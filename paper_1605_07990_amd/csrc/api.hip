@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -160,6 +161,80 @@ im_status check_query(const im_graph *g, im_model model, uint32_t k, double eps,
 
 // Largest batch drawn at once: LT reserves a staging region per sample.
 uint64_t max_batch(im_model model) { return model == IM_LT ? (1ull << 20) : (1ull << 24); }
+
+// Max-Coverage of a later D-SSA iteration's R_t = [0, N_t) and its stare
+// count over [N_t, 2 N_t), on a helper context in a thread of its own. The
+// result depends only on those sets, so it is the iteration's own whenever
+// the run gets there. If the run stops first, the cover is dropped but not
+// waited for: the slot keeps the run's pool (`orphan`) until the thread has
+// returned, and the pool is freed when the slot is next reaped.
+struct AheadCover {
+    std::thread th;
+    bool running = false;            // started and not joined
+    std::atomic<bool> done{false};   // the thread has returned
+    const im_pool *pool = nullptr;   // the pool it reads
+    im_pool *orphan = nullptr;       // owned: the run that started it has returned
+    im_status rc = IM_OK;
+    std::string err;
+    uint64_t nt = 0, cov = 0, cov_c = 0;
+    std::vector<uint32_t> seeds;
+
+    void start(im_ctx *h, const im_pool *p, uint64_t n_t, uint32_t k) {
+        nt = n_t;
+        pool = p;
+        seeds.assign(k, 0u);
+        rc = IM_OK;
+        done = false;
+        running = true;
+        th = std::thread([this, h, p, k] {
+            if (hipSetDevice(h->device) != hipSuccess) {
+                rc = IM_E_DEVICE;
+                err = "hipSetDevice failed in the cover thread";
+            } else {
+                rc = max_coverage_on(h, p, 0, nt, k, seeds.data(), &cov);
+                if (rc == IM_OK) rc = coverage_range_on(h, p, nt, 2 * nt, seeds.data(), k, &cov_c);
+                if (rc == IM_OK) rc = hipStreamSynchronize(h->stream) == hipSuccess ? IM_OK : IM_E_DEVICE;
+                if (rc != IM_OK) err = im_last_error();
+            }
+            done = true;
+        });
+    }
+    bool busy() const { return running && !done; }
+};
+
+// Join slot i of the two. A dropped cover's pool may be shared by both slots
+// (the run left a cover in each): it is freed by the join that leaves no
+// slot holding it. Only the thread that runs the queries calls this.
+static im_status join_slot(AheadCover *a, int i) {
+    AheadCover &s = a[i];
+    if (!s.running) return IM_OK;
+    s.th.join();
+    s.running = false;
+    s.pool = nullptr;
+    if (s.orphan) {
+        im_pool *p = s.orphan;
+        s.orphan = nullptr;
+        const AheadCover &o = a[1 - i];
+        if (!(o.running && o.orphan == p)) im_pool_free(p);
+        return IM_OK;  // a dropped cover's outcome is not used
+    }
+    if (s.rc != IM_OK) set_error("%s", s.err.c_str());
+    return s.rc;
+}
+
+static AheadCover *ahead_slots(im_ctx *ctx) {
+    if (!ctx->ahead) ctx->ahead = new (std::nothrow) AheadCover[2];
+    return ctx->ahead;
+}
+
+void reap_ahead(im_ctx *ctx, const im_graph *g) {
+    if (!ctx->ahead) return;
+    for (int i = 0; i < 2; ++i) {
+        AheadCover &a = ctx->ahead[i];
+        if (a.running && (!g || !a.pool || a.pool->g == g)) (void)join_slot(ctx->ahead, i);
+    }
+    clear_error();
+}
 
 // A context on the same device and allocator with its own stream and work
 // buffers (its launch parameters are copied from ctx on each use).
@@ -471,8 +546,20 @@ extern "C" im_status im_ctx_read_timing(im_ctx *c, im_kernel_times *out, int res
     return IM_OK;
 }
 
+extern "C" im_status im_ctx_sync(im_ctx *c) {
+    clear_error();
+    if (!c) return IM_E_ARG;
+    reap_ahead(c, nullptr);
+    IM_HIP(hipStreamSynchronize(c->stream));
+    if (c->aux) IM_HIP(hipStreamSynchronize(c->aux->stream));
+    return IM_OK;
+}
+
 extern "C" void im_ctx_free(im_ctx *c) {
     if (!c) return;
+    reap_ahead(c, nullptr);
+    delete[] c->ahead;
+    c->ahead = nullptr;
     if (c->aux) im_ctx_free(c->aux);
     for (im_ctx *h : c->helpers)
         if (h) im_ctx_free(h);
@@ -520,6 +607,7 @@ extern "C" im_status im_graph_set_source_weights(im_graph *g, const uint32_t *no
 
 extern "C" void im_graph_free(im_graph *g) {
     if (!g) return;
+    reap_ahead(g->ctx, g);  // dropped covers of this graph's runs read g
     (void)hipStreamSynchronize(g->ctx->stream);
     dev_free(g->ctx, g->off);
     dev_free(g->ctx, g->edges_ic);
@@ -915,43 +1003,6 @@ struct Speculation {
     }
 };
 
-// Max-Coverage of a later D-SSA iteration's R_t = [0, N_t) and its stare
-// count over [N_t, 2 N_t), on a helper context in a thread of its own. The
-// result depends only on those sets, so it is the iteration's own whenever
-// the loop gets there; if the loop stops first it is dropped.
-struct AheadCover {
-    std::thread th;
-    bool running = false;
-    im_status rc = IM_OK;
-    std::string err;
-    uint64_t nt = 0, cov = 0, cov_c = 0;
-    std::vector<uint32_t> seeds;
-
-    void start(im_ctx *h, const im_pool *p, uint64_t n_t, uint32_t k) {
-        nt = n_t;
-        seeds.assign(k, 0u);
-        rc = IM_OK;
-        running = true;
-        th = std::thread([this, h, p, k] {
-            if (hipSetDevice(h->device) != hipSuccess) {
-                rc = IM_E_DEVICE;
-                err = "hipSetDevice failed in the cover thread";
-                return;
-            }
-            rc = max_coverage_on(h, p, 0, nt, k, seeds.data(), &cov);
-            if (rc == IM_OK) rc = coverage_range_on(h, p, nt, 2 * nt, seeds.data(), k, &cov_c);
-            if (rc != IM_OK) err = im_last_error();
-        });
-    }
-    im_status join() {
-        if (!running) return IM_OK;
-        th.join();
-        running = false;
-        if (rc != IM_OK) set_error("%s", err.c_str());
-        return rc;
-    }
-};
-
 }  // namespace
 
 extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, double eps, double delta, uint64_t key,
@@ -981,18 +1032,17 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     uint64_t most = 2 * n1;
     while (double(most / 2) < c.n_max && most < (1ull << 62)) most *= 2;
     im_status rc = IM_OK;
-    // later iterations' covers running on helper contexts (slot = helper)
-    AheadCover ahead[2];
-    const uint32_t n_ahead = ctx->dssa_greedy_ahead;
-    im_ctx *helpers[2] = {nullptr, nullptr};
-    for (uint32_t i = 0; i < n_ahead; ++i)
-        if (helper_ctx(ctx, int(i), &helpers[i]) != IM_OK) helpers[i] = nullptr;  // run without
-    clear_error();
-    // every helper is done before the pool's buffers may move
+    // later iterations' covers running on helper contexts (slot i = helper
+    // i); a slot still busy with a dropped cover of an earlier run is left
+    // alone until it is done
+    AheadCover *ahead = ctx->dssa_greedy_ahead ? ahead_slots(ctx) : nullptr;
+    const uint32_t n_ahead = ahead ? ctx->dssa_greedy_ahead : 0u;
+    // every cover of this run is done before the pool's buffers may move
     auto join_ahead = [&]() {
         im_status r = IM_OK;
-        for (AheadCover &a : ahead) {
-            const im_status x = a.join();
+        for (uint32_t i = 0; i < n_ahead; ++i) {
+            if (ahead[i].pool != pool) continue;
+            const im_status x = join_slot(ahead, int(i));
             if (r == IM_OK) r = x;
         }
         return r;
@@ -1040,10 +1090,17 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
             const uint64_t nj = nt << j;
             if (double(nj >> 1) >= c.n_max || 2 * nj > pool->count) break;
             bool have = false;
-            for (AheadCover &a : ahead) have = have || (a.running && a.nt == nj);
+            for (uint32_t i = 0; i < n_ahead; ++i) have = have || (ahead[i].pool == pool && ahead[i].nt == nj);
             if (have) continue;
             for (uint32_t i = 0; i < n_ahead; ++i) {
-                if (!helpers[i] || ahead[i].running) continue;
+                if (ahead[i].running && ahead[i].pool == pool) continue;  // this run's, not yet used
+                if (ahead[i].busy()) continue;                            // an earlier run's, still running
+                if (ahead[i].running) (void)join_slot(ahead, int(i));     // an earlier run's dropped cover, done
+                im_ctx *h = nullptr;
+                if (helper_ctx(ctx, int(i), &h) != IM_OK) {
+                    clear_error();
+                    continue;  // go on without this helper
+                }
                 if (!synced) {
                     // the pool's sets were written on this context's stream
                     if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -1052,23 +1109,24 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
                     }
                     synced = true;
                 }
-                if (rc == IM_OK) ahead[i].start(helpers[i], pool, nj, k);
+                if (rc == IM_OK) ahead[i].start(h, pool, nj, k);
                 break;
             }
             if (rc != IM_OK) break;
         }
         if (rc != IM_OK) break;
         uint64_t cov = 0, cov_c = 0;
-        AheadCover *mine = nullptr;
-        for (AheadCover &a : ahead)
-            if (a.running && a.nt == nt) mine = &a;
+        int mine = -1;
+        for (uint32_t i = 0; i < n_ahead; ++i)
+            if (ahead[i].running && ahead[i].pool == pool && ahead[i].nt == nt) mine = int(i);
         t0 = now_ms();
-        if (mine) {
+        if (mine >= 0) {
             // covered on a helper since an earlier iteration
-            if ((rc = mine->join())) break;
-            std::copy(mine->seeds.begin(), mine->seeds.end(), seeds.begin());
-            cov = mine->cov;
-            cov_c = mine->cov_c;
+            if ((rc = join_slot(ahead, mine))) break;
+            const AheadCover &m = ahead[mine];
+            std::copy(m.seeds.begin(), m.seeds.end(), seeds.begin());
+            cov = m.cov;
+            cov_c = m.cov_c;
             ms_cover_last = now_ms() - t0;
             st->ms_cover += ms_cover_last;
         } else {
@@ -1115,8 +1173,15 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     }
     const im_status rs = spec.join();  // a draw still running is waited for and dropped
     if (rc == IM_OK) rc = rs;
-    const im_status ra = join_ahead();  // so are covers of iterations not reached
-    if (rc == IM_OK) rc = ra;
+    // covers of iterations the run did not reach are dropped without waiting:
+    // their slots keep the pool until they are done
+    bool pool_kept = false;
+    for (uint32_t i = 0; i < n_ahead; ++i) {
+        if (ahead[i].running && ahead[i].pool == pool) {
+            ahead[i].orphan = pool;
+            pool_kept = true;
+        }
+    }
     if (rc == IM_OK) {
         st->edges = pool->edges;
         if (pool->count > st->n_sets) {
@@ -1126,7 +1191,7 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         }
         std::memcpy(seeds_out, seeds.data(), 4ull * k);
     }
-    im_pool_free(pool);
+    if (!pool_kept) im_pool_free(pool);
     st->ms_total = now_ms() - t_start;
     return rc;
 }

@@ -40,6 +40,10 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+namespace im {
+struct AheadCover;  // api.hip
+}  // namespace im
+
 struct im_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -97,6 +101,9 @@ struct im_ctx {
     // contexts on their own streams that run later D-SSA iterations'
     // Max-Coverage while the current one is covered; created on first use
     im_ctx *helpers[2] = {nullptr, nullptr};
+    // the work of each helper: a later iteration's cover, and, when the run
+    // stopped before it, the pool it reads (freed once the cover is done)
+    im::AheadCover *ahead = nullptr;
     uint32_t dssa_greedy_ahead = 2;  // later iterations covered at once (0..2)
     bool owns_stream = false;
     size_t slot_budget = 8ull << 30;  // long-path slot memory cap
@@ -209,6 +216,9 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
                           uint32_t *seeds_host, uint64_t *cov);
 im_status coverage_range_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host,
                             uint32_t k, uint64_t *cov);
+// Wait for the helpers' covers (all of them, or those of graph g's pools)
+// and free the pools of dropped ones.
+void reap_ahead(im_ctx *ctx, const im_graph *g);
 // Build ctx->seedbits from host seeds.
 im_status set_seed_bits(im_ctx *ctx, uint32_t n, const uint32_t *seeds_host, uint32_t k);
 // First index in zflags[0..count) where the running hit count reaches

@@ -166,3 +166,34 @@ def test_dssa_greedy_ahead_matches_oracle(im, ctx, oracle_lib, name, model, k, a
     finally:
         for x, v in zip(names, old):
             ctx.set_param(x, v)
+
+
+def test_dssa_dropped_covers_outlive_the_run(im, oracle_lib):
+    """A run that stops before a later iteration's cover is done returns
+    without waiting for it. Later runs that need the helper, a graph freed
+    right after such runs, im_ctx_sync and the context's own free all wait
+    for those covers, and every run gives the oracle's result."""
+    g = synth.make("rmat20")
+    og = oracle_lib.Graph(1, g.n, g.src, g.dst, g.w_lt)
+    keys = (0, 1, 2, 3)
+    want = {key: og.dssa(100, 0.1, 1.0 / g.n, key) for key in keys}
+    ctx2 = im.Context(0)
+    try:
+        for rep in range(2):
+            note(f"dropped covers, graph lifetime {rep}")
+            dg = im.Graph(ctx2, g.n, g.src, g.dst, w_lt=g.w_lt)
+            for key in keys:
+                seeds, st = dg.dssa(1, 100, 0.1, 1.0 / g.n, key)
+                oseeds, ost = want[key]
+                assert seeds.tolist() == oseeds.tolist(), (rep, key)
+                _compare(st, ost, "dssa")
+            dg.close()  # right after runs whose dropped covers may still run
+        dg = im.Graph(ctx2, g.n, g.src, g.dst, w_lt=g.w_lt)
+        seeds, _ = dg.dssa(1, 100, 0.1, 1.0 / g.n, 0)
+        ctx2.sync()
+        assert seeds.tolist() == want[0][0].tolist()
+        seeds, _ = dg.dssa(1, 100, 0.1, 1.0 / g.n, 1)
+        assert seeds.tolist() == want[1][0].tolist()
+        dg.close()
+    finally:
+        ctx2.close()
