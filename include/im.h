@@ -343,7 +343,7 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       a range run grid-wide, two launches each (they cover the most sets),
  *       before the one-workgroup rounds take over (default 16);
  *   IM_PARAM_DSSA_GREEDY_AHEAD    im_dssa covers up to this many later
- *       iterations (0..2) at once, each on a helper context with its own
+ *       iterations (0..3) at once, each on a helper context with its own
  *       stream and thread, once the pool holds their sets: iteration t's
  *       Max-Coverage reads only R_t, so the result is the one the iteration
  *       would compute; if the run stops first it is dropped and im_dssa

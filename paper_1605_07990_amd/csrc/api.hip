@@ -202,9 +202,11 @@ struct AheadCover {
     bool busy() const { return running && !done; }
 };
 
-// Join slot i of the two. A dropped cover's pool may be shared by both slots
-// (the run left a cover in each): it is freed by the join that leaves no
-// slot holding it. Only the thread that runs the queries calls this.
+constexpr int kAheadSlots = 3;
+
+// Join slot i. A dropped cover's pool may be shared by several slots (the
+// run left a cover in each): it is freed by the join that leaves no slot
+// holding it. Only the thread that runs the queries calls this.
 static im_status join_slot(AheadCover *a, int i) {
     AheadCover &s = a[i];
     if (!s.running) return IM_OK;
@@ -214,8 +216,9 @@ static im_status join_slot(AheadCover *a, int i) {
     if (s.orphan) {
         im_pool *p = s.orphan;
         s.orphan = nullptr;
-        const AheadCover &o = a[1 - i];
-        if (!(o.running && o.orphan == p)) im_pool_free(p);
+        bool held = false;
+        for (int j = 0; j < kAheadSlots; ++j) held = held || (a[j].running && a[j].orphan == p);
+        if (!held) im_pool_free(p);
         return IM_OK;  // a dropped cover's outcome is not used
     }
     if (s.rc != IM_OK) set_error("%s", s.err.c_str());
@@ -223,13 +226,13 @@ static im_status join_slot(AheadCover *a, int i) {
 }
 
 static AheadCover *ahead_slots(im_ctx *ctx) {
-    if (!ctx->ahead) ctx->ahead = new (std::nothrow) AheadCover[2];
+    if (!ctx->ahead) ctx->ahead = new (std::nothrow) AheadCover[kAheadSlots];
     return ctx->ahead;
 }
 
 void reap_ahead(im_ctx *ctx, const im_graph *g) {
     if (!ctx->ahead) return;
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kAheadSlots; ++i) {
         AheadCover &a = ctx->ahead[i];
         if (a.running && (!g || !a.pool || a.pool->g == g)) (void)join_slot(ctx->ahead, i);
     }
@@ -277,7 +280,7 @@ static void copy_greedy_params(const im_ctx *from, im_ctx *to) {
     to->greedy_wg_cand_batch = from->greedy_wg_cand_batch;
 }
 
-// Helper context i (0 or 1) of ctx for later iterations' Max-Coverage.
+// Helper context i (0..2) of ctx for later iterations' Max-Coverage.
 static im_status helper_ctx(im_ctx *ctx, int i, im_ctx **out) {
     if (!ctx->helpers[i]) IM_TRY(new_side_ctx(ctx, &ctx->helpers[i]));
     copy_greedy_params(ctx, ctx->helpers[i]);
@@ -461,7 +464,7 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         c->greedy_wg_cand_grid_rounds = static_cast<uint32_t>(value);
         return IM_OK;
     case IM_PARAM_DSSA_GREEDY_AHEAD:
-        if (value > 2) break;
+        if (value > 3) break;
         c->dssa_greedy_ahead = static_cast<uint32_t>(value);
         return IM_OK;
     case IM_PARAM_GREEDY_WG_CAND_BATCH:

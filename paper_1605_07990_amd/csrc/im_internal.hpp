@@ -100,11 +100,11 @@ struct im_ctx {
     im_ctx *aux = nullptr;
     // contexts on their own streams that run later D-SSA iterations'
     // Max-Coverage while the current one is covered; created on first use
-    im_ctx *helpers[2] = {nullptr, nullptr};
+    im_ctx *helpers[3] = {nullptr, nullptr, nullptr};
     // the work of each helper: a later iteration's cover, and, when the run
     // stopped before it, the pool it reads (freed once the cover is done)
     im::AheadCover *ahead = nullptr;
-    uint32_t dssa_greedy_ahead = 2;  // later iterations covered at once (0..2)
+    uint32_t dssa_greedy_ahead = 2;  // later iterations covered at once (0..3)
     bool owns_stream = false;
     size_t slot_budget = 8ull << 30;  // long-path slot memory cap
     bool speculate = true;
