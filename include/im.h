@@ -348,7 +348,7 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       Max-Coverage reads only R_t, so the result is the one the iteration
  *       would compute; if the run stops first it is dropped and im_dssa
  *       returns without waiting for it (see im_ctx_sync). The pool never
- *       grows while a helper runs (default 2);
+ *       grows while a helper runs (default 3);
  *   IM_PARAM_GREEDY_WG_CAND_BATCH  the engine's batched Max-Coverage runs
  *       IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS grid-wide rounds and then
  *       one-workgroup rounds over candidate nodes, a workgroup per query,

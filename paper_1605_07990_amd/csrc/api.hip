@@ -1024,9 +1024,11 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
 
     im_pool *pool = nullptr;
     IM_TRY(im_pool_create(ctx, g, model, key, &pool));
+    // the side-sampling context, made on the first draw on the side (an LT
+    // run drawing ahead never makes one, so its stream takes no hardware
+    // queue from the helpers)
     im_ctx *aux = nullptr;
-    if (ctx->speculate && aux_ctx(ctx, &aux) != IM_OK) aux = nullptr;  // run without speculation
-    clear_error();
+    bool aux_tried = false;
     Speculation spec;
     double ms_draw = 0.0, ms_cover_last = 0.0;  // wall time of the last own draw of N_t sets / last cover
     std::vector<uint32_t> seeds(k);
@@ -1083,9 +1085,15 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         if (ms_fresh > 0) ms_draw = ms_fresh;
         const double est_cover = std::max(ms_cover_last, 0.015 * k);
         const bool ahead_lt = model == IM_LT && ctx->dssa_draw_ahead > 1;
-        if (aux && !ahead_lt && double(nt) < c.n_max && 2 * nt <= max_batch(model) && est_cover >= ms_draw &&
-            pool->count < 4 * nt)
-            spec.start(aux, pool, pool->count, 4 * nt - pool->count);
+        if (ctx->speculate && !ahead_lt && double(nt) < c.n_max && 2 * nt <= max_batch(model) &&
+            est_cover >= ms_draw && pool->count < 4 * nt) {
+            if (!aux_tried) {
+                aux_tried = true;
+                if (aux_ctx(ctx, &aux) != IM_OK) aux = nullptr;  // run without speculation
+                clear_error();
+            }
+            if (aux) spec.start(aux, pool, pool->count, 4 * nt - pool->count);
+        }
         // the next iterations whose sets are all drawn are covered on the
         // helper contexts meanwhile (at most one per helper)
         bool synced = false;

@@ -104,7 +104,7 @@ struct im_ctx {
     // the work of each helper: a later iteration's cover, and, when the run
     // stopped before it, the pool it reads (freed once the cover is done)
     im::AheadCover *ahead = nullptr;
-    uint32_t dssa_greedy_ahead = 2;  // later iterations covered at once (0..3)
+    uint32_t dssa_greedy_ahead = 3;  // later iterations covered at once (0..3)
     bool owns_stream = false;
     size_t slot_budget = 8ull << 30;  // long-path slot memory cap
     bool speculate = true;

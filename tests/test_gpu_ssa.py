@@ -141,7 +141,7 @@ def test_wg_candidate_rounds_runs_match_oracle(im, ctx, oracle_lib, algo, name, 
 
 @pytest.mark.parametrize("name,model,k", [("rmat16", 1, 40), ("cl_small", 1, 5), ("nethept", 0, 50),
                                           ("rmat20", 1, 100)])
-@pytest.mark.parametrize("ahead", [0, 1, 2])
+@pytest.mark.parametrize("ahead", [0, 1, 2, 3])
 def test_dssa_greedy_ahead_matches_oracle(im, ctx, oracle_lib, name, model, k, ahead):
     """D-SSA covering later iterations on helper contexts while the current
     one is covered gives the oracle's run, with and without drawing ahead and
