@@ -850,9 +850,23 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
         }
         wave_sync();
         if (kModel == IM_LT) {
-            // the walk runs on lane 0; the other lanes wait
+            // the main pass walked this sample's first max_walk nodes into
+            // its staging region before handing it on; a walk's coins depend
+            // on the node, not the step, so the walk goes on from the last of
+            // them once they are all marked (on lane 0; the others wait)
+            const uint32_t walked = min(kLtMaxWalk, p.lt_cap);
+            const uint32_t *region = p.stage + static_cast<uint64_t>(t) * p.lt_cap;
+            for (uint32_t i = lane; i < walked; i += kWave) {
+                const uint32_t u = region[i];
+                queue[i] = u;
+                vis[u] = stamp;
+            }
+            __threadfence_block();
+            wave_sync();
+            tail = walked;
+            sample_edges = walked - 1;  // the lists of all but the last were examined
             if (lane == 0 && !hit) {
-                uint32_t v = v0;
+                uint32_t v = queue[walked - 1];
                 for (;;) {
                     sample_edges += 1;
                     const uint64_t a = p.off[v], b = p.off[v + 1];
