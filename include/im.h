@@ -338,7 +338,8 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       candidates; if a re-selection keeps fewer than 64 candidates (and
  *       fewer than the rounds left), the remaining rounds run grid-wide, two
  *       launches each (default: every range; 0: off). Takes precedence over
- *       the two parameters above and IM_PARAM_GREEDY_WG_MAX_ENTRIES;
+ *       IM_PARAM_GREEDY_CANDIDATES, IM_PARAM_GREEDY_GRAPH and
+ *       IM_PARAM_GREEDY_WG_MAX_ENTRIES;
  *   IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS the first this many rounds of such
  *       a range run grid-wide, two launches each (they cover the most sets),
  *       before the one-workgroup rounds take over (default 16);
