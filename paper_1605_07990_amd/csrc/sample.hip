@@ -439,7 +439,7 @@ __device__ __forceinline__ uint64_t lt_entry(uint32_t stamp, uint32_t u) {
 }
 
 // The in-edge kept by node v's LT coin c: the first e in [a, b) whose
-// cumulative threshold exceeds c, or b if none. Interpolation on the
+// cumulative threshold exceeds c, or b if none (a < b). Interpolation on the
 // thresholds picks an 8-record window (one round trip); a probe that does not
 // halve the interval makes the next probe a bisection.
 __device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint64_t b, uint32_t c, uint32_t &u) {
@@ -449,7 +449,11 @@ __device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint
     bool bisect = false;
     while (hi - lo > 8) {
         const uint64_t len = hi - lo;
-        const uint64_t g = bisect ? lo + len / 2 : lo + (static_cast<uint64_t>(c) - tlo) * len / (thi - tlo);
+        const uint64_t span = thi - tlo;
+        // both ends still open (the first probe): the division by 2^32 is a shift
+        const uint64_t g = bisect                  ? lo + len / 2
+                           : span == (1ull << 32) ? lo + ((static_cast<uint64_t>(c) * len) >> 32)
+                                                  : lo + (static_cast<uint64_t>(c) - tlo) * len / span;
         uint64_t ws = (g >= lo + 3) ? g - 3 : lo;
         if (ws + 8 > hi) ws = hi - 8;
         uint2 r[8];
@@ -477,19 +481,37 @@ __device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint
         }
         bisect = (hi - lo) * 2 > len;
     }
-    uint2 r[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const uint64_t e = lo + i;
-        r[i] = (e < hi) ? edges[e] : make_uint2(0u, 0u);
-    }
     uint64_t pick = hi;
     uint32_t pu = hi_src;
+    if (b >= 8) {
+        // one window of eight records that covers [lo, hi), all loads in
+        // flight at once (records outside [lo, hi) belong to neighbours and
+        // are skipped)
+        const uint64_t ws = lo < b - 8 ? lo : b - 8;
+        uint2 r[8];
 #pragma unroll
-    for (int i = 7; i >= 0; --i) {
-        if (r[i].y > c) {
-            pick = lo + i;
-            pu = r[i].x;
+        for (int i = 0; i < 8; ++i) r[i] = edges[ws + i];
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+            const uint64_t e = ws + i;
+            if (e >= lo && e < hi && r[i].y > c) {
+                pick = e;
+                pu = r[i].x;
+            }
+        }
+    } else {  // fewer than eight records before b in the whole edge array
+        uint2 r[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint64_t e = lo + i;
+            r[i] = (e < hi) ? edges[e] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+            if (r[i].y > c) {
+                pick = lo + i;
+                pu = r[i].x;
+            }
         }
     }
     if (pick == b) return b;
@@ -508,6 +530,7 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
 
     bool active = false, finished = false;
     uint32_t t = 0, v = 0, len = 0, stamp = 0;
+    uint32_t cv = 0;  // LT coin of v, computed while v's offsets load
     uint64_t s = 0, a = 0, b = 0;
     uint32_t *region = nullptr;
     uint64_t edges_acc = 0, nodes_acc = 0;
@@ -538,6 +561,7 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                     table[lt_bucket(v) * kLtBucketSlots] = lt_entry(stamp, v);
                     a = p.off[v];
                     b = p.off[v + 1];
+                    cv = lt_coin(st, s, v);
                     active = true;
                     if (kMode == 1 && test_bit(seedbits, v)) {
                         p.z[t] = 1;
@@ -558,18 +582,24 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
         bool stop = (a == b);
         uint32_t u = 0;
         uint64_t na = 0, nb = 0;
-        if (!stop) {
-            const uint32_t c = lt_coin(st, s, v);
-            if (lt_pick(p.edges, a, b, c, u) == b) stop = true;
-        }
+        if (!stop && lt_pick(p.edges, a, b, cv, u) == b) stop = true;
         if (!stop) {
             na = p.off[u];
             nb = p.off[u + 1];
             const uint64_t want = lt_entry(stamp, u);
             uint32_t bi = lt_bucket(u);
+            const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+            ulonglong2 q0 = bucket[0], q1 = bucket[1], q2 = bucket[2], q3 = bucket[3];
+            cv = lt_coin(st, s, u);  // the next step's coin, while the loads above are in flight
+            asm volatile("" : "+v"(cv));  // keeps it here rather than after the probe
             for (uint32_t probe = 0; probe < kLtBuckets; ++probe) {
-                const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
-                const ulonglong2 q0 = bucket[0], q1 = bucket[1], q2 = bucket[2], q3 = bucket[3];
+                if (probe) {
+                    bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+                    q0 = bucket[0];
+                    q1 = bucket[1];
+                    q2 = bucket[2];
+                    q3 = bucket[3];
+                }
                 const uint64_t ent[8] = {q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
                 int free_slot = -1;
                 bool found = false;
