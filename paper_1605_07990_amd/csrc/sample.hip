@@ -200,6 +200,33 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
 
 // ---------------------------------------------------------------- IC ----
 
+// The live edges among the four in-edge records of 4-edge group g of a node
+// whose in-edges are [ea, eb). The four loads are issued together (an index
+// outside the range is clipped into it, and its slot is never live), and
+// liveness is decided without a branch, so that the compiler does not move
+// each load behind its own test and wait for them one by one.
+__device__ __forceinline__ void ic_group_live(const uint2 *edges, uint64_t g, uint64_t ea, uint64_t eb,
+                                              const uint4 &coins, uint2 (&rec)[4], bool (&live)[4]) {
+    if (eb <= ea) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            rec[q] = make_uint2(0u, 0u);
+            live[q] = false;
+        }
+        return;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint64_t e = (g << 2) + q;
+        rec[q] = edges[e < ea ? ea : (e < eb ? e : eb - 1)];
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint64_t e = (g << 2) + q;
+        live[q] = (e >= ea) & (e < eb) & ic_live(word_of(coins, q), rec[q].y);
+    }
+}
+
 template <bool kBitmap>
 __device__ __forceinline__ bool vis_insert(uint32_t *vis, uint32_t u, bool &full) {
     if constexpr (kBitmap) {
@@ -340,18 +367,16 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                     const uint64_t ea = fa[lo], eb = fb[lo];
                     const uint64_t g = (ea >> 2) + (w - pre[lo]);
                     const uint4 coins = ic_coins(st, s, g);
-                    const uint64_t e0 = g << 2;
+                    uint2 rec[4];
+                    bool live[4];
+                    ic_group_live(p.edges, g, ea, eb, coins, rec, live);
 #pragma unroll
                     for (uint32_t q = 0; q < 4; ++q) {
-                        const uint64_t e = e0 + q;
-                        if (e >= ea && e < eb) {
-                            const uint2 rec = p.edges[e];
-                            if (ic_live(word_of(coins, q), rec.y) && vis_insert<kBitmap>(vis, rec.x, full)) {
-                                if (q == 0) f0 = rec.x;
-                                else if (q == 1) f1 = rec.x;
-                                else if (q == 2) f2 = rec.x;
-                                else f3 = rec.x;
-                            }
+                        if (live[q] && vis_insert<kBitmap>(vis, rec[q].x, full)) {
+                            if (q == 0) f0 = rec[q].x;
+                            else if (q == 1) f1 = rec[q].x;
+                            else if (q == 2) f2 = rec[q].x;
+                            else f3 = rec[q].x;
                         }
                     }
                 }
@@ -756,17 +781,16 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
                 const uint64_t g = (ea >> 2) + (w - s_pre[lo]);
                 const uint4 coins = ic_coins(st, s, g);
                 bool full = false;
+                uint2 rec[4];
+                bool live[4];
+                ic_group_live(p.edges, g, ea, eb, coins, rec, live);
 #pragma unroll
                 for (uint32_t q = 0; q < 4; ++q) {
-                    const uint64_t e = (g << 2) + q;
-                    if (e >= ea && e < eb) {
-                        const uint2 rec = p.edges[e];
-                        if (ic_live(word_of(coins, q), rec.y) && grp_insert<kGrpHbits>(s_vis, rec.x, full)) {
-                            const uint32_t pos = atomicAdd(&s_tail, 1u);
-                            if (pos < kGrpQcap) s_queue[pos] = rec.x;
-                            else atomicOr(&s_flags, 2u);
-                            if (kMode == 1 && test_bit(seedbits, rec.x)) atomicOr(&s_flags, 1u);
-                        }
+                    if (live[q] && grp_insert<kGrpHbits>(s_vis, rec[q].x, full)) {
+                        const uint32_t pos = atomicAdd(&s_tail, 1u);
+                        if (pos < kGrpQcap) s_queue[pos] = rec[q].x;
+                        else atomicOr(&s_flags, 2u);
+                        if (kMode == 1 && test_bit(seedbits, rec[q].x)) atomicOr(&s_flags, 1u);
                     }
                 }
                 if (full) atomicOr(&s_flags, 2u);
@@ -949,14 +973,12 @@ __global__ __launch_bounds__(kLongWaves *kWave) void long_kernel(Params p, uint3
                         const uint64_t ea = fa[lo], eb = fb[lo];
                         const uint64_t g = (ea >> 2) + (w - pre[lo]);
                         const uint4 coins = ic_coins(st, s, g);
+                        uint2 rec[4];
+                        bool live[4];
+                        ic_group_live(p.edges, g, ea, eb, coins, rec, live);
 #pragma unroll
                         for (uint32_t q = 0; q < 4; ++q) {
-                            const uint64_t e = (g << 2) + q;
-                            if (e >= ea && e < eb) {
-                                const uint2 rec = p.edges[e];
-                                if (ic_live(word_of(coins, q), rec.y) && atomicExch(&vis[rec.x], stamp) != stamp)
-                                    f[q] = rec.x;
-                            }
+                            if (live[q] && atomicExch(&vis[rec[q].x], stamp) != stamp) f[q] = rec[q].x;
                         }
                     }
 #pragma unroll
