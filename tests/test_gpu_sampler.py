@@ -146,6 +146,70 @@ def test_edge_cases(im, ctx, oracle_lib):
         assert np.all(np.diff(off) == 1)
 
 
+
+def _mixed_degree_graph(n, seed):
+    """In-degrees alternating between 0-3 and 20 or more, so that 8-record
+    windows around small in-lists take records of the neighbouring nodes;
+    edges in (dst, src) order; LT weights per node sum to 0.6-1.0 (the
+    live-edge reading of the LT model)."""
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    for v in range(n):
+        d = 20 + v % 13 if v % 5 == 0 else v % 4
+        us = np.sort(rng.choice(np.delete(np.arange(n), v), size=min(d, n - 1), replace=False))
+        src += us.tolist()
+        dst += [v] * len(us)
+    src = np.array(src, np.uint32)
+    dst = np.array(dst, np.uint32)
+    w_ic = rng.uniform(0.05, 1.0, len(src)).astype(np.float32)
+    w_lt = np.zeros(len(src), np.float32)
+    for v in range(n):
+        idx = np.nonzero(dst == v)[0]
+        if len(idx):
+            r = rng.uniform(0.1, 1.0, len(idx))
+            w_lt[idx] = (r / r.sum() * rng.uniform(0.6, 1.0)).astype(np.float32)
+    return src, dst, w_ic, w_lt
+
+
+def test_few_edges_and_neighbouring_windows(im, ctx, oracle_lib):
+    """Edge arrays of fewer than eight records (the LT pick cannot take a full
+    window there) and in-lists shorter than a window next to long ones (the
+    window and the IC 4-edge groups reach into neighbouring nodes' records,
+    which must be skipped)."""
+    cases = [
+        ("one edge", 3, np.array([1], np.uint32), np.array([0], np.uint32)),
+        ("cycle of five", 5, np.array([1, 2, 3, 4, 0], np.uint32), np.array([0, 1, 2, 3, 4], np.uint32)),
+        ("seven edges", 6, np.array([1, 2, 0, 3, 4, 5, 1], np.uint32), np.array([0, 0, 1, 2, 2, 3, 4], np.uint32)),
+    ]
+    for label, n, src, dst in cases:
+        note(f"few edges: {label}")
+        m = len(src)
+        w_ic = np.full(m, 0.8, np.float32)
+        w_lt = np.zeros(m, np.float32)
+        for v in range(n):
+            idx = np.nonzero(dst == v)[0]
+            if len(idx):
+                w_lt[idx] = np.float32(0.9 / len(idx))
+        dg = im.Graph(ctx, n, src, dst, w_ic=w_ic, w_lt=w_lt)
+        for model, w in ((0, w_ic), (1, w_lt)):
+            og = oracle_lib.Graph(model, n, src, dst, w)
+            pool = im.Pool(dg, model, 11 + model)
+            pool.sample(2000)
+            op = oracle_lib.Pool(og, 11 + model)
+            op.extend(2000)
+            assert_pool_equal(pool, op, 0, 2000)
+    note("neighbouring windows: mixed in-degrees")
+    n = 400
+    src, dst, w_ic, w_lt = _mixed_degree_graph(n, 5)
+    dg = im.Graph(ctx, n, src, dst, w_ic=w_ic, w_lt=w_lt)
+    for model, w in ((0, w_ic), (1, w_lt)):
+        og = oracle_lib.Graph(model, n, src, dst, w)
+        pool = im.Pool(dg, model, 21 + model)
+        pool.sample(5000)
+        op = oracle_lib.Pool(og, 21 + model)
+        op.extend(5000)
+        assert_pool_equal(pool, op, 0, 5000)
+
 def test_weighted_sources(im, ctx, oracle_lib):
     g = synth.make("cl_small")
     wts = synth.node_weights(g.n, 0.2, 2.1, 5)
