@@ -93,6 +93,10 @@ im_status im_graph_load(im_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src
  * node_w[v] >= 0 integer relevance of v, n entries, not all zero. After this
  * call RR sets of this graph pick their source v with probability
  * node_w[v] / sum(node_w); NULL restores uniform sources (Definition 2).
+ * The objective becomes the weighted spread I_w(S) (expected total weight
+ * of the nodes S reaches), and since I_w(S) = W Pr[S meets an RR set] with
+ * W = sum(node_w), every reported estimate (i_hat, i_c, Estimate-Inf's I_c)
+ * scales by W instead of n; stopping decisions do not depend on the scale.
  * Pools created before the call are unaffected only if they are not
  * extended again. Errors: IM_E_ARG (all zero), IM_E_OOM.
  */
@@ -164,7 +168,8 @@ im_status im_coverage_range(const im_pool *p, uint64_t begin, uint64_t end, cons
  * Estimate-Inf (Algorithm 3): draw RR sets of samples 0, 1, 2, ... of
  * stream `stream_key`, and at the first T with #{j <= T : R_j meets S} >=
  * Lambda2 = 1 + (1 + eps_p) Upsilon(eps_p, delta_p) return
- * *ic_out = n Lambda2 / T and *t_out = T; after floor(t_max) sets without
+ * *ic_out = n Lambda2 / T (W Lambda2 / T with weighted sources) and
+ * *t_out = T; after floor(t_max) sets without
  * reaching it return *ic_out = -1 and *t_out = floor(t_max).
  * Errors: IM_E_ARG (eps_p, delta_p outside (0,1), seeds out of range).
  */

@@ -380,6 +380,15 @@ int ora_max_coverage(const ora_pool *p, uint64_t begin, uint64_t end, uint32_t n
     return ORA_OK;
 }
 
+/* Scale of an influence estimate. Lemma 1: I(S) = n Pr[S meets an RR set].
+ * With sources drawn in proportion to node weights (WRIS for targeted viral
+ * marketing, Section 7.3) the spread is the expected total weight of the
+ * reached nodes, Pr[S meets R] = I_w(S) / W for the total weight W, and W
+ * takes the place of n. Pinned by the weighted brute-force tests. */
+static double estimate_scale(const ora_graph *g) {
+    return g->src_cum ? (double)g->src_cum[g->n] : (double)g->n;
+}
+
 /* Cov_R(S) over the sets [begin, end) (Eq. 1). Pinned by direct set
  * intersection in the tests. */
 uint64_t ora_coverage(const ora_pool *p, uint64_t begin, uint64_t end, uint32_t n,
@@ -531,7 +540,7 @@ double ora_estimate_inf(const ora_graph *g, const uint32_t *seeds, uint32_t k, d
             if (in_s[buf[i]]) hit = 1;
         cov += (uint64_t)hit;
         if ((double)cov >= lambda2) {
-            result = (double)g->n * lambda2 / (double)T;
+            result = estimate_scale(g) * lambda2 / (double)T;
             break;
         }
     }
@@ -568,7 +577,7 @@ static int ssa_run(const ora_graph *g, uint32_t k, const double c[8], uint64_t k
         uint64_t cov = 0;
         rc = ora_max_coverage(&pool, 0, size, g->n, k, seeds, &cov);
         if (rc) return rc;
-        double i_hat = (double)g->n * (double)cov / (double)size;
+        double i_hat = estimate_scale(g) * (double)cov / (double)size;
         st->iterations = t;
         st->n_sets = size;
         st->cov = cov;
@@ -647,7 +656,7 @@ int ora_ris(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t k
         st->iterations = 1;
         st->n_sets = count;
         st->cov = cov;
-        st->i_hat = (double)g->n * (double)cov / (double)count;
+        st->i_hat = estimate_scale(g) * (double)cov / (double)count;
         st->edges = pool.edges;
     }
     ora_pool_free(&pool);
@@ -670,7 +679,7 @@ int ora_dssa(const ora_graph *g, uint32_t k, double eps, double delta, uint64_t 
     if (rc) return rc;
     const double one_minus_inv_e = 1.0 - exp(-1.0);
     double nmax = c[0], lambda = c[2], lambda1 = c[3];
-    double n = (double)g->n;
+    double n = estimate_scale(g);
     memset(st, 0, sizeof(*st));
     st->i_c = -1.0;
     ora_pool pool;

@@ -348,7 +348,7 @@ im_status estimate_inf(const im_graph *g, im_model model, const uint32_t *seeds,
         IM_TRY(first_crossing(ctx, c, need - cov, &idx, &hits));
         if (idx >= 0) {
             const uint64_t T = done + uint64_t(idx) + 1;
-            *ic_out = double(g->n) * lambda2 / double(T);
+            *ic_out = estimate_scale(g) * lambda2 / double(T);
             *t_out = T;
             if (edges_out) *edges_out = edges;
             return IM_OK;
@@ -799,7 +799,7 @@ static im_status ssa_run(const im_graph *g, im_model model, uint32_t k, double e
     const double lambda1 = (1.0 + eps1) * (1.0 + eps2) * upsilon(eps3, delta / (3.0 * c.i_max));
     const double delta2p = delta / (3.0 * c.i_max);
     const double lambda2 = 1.0 + (1.0 + eps2) * upsilon(eps2, delta2p);
-    const double n = double(g->n);
+    const double n = estimate_scale(g);
 
     im_pool *pool = nullptr;
     IM_TRY(im_pool_create(g->ctx, g, model, key, &pool));
@@ -953,7 +953,7 @@ extern "C" im_status im_ris(const im_graph *g, im_model model, uint32_t k, doubl
         st->iterations = 1;
         st->n_sets = count;
         st->cov = cov;
-        st->i_hat = double(g->n) * double(cov) / double(count);
+        st->i_hat = estimate_scale(g) * double(cov) / double(count);
         st->edges = pool->edges;
         st->it_sets[0] = count;
         st->it_cov[0] = cov;
@@ -1019,7 +1019,7 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     const double one_m = 1.0 - std::exp(-1.0);
     const Caps c = caps(g->n, k, eps, delta);  // t_max = i_max
     const double lambda1 = 1.0 + (1.0 + eps) * upsilon(eps, delta / (3.0 * c.i_max));
-    const double n = double(g->n);
+    const double n = estimate_scale(g);
     im_ctx *ctx = g->ctx;
 
     im_pool *pool = nullptr;

@@ -162,7 +162,7 @@ void next_iteration(Query *q) {
 
 // D-SSA checkpoint after the greedy and the stare step (Algorithm 4).
 void check_dssa(im_engine *e, Query *q, uint64_t cov, uint64_t cov_c) {
-    const double n = double(q->q.graph->n), eps = q->q.eps;
+    const double n = estimate_scale(q->q.graph), eps = q->q.eps;
     const double one_m = 1.0 - std::exp(-1.0);
     const uint32_t t = q->t;
     const uint64_t nt = q->n1 << (t - 1);
@@ -207,7 +207,7 @@ void check_dssa(im_engine *e, Query *q, uint64_t cov, uint64_t cov_c) {
 
 // SSA after the greedy: condition C1 decides whether to verify.
 im_status after_cover_ssa(im_engine *e, Query *q, uint64_t cov) {
-    const double n = double(q->q.graph->n);
+    const double n = estimate_scale(q->q.graph);
     const uint32_t t = q->t;
     const uint64_t size = q->n1 << (t - 1);
     im_stats &st = q->st;
@@ -369,7 +369,7 @@ im_status verify_phase(im_engine *e) {
                 q->verify_edges += tot[j].edges;
                 if (idx[j] >= 0) {
                     const uint64_t T = q->vdone + uint64_t(idx[j]) + 1;
-                    after_verify_ssa(e, q, double(g->n) * q->lambda2 / double(T), T);
+                    after_verify_ssa(e, q, estimate_scale(g) * q->lambda2 / double(T), T);
                     continue;
                 }
                 q->vcov += hits[j];

@@ -215,6 +215,7 @@ im_status graph_build(im_graph *g, const uint32_t *src_h, const uint32_t *dst_h,
 im_status graph_source_weights(im_graph *g, const uint32_t *node_w) {
     im_ctx *ctx = g->ctx;
     dev_free(ctx, g->src_cum);
+    g->src_total = 0;
     if (!node_w) return IM_OK;
     uint64_t total = 0;
     for (uint32_t v = 0; v < g->n; ++v) total += node_w[v];
@@ -240,6 +241,7 @@ im_status graph_source_weights(im_graph *g, const uint32_t *node_w) {
         set_error("source weights: %s", hipGetErrorString(e));
         return IM_E_DEVICE;
     }
+    g->src_total = total;
     return IM_OK;
 }
 

@@ -123,7 +123,16 @@ struct im_graph {
     DevBuf edges_ic;             // uint2[m] {src, thr}
     DevBuf edges_lt;             // uint2[m] {src, cumulative thr}
     DevBuf src_cum;              // u64[n+1] cumulative integer source weights, or empty
+    uint64_t src_total = 0;      // sum of the source weights (0: uniform sources)
 };
+
+// Scale of influence estimates (Lemma 1: I(S) = n Pr[S meets an RR set]).
+// With sources drawn in proportion to node weights (WRIS, Section 7.3) the
+// estimate is of the weighted spread, and Pr[S meets R] = I_w(S) / W with W
+// the total weight, so W takes the place of n.
+inline double estimate_scale(const im_graph *g) {
+    return g->src_total ? double(g->src_total) : double(g->n);
+}
 
 struct im_pool {
     im_ctx *ctx = nullptr;

@@ -19,7 +19,9 @@ from collections import defaultdict
 import numpy as np
 
 
-def _reach(n, live_edges, S):
+def _reach(n, live_edges, S, node_w=None):
+    """Nodes reachable from S over live edges: their number, or the sum of
+    their weights node_w[v] (the targeted spread of Section 7.3)."""
     out = defaultdict(list)
     for u, v in live_edges:
         out[u].append(v)
@@ -31,11 +33,14 @@ def _reach(n, live_edges, S):
             if v not in seen:
                 seen.add(v)
                 stack.append(v)
-    return len(seen)
+    if node_w is None:
+        return len(seen)
+    return float(sum(node_w[v] for v in seen))
 
 
-def ic_exact_spread(n, edges, S):
-    """edges: list of (u, v, p). Exact I(S) under IC by enumeration."""
+def ic_exact_spread(n, edges, S, node_w=None):
+    """edges: list of (u, v, p). Exact I(S) under IC by enumeration (with
+    node_w: the expected total weight of the reached nodes)."""
     m = len(edges)
     total = 0.0
     for mask in range(1 << m):
@@ -49,12 +54,13 @@ def ic_exact_spread(n, edges, S):
                 prob *= 1.0 - p
         if prob == 0.0:
             continue
-        total += prob * _reach(n, live, S)
+        total += prob * _reach(n, live, S, node_w)
     return total
 
 
-def lt_exact_spread(n, edges, S):
-    """edges: list of (u, v, w) with sum of w into each v <= 1. Exact I(S)."""
+def lt_exact_spread(n, edges, S, node_w=None):
+    """edges: list of (u, v, w) with sum of w into each v <= 1. Exact I(S)
+    (with node_w: the expected total weight of the reached nodes)."""
     into = defaultdict(list)
     for u, v, w in edges:
         into[v].append((u, w))
@@ -73,7 +79,7 @@ def lt_exact_spread(n, edges, S):
                 live.append((u, v))
         if prob <= 0.0:
             continue
-        total += prob * _reach(n, live, S)
+        total += prob * _reach(n, live, S, node_w)
     return total
 
 

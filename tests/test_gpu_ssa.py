@@ -58,6 +58,35 @@ def test_run_matches_oracle(im, ctx, oracle_lib, algo, name, model, k, eps, key)
     _compare(st, ost, algo)
 
 
+@pytest.mark.parametrize("algo,model,k,key", [("ssa", 0, 20, 1), ("dssa", 0, 20, 2), ("ssa", 1, 15, 3),
+                                               ("dssa", 1, 15, 4)])
+def test_weighted_runs_match_oracle(im, ctx, oracle_lib, algo, model, k, key):
+    """Targeted sources (WRIS, Section 7.3): seeds, trajectories and the
+    estimates, which scale by the total node weight, equal the oracle's;
+    the same query through the engine gives the same result."""
+    g = synth.make("cl_20k")
+    w = g.w_ic if model == 0 else g.w_lt
+    wts = synth.node_weights(g.n, 0.2, 2.1, 5)
+    note(f"weighted {algo} cl_20k model={model} k={k} key={key}")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
+    dg.set_source_weights(wts)
+    og = oracle_lib.Graph(model, g.n, g.src, g.dst, w, node_weights=wts)
+    delta = 1.0 / g.n
+    seeds, st = getattr(dg, algo)(model, k, 0.1, delta, key)
+    oseeds, ost = getattr(og, algo)(k, 0.1, delta, key)
+    assert seeds.tolist() == oseeds.tolist()
+    _compare(st, ost, algo)
+    assert st["i_hat"] == pytest.approx(float(wts.sum()) * st["cov"] / (st["it_sets"][-1]), rel=1e-12)
+    eng = im.Engine(ctx, pool_budget_bytes=1 << 30, max_active=4)
+    t = eng.submit(dg, model, algo, k, 0.1, delta, key)
+    eng.run()
+    eseeds, est = eng.result(t)
+    eng.close()
+    assert eseeds.tolist() == seeds.tolist()
+    _compare(est, ost, algo)
+    dg.close()
+
+
 def test_query_errors(im, ctx):
     g = synth.make("cl_small")
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
