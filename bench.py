@@ -1,22 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the Stop-and-Stare hot path on one MI355X.
 
-Default workload (--workload rmat20-lt-dssa): the R-MAT scale-20 graph
-(1,048,576 nodes, 16M draws with a,b,c = 0.57, 0.19, 0.19, self-loops and
-repeats dropped), LT model with uniform(0,1) in-weights normalised to sum 1
-per node; each step is one full D-SSA query (Algorithm 4: RR-set sampling,
-incidence, greedy max-coverage, stare step, FP64 checkpoint logic) with
-k = 100, eps = 0.1, delta = 1/n and a fresh stream key.
+Default workload (--workload twitter-ic-dssa), the largest single-GPU
+configuration: the Twitter-shaped Chung-Lu graph (41.7M nodes, 1.47B edges,
+out- and in-degree exponent 2.0, reverse CSR of about 12 GB resident in
+HBM), IC weighted cascade; each step is three full D-SSA queries
+(Algorithm 4: RR-set sampling, incidence, greedy max-coverage, stare step,
+FP64 checkpoint logic) with k = 1, 100 and 1000, eps = 0.1, delta = 1/n and
+stream key = step index.
 
 Other workloads (one JSON line each, same fields):
+  rmat20-lt-dssa  R-MAT scale-20 graph (1,048,576 nodes, 16M draws with
+                  a,b,c = 0.57, 0.19, 0.19, self-loops and repeats dropped),
+                  LT model with uniform(0,1) in-weights normalised to sum 1
+                  per node; each step is one D-SSA query, k = 100.
   pokec-ic-ssa64  Pokec-shaped Chung-Lu graph (4.8M nodes, 69M edges,
                   exponent 2.3), IC trivalency; each step is 64 concurrent
                   SSA queries (k log-uniform in [1, 500], eps in
                   {0.05, 0.1, 0.2}, delta = 1/n, key = query index) through
                   the multi-query engine, all sampling fused per pass.
-  twitter-ic-dssa Twitter-shaped Chung-Lu graph (41.7M nodes, 1.47B edges,
-                  exponent 2.0), IC weighted cascade; each step is three D-SSA
-                  queries, k = 1, 100, 1000, eps = 0.1, delta = 1/n.
   serving         Poisson stream of queries over the resident NetHEPT-,
                   R-MAT-20- and Pokec-shaped graphs through the request loop
                   (continuous batching, admission by RR-pool bytes).
@@ -66,10 +68,11 @@ def percentile(xs, q):
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs (scaled by a plain copy of known size), or
-    None when the kernel's sources, or the query loop that sizes its
-    launches, changed since the counters were taken."""
+    """HBM bytes per timed launch of `kernel` (for the IC sampler: its wave
+    pass and both workgroup tiers) from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by a plain copy of known size), or None when the
+    kernel's sources, or the query loop that sizes its launches, changed
+    since the counters were taken."""
     import hashlib
 
     path = ROOT / "profiles" / "traffic.json"
@@ -84,26 +87,37 @@ def measured_traffic(kernel: str):
     return rec["hbm_bytes_per_dispatch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
-def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_bytes: int = 16 << 30, trials: int = 3) -> dict:
+GATHER_SHAPES = {}
+
+
+def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_bytes: int = 16 << 30, trials: int = 3,
+                     record: str = "") -> dict:
     """Measured random-gather bandwidth (GB/s of segment bytes) per segment
     size, from the probe library: hashed random segment-aligned reads of a
-    buffer (by default far larger than the 256 MB last-level cache)."""
+    buffer (by default far larger than the 256 MB last-level cache), in two
+    access shapes (a lane per segment; the lanes of a wave splitting
+    segments 16 bytes each, eight in flight per lane). The faster shape is
+    the roofline; both curves are kept in GATHER_SHAPES[record]."""
     import ctypes
 
     lib = ctypes.CDLL(str(ROOT / "paper_1605_07990_amd" / "libimprobe.so"))
-    lib.im_probe_gather.restype = ctypes.c_int
-    lib.im_probe_gather.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                    ctypes.POINTER(ctypes.c_double)]
-    out = {}
+    lib.im_probe_gather_shape.restype = ctypes.c_int
+    lib.im_probe_gather_shape.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    out, shapes = {}, {"lane": {}, "coop": {}}
     for seg in segs:
-        g = ctypes.c_double(0.0)
-        if lib.im_probe_gather(0, buffer_bytes, seg, trials, ctypes.byref(g)) != 0:
-            raise RuntimeError(f"gather probe failed for {seg}-byte segments")
-        out[seg] = round(g.value, 1)
+        for shape, name in ((0, "lane"), (1, "coop")):
+            g = ctypes.c_double(0.0)
+            if lib.im_probe_gather_shape(0, buffer_bytes, seg, trials, shape, ctypes.byref(g)) != 0:
+                raise RuntimeError(f"gather probe failed for {seg}-byte segments ({name})")
+            shapes[name][seg] = round(g.value, 1)
+        out[seg] = max(shapes["lane"][seg], shapes["coop"][seg])
+    if record:
+        GATHER_SHAPES[record] = shapes
     return out
 
 
-def roofline(kt: dict, model: int, traffic_measured_here: bool = False) -> dict:
+def roofline(kt: dict, model: int, traffic_measured_here: bool = False, traffic_key: str = "") -> dict:
     """Roofline of the main sampler kernel from its event timing: algorithmic
     bytes per launch over the mean launch duration, against HBM peak.
     `traffic` (HBM bytes per launch from the committed counter runs) is
@@ -120,7 +134,8 @@ def roofline(kt: dict, model: int, traffic_measured_here: bool = False) -> dict:
     ms_per_launch = kt["sample_ms"] / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
     sec = kt["sample_ms"] * 1e-3
-    traffic = measured_traffic("lt_main_kernel" if model == 1 else "ic_main_kernel") if traffic_measured_here else None
+    key = traffic_key or ("lt_main_kernel" if model == 1 else "ic_sampler")
+    traffic = measured_traffic(key) if traffic_measured_here else None
     out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "launches": kt["sample_launches"],
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
@@ -139,6 +154,7 @@ def roofline(kt: dict, model: int, traffic_measured_here: bool = False) -> dict:
             mean = 8.0 * kt["sample_steps"] / max(kt["sample_nodes"], 1)
             seg = min(GATHER, key=lambda x: abs(math.log2(x) - math.log2(max(mean, 1.0))))
         out["gather_gbs"] = GATHER
+        out["gather_gbs_by_shape"] = GATHER_SHAPES.get("hbm")
         out["gather_segment_bytes"] = seg
         out["gather_frac"] = round(achieved / GATHER[seg], 5)
         if seg in GATHER_MALL:
@@ -442,9 +458,14 @@ def run_twitter(args, im, ctx, sync):
            "edges_per_s": round(edges / dt, 1), "p50_ms": round(percentile(lat, 50), 3),
            "p99_ms": round(percentile(lat, 99), 3), "per_k": per_k,
            "graph_generate_s": round(t_gen, 1), "graph_load_s": round(t_load, 2),
-           "roofline": roofline(kt, 0)}
+           "roofline": roofline(kt, 0, traffic_measured_here=(not args.engine and args.ks is None and not args.param
+                                                              and not args.no_speculate
+                                                              and args.greedy_wg_max_entries is None),
+                                traffic_key="ic_sampler_twitter")}
     if args.engine:
         out["config"]["workload"] += ", concurrent through the engine"
+    if not args.no_batching_compare:
+        out["batching"] = batching_compare(im, ctx, dg, sync, progress)
     if args.compare_plain:
         # the same step-0 queries one after another through im_dssa
         sync()
@@ -460,21 +481,106 @@ def run_twitter(args, im, ctx, sync):
     dg.close()
 
     def cpu(budget_s):
-        import oracle
-
-        og = oracle.Graph(oracle.IC, g.n, g.src, g.dst, g.w_ic)
-        pool = oracle.Pool(og, 0)
-        c = 0
-        t = time.perf_counter()
-        while time.perf_counter() - t < budget_s and c < (1 << 16):
-            c += 4096
-            pool.extend(c)
-        d = time.perf_counter() - t
-        return {"value": c / d, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
-                "sample": f"oracle RR-set sampling of samples 0..{c - 1} of key 0 on the same graph "
-                          f"({d:.1f} s, one host core); sampling only"}
+        return oracle_sampling_baseline(g, budget_s)
 
     return out, cpu
+
+
+def batching_compare(im, ctx, dg, sync, progress, queries: int = 8, per_query: int = 145_344) -> dict:
+    """The batched persistent IC sampler against one launch per query, on
+    the same RR sets: `queries` pools (keys 0..queries-1), each drawing
+    `per_query` sets (a k = 100 D-SSA run's 2 N_t at its stop on this graph).
+      fused   one im_sample_rr_multi call: every pool's samples in one device
+              work queue (tickets), heavy samples moved to workgroup tiers;
+      per_query  one im_sample_rr per pool, same kernels;
+      plain   one im_sample_rr per pool with IM_PARAM_IC_PLAIN: static
+              assignment of samples to waves, no tiers (samples that outgrow
+              a wave's LDS go to the one-wave-per-sample long path).
+    Host wall time of each (the calls synchronise), best of two; the three
+    must leave identical pools (offsets and per-set node sums checked)."""
+    import numpy as np
+
+    def run(mode):
+        best, sig = None, None
+        for rep in range(2):
+            pools = [im.Pool(dg, im.IM_IC, q) for q in range(queries)]
+            ctx.set_param("ic_plain", 1 if mode == "plain" else 0)
+            sync()
+            t = time.perf_counter()
+            if mode == "fused":
+                im.Pool.sample_multi(pools, [per_query] * queries)
+            else:
+                for p_ in pools:
+                    p_.sample(per_query)
+            sync()
+            dt = time.perf_counter() - t
+            ctx.set_param("ic_plain", 0)
+            best = dt if best is None else min(best, dt)
+            if rep == 0:
+                sig = []
+                for p_ in pools:
+                    off, nodes = p_.read()
+                    sums = np.add.reduceat(nodes.astype(np.uint64), off[:-1].astype(np.int64)) if nodes.size else 0
+                    sig.append((off.tobytes(), np.asarray(sums).tobytes()))
+            del pools
+        progress(f"batching comparison: {mode} {best * 1e3:.1f} ms")
+        return best, sig
+
+    t_fused, s_fused = run("fused")
+    t_pq, s_pq = run("per_query")
+    t_plain, s_plain = run("plain")
+    sets = queries * per_query
+    return {"workload": f"{queries} IC pools on the Twitter-shaped graph (keys 0..{queries - 1}), {per_query} RR sets "
+                        f"each (a k=100 D-SSA run's 2 N_t at its stop)",
+            "sets": sets, "fused_ms": round(t_fused * 1e3, 3), "per_query_ms": round(t_pq * 1e3, 3),
+            "plain_ms": round(t_plain * 1e3, 3), "fused_sets_per_s": round(sets / t_fused),
+            "plain_sets_per_s": round(sets / t_plain),
+            "speedup_vs_plain": round(t_plain / t_fused, 3), "speedup_vs_per_query": round(t_pq / t_fused, 3),
+            "identical_pools": s_fused == s_pq == s_plain}
+
+
+def host_threads() -> int:
+    """Host threads for the multi-core oracle: the cores this process may
+    run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_sampling_baseline(g, budget_s: float) -> dict:
+    """The oracle's RR-set sampling on the host (IC, key 0, the same graph):
+    the first 2^16 samples on one core (sequential, as the oracle draws
+    them), then the samples after them on every host thread (contiguous
+    sample blocks per thread, the same sets), sized to take about half the
+    budget each. Sampling only: the oracle's greedy over 41.7M nodes is a
+    linear argmax per round."""
+    import oracle
+
+    og = oracle.Graph(oracle.IC, g.n, g.src, g.dst, g.w_ic)
+    pool = oracle.Pool(og, 0)
+    c = 0
+    t = time.perf_counter()
+    while time.perf_counter() - t < budget_s / 2 and c < (1 << 16):
+        c += 4096
+        pool.extend(c)
+    d1 = time.perf_counter() - t
+    e1 = pool.edges
+    one = {"value": c / d1, "edges_per_s": e1 / d1, "cores": 1, "samples": c, "seconds": round(d1, 2)}
+    threads = host_threads()
+    rate = c / d1
+    more = int(min(1 << 22, max(4096, rate * threads * budget_s / 2)))
+    t = time.perf_counter()
+    pool.extend(c + more, threads=threads)
+    dm = time.perf_counter() - t
+    multi = {"value": more / dm, "edges_per_s": (pool.edges - e1) / dm, "cores": threads, "samples": more,
+             "seconds": round(dm, 2)}
+    return {"value": multi["value"], "unit": "RR sets/s", "cores": threads, "kind": "oracle",
+            "edges_per_s": multi["edges_per_s"], "single_core": one,
+            "sample": f"oracle RR-set sampling of key 0 on the same graph, sampling only: samples 0..{c - 1} on one "
+                      f"core ({d1:.1f} s), then samples {c}..{c + more - 1} on {threads} host threads "
+                      f"({dm:.1f} s); value and cores are the multi-thread figures"}
 
 
 WORKLOADS = {"rmat20-lt-dssa": run_rmat20, "pokec-ic-ssa64": run_pokec64, "serving": run_serving,
@@ -486,7 +592,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="rmat20-lt-dssa")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="twitter-ic-dssa")
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--eps", type=float, default=0.1)
     ap.add_argument("--pool-budget-gb", type=float, default=64.0)
@@ -509,6 +615,8 @@ def main() -> int:
                     help="launch parameter: D-SSA draws each iteration's sets only after the previous check")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batching-compare", action="store_true",
+                    help="Twitter-shaped workload: skip timing the batched sampler against one launch per query")
     ap.add_argument("--no-gather-probe", action="store_true",
                     help="skip measuring the random-gather bandwidth the sampler is compared with")
     args = ap.parse_args()
@@ -524,8 +632,8 @@ def main() -> int:
         import torch
 
     if not args.no_gather_probe:
-        GATHER.update(gather_bandwidth())
-        GATHER_MALL.update(gather_bandwidth(segs=(64, 128, 256), buffer_bytes=128 << 20))
+        GATHER.update(gather_bandwidth(record="hbm"))
+        GATHER_MALL.update(gather_bandwidth(segs=(64, 128, 256), buffer_bytes=128 << 20, record="mall"))
     ctx = im.Context(0)
 
     def sync():

@@ -128,6 +128,20 @@ void im_pool_free(im_pool *p);
 im_status im_sample_rr(const im_graph *g, im_model model, uint64_t n_sets, uint64_t stream_key,
                        im_pool *pool);
 
+/*
+ * The batched form of im_sample_rr: append n_sets[i] RR sets (Definition 2)
+ * to pools[i], i < n_pools, all of one graph and model, drawing the sets of
+ * every pool together in fused launches of the persistent sampler (one
+ * device work queue of (pool stream, sample range) items; heavy samples
+ * move to workgroup tiers), at most 2^24 IC or 2^20 LT samples per launch.
+ * Each pool ends as im_sample_rr would leave it: set j of a pool is a pure
+ * function of (graph, model, the pool's key, j). Errors: IM_E_ARG (null
+ * arguments, a pool of another graph, a pool listed twice),
+ * IM_E_STREAM_MISMATCH (a pool of another model), IM_E_OOM, IM_E_DEVICE.
+ */
+im_status im_sample_rr_multi(const im_graph *g, im_model model, uint32_t n_pools, im_pool *const *pools,
+                             const uint64_t *n_sets);
+
 /* Number of sets and total number of node entries in the pool. */
 im_status im_pool_info(const im_pool *p, uint64_t *count, uint64_t *total_nodes);
 
@@ -362,7 +376,15 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES) and the graph has no more
  *       nodes than this (a re-selection passes over every node once per
  *       query); other batches use the batched schedules above (default
- *       2^21; 0: never).
+ *       2^21; 0: never);
+ *   IM_PARAM_IC_PLAIN              1: IC draws run as plain launches, the
+ *       baseline the batched sampler is measured against: every wave takes
+ *       a fixed share of the samples (wave w of W: samples w, w + W, ...)
+ *       instead of tickets from the device work queue, and there are no
+ *       workgroup tiers, so a sample stays with its wave until it outgrows
+ *       the wave's LDS queue or visited set and then goes to the long path
+ *       (one wave per sample with global visited stamps); 0: the batched
+ *       persistent sampler (default 0).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -379,7 +401,8 @@ typedef enum {
     IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES = 10,
     IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 11,
     IM_PARAM_DSSA_GREEDY_AHEAD = 12,
-    IM_PARAM_GREEDY_WG_CAND_BATCH = 13
+    IM_PARAM_GREEDY_WG_CAND_BATCH = 13,
+    IM_PARAM_IC_PLAIN = 14
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

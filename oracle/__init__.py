@@ -28,7 +28,7 @@ MAX_ITERS = 64
 
 def build(force: bool = True) -> Path:
     if force or not _LIB_PATH.exists():
-        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", str(_HERE / "oracle.c"),
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-pthread", str(_HERE / "oracle.c"),
                "-o", str(_LIB_PATH) + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(str(_LIB_PATH) + ".tmp", _LIB_PATH)
@@ -87,6 +87,7 @@ def _load():
         "ora_rr_set": (ctypes.c_uint32, [gp, ctypes.c_uint64, ctypes.c_uint64, u32p, u64p]),
         "ora_pool_init": (ctypes.c_int, [pp, ctypes.c_uint64]),
         "ora_pool_extend": (ctypes.c_int, [pp, gp, ctypes.c_uint64]),
+        "ora_pool_extend_threads": (ctypes.c_int, [pp, gp, ctypes.c_uint64, ctypes.c_int]),
         "ora_pool_free": (None, [pp]),
         "ora_pool_load": (ctypes.c_int, [pp, ctypes.c_uint64, u64p, u32p]),
         "ora_max_coverage": (ctypes.c_int, [pp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
@@ -317,8 +318,14 @@ class Pool:
     def edges(self) -> int:
         return int(self.p.edges)
 
-    def extend(self, new_count: int):
-        if _load().ora_pool_extend(ctypes.byref(self.p), self.graph.ref, new_count):
+    def extend(self, new_count: int, threads: int = 1):
+        """Append sets up to new_count; threads > 1 splits the new samples
+        into contiguous blocks drawn on that many host threads (same sets)."""
+        if threads > 1:
+            rc = _load().ora_pool_extend_threads(ctypes.byref(self.p), self.graph.ref, new_count, threads)
+        else:
+            rc = _load().ora_pool_extend(ctypes.byref(self.p), self.graph.ref, new_count)
+        if rc:
             raise MemoryError
 
     def offsets(self) -> np.ndarray:

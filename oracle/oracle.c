@@ -8,6 +8,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -192,9 +193,10 @@ static int cmp_u32(const void *a, const void *b) {
 }
 
 uint32_t ora_rr_set(const ora_graph *g, uint64_t key, uint64_t s, uint32_t *out, uint64_t *edges) {
-    /* out doubles as the BFS queue; `seen` marks members */
-    static unsigned char *seen = NULL;
-    static uint32_t seen_n = 0;
+    /* out doubles as the BFS queue; `seen` marks members (one buffer per
+     * host thread, so that independent runs may proceed on several threads) */
+    static _Thread_local unsigned char *seen = NULL;
+    static _Thread_local uint32_t seen_n = 0;
     if (seen_n < g->n) {
         free(seen);
         seen = (unsigned char *)calloc(g->n, 1);
@@ -315,6 +317,103 @@ int ora_pool_extend(ora_pool *p, const ora_graph *g, uint64_t new_count) {
     }
     free(buf);
     return ORA_OK;
+}
+
+/* The same extension with the sample range split into `threads` contiguous */
+/* blocks, one per host thread. Each set is a pure function of (key, s), so  */
+/* the pool equals the sequential one; this exists only to time the oracle   */
+/* on several host cores.                                                    */
+typedef struct {
+    const ora_graph *g;
+    uint64_t key, s0, s1;
+    uint32_t *nodes;
+    uint64_t *sizes;
+    uint64_t cap, used, edges;
+    int failed;
+} ora_block;
+
+static void *draw_block(void *arg) {
+    ora_block *b = (ora_block *)arg;
+    uint32_t *buf = (uint32_t *)malloc(sizeof(uint32_t) * b->g->n);
+    b->cap = 1 << 16;
+    b->nodes = (uint32_t *)malloc(sizeof(uint32_t) * b->cap);
+    b->sizes = (uint64_t *)malloc(sizeof(uint64_t) * (b->s1 - b->s0 + 1));
+    if (!buf || !b->nodes || !b->sizes) {
+        b->failed = 1;
+        free(buf);
+        return NULL;
+    }
+    for (uint64_t s = b->s0; s < b->s1; ++s) {
+        uint64_t ex = 0;
+        uint32_t size = ora_rr_set(b->g, b->key, s, buf, &ex);
+        while (b->used + size > b->cap) {
+            b->cap *= 2;
+            b->nodes = (uint32_t *)realloc(b->nodes, sizeof(uint32_t) * b->cap);
+            if (!b->nodes) {
+                b->failed = 1;
+                free(buf);
+                return NULL;
+            }
+        }
+        memcpy(b->nodes + b->used, buf, sizeof(uint32_t) * size);
+        b->used += size;
+        b->sizes[s - b->s0] = size;
+        b->edges += ex;
+    }
+    free(buf);
+    return NULL;
+}
+
+int ora_pool_extend_threads(ora_pool *p, const ora_graph *g, uint64_t new_count, int threads) {
+    if (new_count <= p->count) return ORA_OK;
+    if (threads < 1) threads = 1;
+    uint64_t todo = new_count - p->count;
+    if ((uint64_t)threads > todo) threads = (int)todo;
+    ora_block *blocks = (ora_block *)calloc((size_t)threads, sizeof(ora_block));
+    pthread_t *tid = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
+    if (!blocks || !tid) return ORA_E_OOM;
+    for (int i = 0; i < threads; ++i) {
+        blocks[i].g = g;
+        blocks[i].key = p->key;
+        blocks[i].s0 = p->count + todo * (uint64_t)i / (uint64_t)threads;
+        blocks[i].s1 = p->count + todo * (uint64_t)(i + 1) / (uint64_t)threads;
+        pthread_create(&tid[i], NULL, draw_block, &blocks[i]);
+    }
+    int rc = ORA_OK;
+    for (int i = 0; i < threads; ++i) {
+        pthread_join(tid[i], NULL);
+        if (blocks[i].failed) rc = ORA_E_OOM;
+    }
+    for (int i = 0; i < threads && rc == ORA_OK; ++i) {
+        ora_block *b = &blocks[i];
+        uint64_t nsets = b->s1 - b->s0;
+        while (p->count + nsets > p->cap_sets) {
+            p->cap_sets *= 2;
+            p->off = (uint64_t *)realloc(p->off, sizeof(uint64_t) * (p->cap_sets + 1));
+        }
+        uint64_t base = p->off[p->count];
+        while (base + b->used > p->cap_nodes) {
+            p->cap_nodes *= 2;
+            p->nodes = (uint32_t *)realloc(p->nodes, sizeof(uint32_t) * p->cap_nodes);
+        }
+        if (!p->off || !p->nodes) {
+            rc = ORA_E_OOM;
+            break;
+        }
+        memcpy(p->nodes + base, b->nodes, sizeof(uint32_t) * b->used);
+        for (uint64_t j = 0; j < nsets; ++j) {
+            p->off[p->count + 1] = p->off[p->count] + b->sizes[j];
+            p->count++;
+        }
+        p->edges += b->edges;
+    }
+    for (int i = 0; i < threads; ++i) {
+        free(blocks[i].nodes);
+        free(blocks[i].sizes);
+    }
+    free(blocks);
+    free(tid);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -118,6 +118,8 @@ uint32_t ora_rr_set(const ora_graph *g, uint64_t key, uint64_t s, uint32_t *out,
 
 int ora_pool_init(ora_pool *p, uint64_t key);
 int ora_pool_extend(ora_pool *p, const ora_graph *g, uint64_t new_count);
+/* the same sets drawn by `threads` host threads over contiguous blocks */
+int ora_pool_extend_threads(ora_pool *p, const ora_graph *g, uint64_t new_count, int threads);
 int ora_pool_load(ora_pool *p, uint64_t count, const uint64_t *off, const uint32_t *nodes);
 void ora_pool_free(ora_pool *p);
 

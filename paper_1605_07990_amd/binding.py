@@ -31,7 +31,8 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_ssa", "im_dssa", "im_derived_key", "im_last_error", "im_ctx_set_timing", "im_ctx_read_timing",
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
            "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param", "im_ssa_eps",
-           "im_ssa_eps_preset", "im_ris_theta", "im_ris", "im_engine_submit_estimate", "im_ctx_sync"]
+           "im_ssa_eps_preset", "im_ris_theta", "im_ris", "im_engine_submit_estimate", "im_ctx_sync",
+           "im_sample_rr_multi"]
 
 IM_NET_SMALL, IM_NET_MODERATE, IM_NET_LARGE = 0, 1, 2
 REGIMES = {"small": IM_NET_SMALL, "moderate": IM_NET_MODERATE, "large": IM_NET_LARGE}
@@ -40,7 +41,7 @@ IM_PARAM_GREEDY_WG_MAX_ENTRIES, IM_PARAM_IC_TICKET_BLOCK, IM_PARAM_DSSA_SPECULAT
 IM_PARAM_GREEDY_MARK_MIN_CHUNKS, IM_PARAM_GREEDY_COVER_BLOCKS, IM_PARAM_IC_EDGE_BUDGET = 3, 4, 5
 IM_PARAM_GREEDY_CANDIDATES, IM_PARAM_GREEDY_CANDIDATES_BATCH, IM_PARAM_DSSA_DRAW_AHEAD = 6, 7, 8
 IM_PARAM_GREEDY_GRAPH, IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES, IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 9, 10, 11
-IM_PARAM_DSSA_GREEDY_AHEAD, IM_PARAM_GREEDY_WG_CAND_BATCH = 12, 13
+IM_PARAM_DSSA_GREEDY_AHEAD, IM_PARAM_GREEDY_WG_CAND_BATCH, IM_PARAM_IC_PLAIN = 12, 13, 14
 PARAMS = {"greedy_cover_blocks": IM_PARAM_GREEDY_COVER_BLOCKS, "ic_edge_budget": IM_PARAM_IC_EDGE_BUDGET, "greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK,
           "dssa_speculate": IM_PARAM_DSSA_SPECULATE, "greedy_mark_min_chunks": IM_PARAM_GREEDY_MARK_MIN_CHUNKS,
           "greedy_candidates": IM_PARAM_GREEDY_CANDIDATES, "greedy_candidates_batch": IM_PARAM_GREEDY_CANDIDATES_BATCH,
@@ -48,7 +49,8 @@ PARAMS = {"greedy_cover_blocks": IM_PARAM_GREEDY_COVER_BLOCKS, "ic_edge_budget":
           "greedy_wg_cand_max_entries": IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES,
           "greedy_wg_cand_grid_rounds": IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS,
           "dssa_greedy_ahead": IM_PARAM_DSSA_GREEDY_AHEAD,
-          "greedy_wg_cand_batch": IM_PARAM_GREEDY_WG_CAND_BATCH}
+          "greedy_wg_cand_batch": IM_PARAM_GREEDY_WG_CAND_BATCH,
+          "ic_plain": IM_PARAM_IC_PLAIN}
 
 IM_ALGO_SSA, IM_ALGO_DSSA, IM_ALGO_ESTIMATE = 0, 1, 2
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}
@@ -145,6 +147,7 @@ def load_library(path: Path | str | None = None):
         "im_pool_create": (st, [vp, vp, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(vp)]),
         "im_pool_free": (None, [vp]),
         "im_sample_rr": (st, [vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, vp]),
+        "im_sample_rr_multi": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(vp), u64p]),
         "im_pool_info": (st, [vp, u64p, u64p]),
         "im_pool_read": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, u64p, u32p]),
         "im_pool_device": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
@@ -394,6 +397,18 @@ class Pool:
     def sample(self, n_sets: int, key: int | None = None, model=None):
         _check(load_library().im_sample_rr(self.graph.h, self.model if model is None else MODELS[model], n_sets,
                                            self.key if key is None else key, self.h))
+
+    @staticmethod
+    def sample_multi(pools, counts):
+        """im_sample_rr_multi: append counts[i] sets to pools[i] (one graph
+        and model) in fused launches of the batched sampler."""
+        if not pools:
+            return
+        g, model = pools[0].graph, pools[0].model
+        hs = (ctypes.c_void_p * len(pools))(*[p.h for p in pools])
+        cs = np.ascontiguousarray(counts, dtype=np.uint64)
+        _check(load_library().im_sample_rr_multi(g.h, model, len(pools), hs,
+                                                 cs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
 
     def info(self):
         c, t = ctypes.c_uint64(), ctypes.c_uint64()

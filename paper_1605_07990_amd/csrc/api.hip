@@ -470,6 +470,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
     case IM_PARAM_GREEDY_WG_CAND_BATCH:
         c->greedy_wg_cand_batch = value;
         return IM_OK;
+    case IM_PARAM_IC_PLAIN:
+        if (value > 1) break;
+        c->ic_plain = value != 0;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -520,6 +524,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_GREEDY_WG_CAND_BATCH:
         *value = c->greedy_wg_cand_batch;
+        return IM_OK;
+    case IM_PARAM_IC_PLAIN:
+        *value = c->ic_plain ? 1 : 0;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
@@ -687,6 +694,60 @@ extern "C" im_status im_sample_rr(const im_graph *g, im_model model, uint64_t n_
         return IM_E_STREAM_MISMATCH;
     }
     return pool_extend_to(pool, pool->count + n_sets, nullptr);
+}
+
+extern "C" im_status im_sample_rr_multi(const im_graph *g, im_model model, uint32_t n_pools, im_pool *const *pools,
+                                        const uint64_t *n_sets) {
+    clear_error();
+    if (!g || (n_pools && (!pools || !n_sets))) {
+        set_error("im_sample_rr_multi: null arguments");
+        return IM_E_ARG;
+    }
+    for (uint32_t i = 0; i < n_pools; ++i) {
+        const im_pool *p = pools[i];
+        if (!p || p->g != g) {
+            set_error("im_sample_rr_multi: pool %u is null or belongs to another graph", i);
+            return IM_E_ARG;
+        }
+        if (p->model != model) {
+            set_error("im_sample_rr_multi: pool %u is of model %d, the call's is %d", i, int(p->model), int(model));
+            return IM_E_STREAM_MISMATCH;
+        }
+        for (uint32_t j = 0; j < i; ++j)
+            if (pools[j] == p) {
+                set_error("im_sample_rr_multi: pool %u appears twice", i);
+                return IM_E_ARG;
+            }
+    }
+    // fused launches of up to a batch cap of samples each, pools in order
+    std::vector<uint64_t> left(n_sets, n_sets + n_pools);
+    const uint64_t cap = max_batch(model);
+    uint32_t i = 0;
+    while (i < n_pools) {
+        std::vector<SampleItem> items;
+        std::vector<im_pool *> members;
+        uint64_t total = 0;
+        double hint = 0.0;
+        for (; i < n_pools && total < cap; ++i) {
+            if (left[i] == 0) continue;
+            const uint64_t take = std::min<uint64_t>(left[i], cap - total);
+            items.push_back(SampleItem{pools[i]->key, pools[i]->count, take, nullptr});
+            members.push_back(pools[i]);
+            total += take;
+            left[i] -= take;
+            hint = std::max(hint, pools[i]->mean_size);
+            if (left[i]) break;  // the rest of this pool goes in the next launch
+        }
+        if (items.empty()) break;
+        SampleResult r;
+        std::vector<ItemTotals> tot(items.size());
+        IM_TRY(sample_items(g->ctx, g, model, items.data(), uint32_t(items.size()), SampleMode::Pool, hint, &r,
+                            tot.data()));
+        std::vector<AppendItem> app(items.size());
+        for (size_t j = 0; j < items.size(); ++j) app[j] = AppendItem{members[j], items[j].count, tot[j].nodes, tot[j].edges};
+        IM_TRY(pool_append_items(g->ctx, app.data(), uint32_t(app.size())));
+    }
+    return IM_OK;
 }
 
 extern "C" im_status im_pool_info(const im_pool *p, uint64_t *count, uint64_t *total_nodes) {

@@ -78,6 +78,7 @@ struct im_ctx {
     uint64_t greedy_mark_min_chunks = 1u << 16;
     uint32_t greedy_cover_blocks = 0;  // 0: automatic
     uint32_t ic_edge_budget = 16384;
+    bool ic_plain = false;  // IC draws as plain launches (static assignment, no workgroup tiers)
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 8;           // im_dssa on LT: a draw takes up to this many iterations' sets

@@ -103,6 +103,7 @@ struct Params {
     uint32_t lt_cap;
     uint32_t ticket_block;  // IC: consecutive samples a wave takes per ticket
     uint32_t edge_budget;   // IC: edges a wave examines before a workgroup takes the sample over
+    uint32_t plain;         // IC: 1 = static assignment (wave w takes samples w, w + W, ...), no tickets
 };
 
 // The work item owning global slot t.
@@ -177,6 +178,13 @@ __device__ __forceinline__ void flush_lanes(ItemAcc &ia) {
     } else {
         ia.flush();
     }
+}
+
+// Plain IC launches have no workgroup tiers: the samples the wave pass hands
+// on go straight to the long path.
+__global__ void plain_handoff_kernel(Counters *c) {
+    c->long_count = c->defer_count;
+    c->long_ticket = 0;
 }
 
 __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
@@ -301,15 +309,23 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
     // the staging chunk carved up without further atomics
     uint32_t t_next = 0, t_end = 0, cur = 0;
     uint64_t chunk_pos = 0, chunk_end = 0;
+    // plain launches: the wave's fixed share of the samples, no work queue
+    const uint32_t waves_total = gridDim.x * kIcWaves;
+    uint32_t plain_next = blockIdx.x * kIcWaves + wave;
 
     for (;;) {
         if (t_next == t_end) {
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&p.cnt->ticket, p.ticket_block);
-            base = __shfl(base, 0, kWave);
+            if (p.plain) {
+                base = plain_next;
+                plain_next += waves_total;
+            } else {
+                if (lane == 0) base = atomicAdd(&p.cnt->ticket, p.ticket_block);
+                base = __shfl(base, 0, kWave);
+            }
             if (base >= p.count) break;
             t_next = base;
-            t_end = min(base + p.ticket_block, p.count);
+            t_end = p.plain ? base + 1 : min(base + p.ticket_block, p.count);
         }
         const uint32_t t = t_next++;
         const WorkItem &it = item_cached(p, t, cur);
@@ -1296,6 +1312,11 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         p.lt_cap = kLtCap;
         p.ticket_block = 1;
         p.edge_budget = ctx->ic_edge_budget;
+        // plain IC launches: static assignment, no workgroup tiers (a sample
+        // leaves the wave pass only when it outgrows the wave's LDS)
+        const bool plain = model == IM_IC && ctx->ic_plain;
+        p.plain = plain ? 1u : 0u;
+        if (plain) p.edge_budget = 0xFFFFFFFFu;
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
         zero_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(dacc), 2ull * nitems);
@@ -1330,7 +1351,9 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
             else lt_main_kernel<1><<<grid, kWave, 0, st>>>(p, tables, stamp_base);
         }
         if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_end, st));
-        if (model == IM_IC) {
+        if (model == IM_IC && plain) {
+            plain_handoff_kernel<<<1, 1, 0, st>>>(cnt);
+        } else if (model == IM_IC) {
             const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
             Counters *c = cnt;
             if (mode == SampleMode::Pool) {
@@ -1352,8 +1375,13 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
             auto *slot_mem = static_cast<uint32_t *>(ctx->slots.ptr);
             auto *epochs = slot_mem + 2ull * g->n * nslots;
             if (model == IM_IC) {
-                if (mode == SampleMode::Pool) long_kernel<IM_IC, 0><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
-                else long_kernel<IM_IC, 1><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
+                Params pl = p;
+                if (plain) pl.long_list = p.defer_list;  // the wave pass's hand-ons, in its order
+                if (mode == SampleMode::Pool) long_kernel<IM_IC, 0><<<grid, kLongWaves * kWave, 0, st>>>(pl, slot_mem, g->n, nslots, epochs);
+                else long_kernel<IM_IC, 1><<<grid, kLongWaves * kWave, 0, st>>>(pl, slot_mem, g->n, nslots, epochs);
+                // a plain launch's timing covers its long path, which does
+                // the work the tiers do otherwise
+                if (plain && ctx->timing) IM_HIP(hipEventRecord(ctx->ev_group, st));
             } else {
                 if (mode == SampleMode::Pool) long_kernel<IM_LT, 0><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);
                 else long_kernel<IM_LT, 1><<<grid, kLongWaves * kWave, 0, st>>>(p, slot_mem, g->n, nslots, epochs);

@@ -270,3 +270,63 @@ def test_heavy_ic_samples_workgroup_tier(im, ctx, oracle_lib, n, deg, p):
     # hits mode through the same tiers: Estimate-Inf's stopping index
     seeds = np.array([0, 1], dtype=np.uint32)
     assert dg.estimate_inf(0, seeds, 0.2, 0.1, 5000.0, 99) == og.estimate_inf(seeds, 0.2, 0.1, 5000.0, 99)
+
+
+@pytest.mark.parametrize("name", ["cl_mid", "heavy6000"])
+def test_plain_launches_and_fused_pools_match_oracle(im, ctx, oracle_lib, name):
+    """The plain IC launch (static assignment, no workgroup tiers: samples
+    that outgrow a wave's LDS go to the long path) and the fused multi-pool
+    draw (im_sample_rr_multi: several pools' samples in one work queue) give
+    the oracle's sets, including heavy samples and ragged counts."""
+    if name == "cl_mid":
+        g = synth.make("cl_mid")
+    else:
+        n, deg = 6000, 40
+        rng = np.random.default_rng(n + deg)
+        dst = np.repeat(np.arange(n, dtype=np.uint32), deg)
+        src = rng.integers(0, n, size=n * deg).astype(np.uint32)
+        keep = src != dst
+        pairs = np.unique(np.stack([dst[keep], src[keep]], axis=1), axis=0)
+        g = synth.from_edges(f"heavy{n}", n, pairs[:, 1], pairs[:, 0],
+                             w_ic=np.full(pairs.shape[0], 0.3, dtype=np.float32))
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+    counts = [3000, 0, 5000, 1] if name == "cl_mid" else [300, 0, 257, 1]
+    keys = [21, 22, 23, 24]
+    note(f"fused pools {name} counts={counts}")
+    pools = [im.Pool(dg, 0, key) for key in keys]
+    im.Pool.sample_multi(pools, counts)
+    im.Pool.sample_multi(pools, [7, 65, 0, 300])  # appends after the first batch
+    for p, key, c in zip(pools, keys, [c + d for c, d in zip(counts, [7, 65, 0, 300])]):
+        op = oracle_lib.Pool(og, key)
+        op.extend(c)
+        assert p.count == c
+        if c:
+            assert_pool_equal(p, op, 0, c)
+    note(f"plain launches {name}")
+    ctx.set_param("ic_plain", 1)
+    try:
+        for key, c in zip(keys, counts):
+            p = im.Pool(dg, 0, key)
+            p.sample(c)
+            op = oracle_lib.Pool(og, key)
+            op.extend(c)
+            if c:
+                assert_pool_equal(p, op, 0, c)
+        seeds = np.array([0, 1], dtype=np.uint32)
+        assert dg.estimate_inf(0, seeds, 0.2, 0.1, 5000.0, 99) == og.estimate_inf(seeds, 0.2, 0.1, 5000.0, 99)
+    finally:
+        ctx.set_param("ic_plain", 0)
+
+
+def test_fused_pools_argument_errors(im, ctx):
+    g = synth.make("cl_small")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic, w_lt=g.w_lt)
+    a, b = im.Pool(dg, 0, 1), im.Pool(dg, 1, 2)
+    with pytest.raises(im.ImError) as e:
+        im.Pool.sample_multi([a, b], [5, 5])  # mixed models
+    assert e.value.status == -5
+    with pytest.raises(im.ImError) as e:
+        im.Pool.sample_multi([a, a], [5, 5])  # a pool twice
+    assert e.value.status == -1
+    assert a.count == 0 and b.count == 0

@@ -158,3 +158,36 @@ def test_sets_sorted_and_distinct(oracle_lib, synth_lib):
             r, _ = og.rr_set(1, s)
             assert np.all(np.diff(r.astype(np.int64)) > 0)
             assert og.source(1, s) in set(r.tolist())
+
+
+def test_threaded_extension_equals_sequential(oracle_lib, synth_lib):
+    # The multi-core timing path draws contiguous sample blocks on host
+    # threads; every set is a pure function of (key, s), so the pool (and its
+    # edge count) must equal the sequential one, for any thread count.
+    g = synth_lib.make("cl_small")
+    for model, w in ((0, g.w_ic), (1, g.w_lt)):
+        og = oracle_lib.Graph(model, g.n, g.src, g.dst, w)
+        ref = oracle_lib.Pool(og, 12)
+        ref.extend(3001)
+        for threads in (2, 7, 16):
+            p = oracle_lib.Pool(og, 12)
+            p.extend(1000)
+            p.extend(3001, threads=threads)
+            assert np.array_equal(p.offsets(), ref.offsets())
+            assert np.array_equal(p.nodes(), ref.nodes())
+            assert p.edges == ref.edges
+
+
+def test_concurrent_runs_on_threads(oracle_lib, synth_lib):
+    # Runs on several host threads at once (ctypes releases the GIL) give the
+    # results of the same runs one after another.
+    from concurrent.futures import ThreadPoolExecutor
+
+    g = synth_lib.make("cl_small")
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+    keys = list(range(8))
+    seq = [og.dssa(5, 0.2, 1.0 / g.n, key) for key in keys]
+    with ThreadPoolExecutor(4) as ex:
+        par = list(ex.map(lambda key: og.dssa(5, 0.2, 1.0 / g.n, key), keys))
+    for (a, sa), (b, sb) in zip(seq, par):
+        assert a.tolist() == b.tolist() and sa == sb
