@@ -384,7 +384,16 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       workgroup tiers, so a sample stays with its wave until it outgrows
  *       the wave's LDS queue or visited set and then goes to the long path
  *       (one wave per sample with global visited stamps); 0: the batched
- *       persistent sampler (default 0).
+ *       persistent sampler (default 0);
+ *   IM_PARAM_GREEDY_FLAT_LEVELS    1: when a range's one-workgroup rounds
+ *       hand over because the gains are flat (a cut keeps too few
+ *       candidates), the remaining rounds go level by level: with g* the
+ *       largest gain and L the unchosen nodes of gain g* in id order, a
+ *       level takes, walking L in order, every node none of whose g*
+ *       uncovered sets was covered earlier in the level (exactly the
+ *       rounds' argmaxes), then the gains are recounted for the next level;
+ *       levels with g* above 16 use the grid-wide rounds; 0: grid-wide
+ *       rounds, two launches each (default 1).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -402,7 +411,8 @@ typedef enum {
     IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 11,
     IM_PARAM_DSSA_GREEDY_AHEAD = 12,
     IM_PARAM_GREEDY_WG_CAND_BATCH = 13,
-    IM_PARAM_IC_PLAIN = 14
+    IM_PARAM_IC_PLAIN = 14,
+    IM_PARAM_GREEDY_FLAT_LEVELS = 15
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

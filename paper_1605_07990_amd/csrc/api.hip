@@ -474,6 +474,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 1) break;
         c->ic_plain = value != 0;
         return IM_OK;
+    case IM_PARAM_GREEDY_FLAT_LEVELS:
+        if (value > 1) break;
+        c->greedy_flat_levels = value != 0;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -528,6 +532,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
     case IM_PARAM_IC_PLAIN:
         *value = c->ic_plain ? 1 : 0;
         return IM_OK;
+    case IM_PARAM_GREEDY_FLAT_LEVELS:
+        *value = c->greedy_flat_levels ? 1 : 0;
+        return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
     return IM_E_ARG;
@@ -578,7 +585,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     if (c->ev_group) (void)hipEventDestroy(c->ev_group);
     free_round_graphs(c);
-    for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits,
+    for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits, &c->flat,
                       &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);

@@ -1024,11 +1024,23 @@ __device__ __forceinline__ uint32_t wg_slot(const WgLds &L, uint32_t u) {
     return kNoCand;
 }
 
+// Pointers the compiler knows to be global: their loads and atomics become
+// global instructions rather than flat ones, which also count against the
+// LDS wait counter and so make every LDS wait also wait for them.
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4u32 gconst_u4;
+typedef __attribute__((address_space(1))) const uint32_t gconst_u32;
+typedef __attribute__((address_space(1))) uint32_t gmem_u32;
+
 template <bool kLdsCov>
 __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words, WgLds &L) {
     constexpr uint32_t kMask = (1u << kCandHashBits) - 1u;
     const uint32_t tid = threadIdx.x, bd = blockDim.x;
-    uint32_t *covbits = kLdsCov ? L.cov : g.covbits;
+    const gconst_u4 *iext = (const gconst_u4 *)g.iext;
+    const gconst_u32 *pnodes = (const gconst_u32 *)g.pnodes;
+    gmem_u32 *gcov = (gmem_u32 *)g.covbits;
+    gmem_u32 *gseeds = (gmem_u32 *)g.seeds;
+    gmem_u32 *ggain = (gmem_u32 *)g.gain;
     if constexpr (kLdsCov)
         for (uint64_t w = tid; w < words; w += bd) L.cov[w] = g.covbits[w];
     for (uint32_t i = tid; i <= kMask; i += bd) L.key[i] = kNoCand;
@@ -1085,8 +1097,8 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
         const uint32_t sv = __shfl(bslot, static_cast<int>(__ffsll(holder)) - 1, kWave);
         const uint32_t v = ~static_cast<uint32_t>(wbest & 0xFFFFFFFFull);
         if (tid == 0) {
-            g.seeds[r] = v;
-            atomicOr(&g.gain[v], kChosen);
+            gseeds[r] = v;
+            __hip_atomic_fetch_or(&ggain[v], kChosen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const uint64_t a = L.ia[sv], b = a + L.ilen[sv];
         if (a == b) {  // v is in no set (every gain left is zero): only its chosen bit
@@ -1101,10 +1113,13 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
             // the count of this batch (parity bp) was cleared during the one before
             const uint64_t i = e0 + tid;
             if (i < b) {
-                const uint4 x = g.iext[i];
+                const v4u32 x = iext[i];
                 const uint32_t j = x.x;
                 const uint32_t bit = 1u << (j & 31u);
-                if (!(atomicOr(&covbits[j >> 5], bit) & bit)) {
+                uint32_t old;
+                if constexpr (kLdsCov) old = atomicOr(&L.cov[j >> 5], bit);
+                else old = __hip_atomic_fetch_or(&gcov[j >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!(old & bit)) {
                     const uint32_t f = atomicAdd(&L.nfresh[bp], 1u);
                     L.fstart[f] = static_cast<uint64_t>(x.z) | (static_cast<uint64_t>(x.w) << 32);
                     L.fsize[f] = x.y;
@@ -1147,7 +1162,7 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
 #pragma unroll
                             for (uint32_t t = 0; t < 4; ++t) {
                                 const uint32_t q = q0 + sub + 16u * t;
-                                u[4 * w + t] = q < sz[w] ? g.pnodes[sa[w] + q] : kNoCand;
+                                u[4 * w + t] = q < sz[w] ? pnodes[sa[w] + q] : kNoCand;
                             }
 #pragma unroll
                         for (uint32_t t = 0; t < 16; ++t) drop(u[t]);
@@ -1163,7 +1178,7 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
 #pragma unroll
                         for (uint32_t t = 0; t < 8; ++t) {
                             const uint32_t q = q0 + sub + 16u * t;
-                            u[t] = q < sz ? g.pnodes[sa + q] : kNoCand;
+                            u[t] = q < sz ? pnodes[sa + q] : kNoCand;
                         }
 #pragma unroll
                         for (uint32_t t = 0; t < 8; ++t) drop(u[t]);
@@ -1376,6 +1391,19 @@ __global__ __launch_bounds__(kThreads) void wg_collect_kernel(const GreedyState 
         take(4u * i + 3u, q.w);
     }
     for (uint32_t v = 4u * n4 + blockIdx.x * blockDim.x + tid; v < g.n; v += gridDim.x * blockDim.x) take(v, g.gain[v]);
+}
+
+// Max-Coverage with one seed: the packed key (count << 32 | ~v) of the node
+// in the most sets (ties to the lowest id; every count zero gives node 0).
+__global__ __launch_bounds__(kThreads) void argmax_count_kernel(const uint32_t *cnt, uint32_t n,
+                                                                unsigned long long *out) {
+    unsigned long long best = 0;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const unsigned long long key = (static_cast<unsigned long long>(cnt[v]) << 32) | static_cast<uint32_t>(~v);
+        best = key > best ? key : best;
+    }
+    best = wave_max_u64(best);
+    if (lane_id() == 0 && best) atomicMax(out, best);
 }
 
 // Sets in [begin, end) that contain a node of the seed bitmap.
@@ -1623,6 +1651,249 @@ __global__ __launch_bounds__(1024) void crossing_items_kernel(const uint8_t *z, 
     if (threadIdx.x == 0) {
         out[2 * blockIdx.x] = s_idx;
         out[2 * blockIdx.x + 1] = static_cast<long long>(run);
+    }
+}
+
+// ---- greedy rounds level by level (flat gains) ----
+//
+// When the candidate cut keeps too few nodes (many nodes share the gain at
+// the cut), the remaining rounds go by gain level. Let g* be the largest gain
+// of an unchosen node and L the unchosen nodes with gain g*, in increasing id
+// order. Gains only fall, so while a node of L still has g* uncovered sets it
+// is a round's argmax, and the lowest-id such node is the seed. A node of L
+// still has gain g* exactly when none of the sets it had uncovered when L was
+// listed has been covered since. So a level walks L in order and takes every
+// node whose sets are all still uncovered; the nodes it passes over now have
+// less and wait for a later level. Once L is walked the largest gain is below
+// g*: the gains are recounted from the sets still uncovered and the next
+// level is listed. Only nodes that had a gain when the level rounds began
+// (`act`, kept in id order) can have one later.
+
+constexpr uint32_t kFlatMaxGain = 16;  // a larger g* goes back to the grid-wide rounds
+constexpr uint32_t kFlatBatch = 256;   // candidates resolved per pass of the level kernel
+constexpr uint32_t kFlatHash = 8192;   // LDS hash of the sets one pass covers (>= 2 x 256 x 16)
+constexpr uint32_t kFlatTile = 2048;   // items per block of the ordered compactions
+constexpr uint32_t kFlatEmpty = 0xFFFFFFFFu;
+
+struct FlatState {
+    unsigned int gstar;  // the level's g* (unchosen maximum)
+    uint32_t r;          // rounds done
+    uint32_t pad[6];
+};
+
+enum : int { kFlatAct = 0, kFlatLevel = 1, kFlatUnchosen = 2 };
+
+// Which items an ordered compaction keeps: kFlatAct the unchosen nodes with a
+// gain (items are node ids 0..n-1), kFlatLevel the unchosen nodes of `in`
+// with gain g*, kFlatUnchosen every unchosen node (ids 0..n-1).
+template <int kMode>
+__device__ __forceinline__ bool flat_keep(const uint32_t *gain, uint32_t v, uint32_t gstar) {
+    const uint32_t x = gain[v];
+    if (x & kChosen) return false;
+    if constexpr (kMode == kFlatAct) return x != 0u;
+    else if constexpr (kMode == kFlatLevel) return x == gstar;
+    else return true;
+}
+
+template <int kMode>
+__device__ __forceinline__ uint32_t flat_item(const uint32_t *in, uint64_t i) {
+    if constexpr (kMode == kFlatLevel) return in[i];
+    else return static_cast<uint32_t>(i);
+}
+
+// Ordered compaction, pass 1: kept items per tile of kFlatTile (8 per thread).
+template <int kMode>
+__global__ __launch_bounds__(kThreads) void flat_count_kernel(const uint32_t *gain, const uint32_t *in,
+                                                              const uint64_t *nin_p, uint64_t nin_fixed,
+                                                              const FlatState *fs, uint64_t *bcount) {
+    __shared__ uint64_t smem[kThreads / kWave];
+    const uint64_t nin = nin_p ? *nin_p : nin_fixed;
+    const uint32_t gstar = fs->gstar;
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kFlatTile + threadIdx.x * 8ull;
+    uint64_t c = 0;
+    for (uint32_t i = 0; i < 8; ++i)
+        if (b0 + i < nin) c += flat_keep<kMode>(gain, flat_item<kMode>(in, b0 + i), gstar);
+    uint64_t total = 0;
+    block_scan_excl(c, smem, total);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = total;
+}
+
+// Pass 3 (after the exclusive scan of the tile counts): write the kept items
+// in order, at most cap of them.
+template <int kMode>
+__global__ __launch_bounds__(kThreads) void flat_write_kernel(const uint32_t *gain, const uint32_t *in,
+                                                              const uint64_t *nin_p, uint64_t nin_fixed,
+                                                              const FlatState *fs, const uint64_t *boff,
+                                                              uint32_t *out, uint64_t cap) {
+    __shared__ uint64_t smem[kThreads / kWave];
+    const uint64_t nin = nin_p ? *nin_p : nin_fixed;
+    const uint32_t gstar = fs->gstar;
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kFlatTile + threadIdx.x * 8ull;
+    uint32_t keep = 0;
+    uint64_t c = 0;
+    for (uint32_t i = 0; i < 8; ++i)
+        if (b0 + i < nin && flat_keep<kMode>(gain, flat_item<kMode>(in, b0 + i), gstar)) {
+            keep |= 1u << i;
+            ++c;
+        }
+    uint64_t total = 0;
+    uint64_t pos = boff[blockIdx.x] + block_scan_excl(c, smem, total);
+    for (uint32_t i = 0; i < 8; ++i)
+        if ((keep >> i) & 1u) {
+            if (pos < cap) out[pos] = flat_item<kMode>(in, b0 + i);
+            ++pos;
+        }
+}
+
+__global__ void flat_init_kernel(FlatState *fs, uint32_t r) {
+    fs->gstar = 0;
+    fs->r = r;
+}
+
+// g* = the largest gain of an unchosen node of act.
+__global__ __launch_bounds__(kThreads) void flat_max_kernel(const uint32_t *gain, const uint32_t *act,
+                                                            const uint64_t *nact_p, FlatState *fs) {
+    const uint64_t nact = *nact_p;
+    uint32_t best = 0;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nact;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t x = gain[act[i]];
+        if (!(x & kChosen) && x > best) best = x;
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const uint32_t y = __shfl_xor(best, d, kWave);
+        best = y > best ? y : best;
+    }
+    if (lane_id() == 0 && best) atomicMax(&fs->gstar, best);
+}
+
+// Recount, step 1: the gains of act back to zero (chosen bits kept), and g*
+// reset for the next level's maximum.
+__global__ __launch_bounds__(kThreads) void flat_clear_kernel(uint32_t *gain, const uint32_t *act,
+                                                              const uint64_t *nact_p, FlatState *fs) {
+    const uint64_t nact = *nact_p;
+    if (blockIdx.x == 0 && threadIdx.x == 0) fs->gstar = 0;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nact;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        gain[act[i]] &= kChosen;
+}
+
+// Recount, step 2: every set not covered adds one to each member's gain.
+__global__ __launch_bounds__(kThreads) void flat_recount_kernel(GreedyState g) {
+    const uint32_t sub = threadIdx.x & 15u;
+    const uint64_t step = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 4;
+    for (uint64_t j = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4; j < g.nsets; j += step) {
+        if ((g.covbits[j >> 5] >> (j & 31u)) & 1u) continue;
+        const uint64_t sa = g.poff[g.begin + j], sb = g.poff[g.begin + j + 1];
+        for (uint64_t q = sa + sub; q < sb; q += 16) atomicAdd(&g.gain[g.pnodes[q]], 1u);
+    }
+}
+
+__device__ __forceinline__ uint32_t flat_hash(uint32_t j) { return (j * 0x9E3779B1u) >> (32 - 13); }
+
+// One level: walk the listed nodes (gain g* when listed, in id order) in
+// passes of kFlatBatch. Each pass gathers every candidate's uncovered sets,
+// then wave 0 takes, in order, each candidate that still has g* of them and
+// none covered earlier in the pass (an LDS hash of the pass's covered sets),
+// and the block writes the pass's seeds, chosen bits and covered bits.
+__global__ __launch_bounds__(1024) void flat_level_kernel(GreedyState g, const uint32_t *list,
+                                                          const uint64_t *nlist_p, FlatState *fs) {
+    __shared__ uint32_t s_sets[kFlatBatch][kFlatMaxGain];
+    __shared__ uint32_t s_cnt[kFlatBatch];
+    __shared__ uint32_t s_hash[kFlatHash];
+    __shared__ uint32_t s_sel[kFlatBatch];
+    __shared__ uint32_t s_nsel;
+    const uint32_t gstar = fs->gstar;
+    const uint64_t nlist = *nlist_p;
+    uint32_t r = fs->r;
+    if (gstar == 0 || gstar > kFlatMaxGain) return;
+    for (uint32_t i = threadIdx.x; i < kFlatHash; i += blockDim.x) s_hash[i] = kFlatEmpty;
+    for (uint64_t base = 0; base < nlist && r < g.k; base += kFlatBatch) {
+        // gather: candidate t's sets not covered yet (covered bits come from
+        // earlier passes' atomics, read past the L1)
+        if (threadIdx.x < kFlatBatch) {
+            const uint32_t t = threadIdx.x;
+            uint32_t c = 0;
+            if (base + t < nlist) {
+                const uint32_t v = list[base + t];
+                const uint64_t e0 = g.ioff[v], e1 = g.ioff[v + 1];
+                for (uint64_t e = e0; e < e1; ++e) {
+                    const uint32_t j = g.iext ? g.iext[e].x : g.isets[e];
+                    if (!((ld<true>(g.covbits + (j >> 5)) >> (j & 31u)) & 1u)) {
+                        if (c < kFlatMaxGain) s_sets[t][c] = j;
+                        ++c;
+                    }
+                }
+            }
+            s_cnt[t] = c;
+        }
+        __syncthreads();
+        // resolve the pass in order (wave 0)
+        if (threadIdx.x < kWave) {
+            const uint32_t lane = threadIdx.x;
+            uint32_t nsel = 0;
+            for (uint32_t i = 0; i < kFlatBatch && base + i < nlist && r + nsel < g.k; ++i) {
+                if (s_cnt[i] != gstar) continue;  // its gain fell before this pass
+                uint32_t j = 0, h = 0;
+                bool seen = false;
+                if (lane < gstar) {
+                    j = s_sets[i][lane];
+                    h = flat_hash(j);
+                    for (;;) {
+                        const uint32_t x = s_hash[h];
+                        if (x == kFlatEmpty) break;
+                        if (x == j) {
+                            seen = true;
+                            break;
+                        }
+                        h = (h + 1u) & (kFlatHash - 1u);
+                    }
+                }
+                if (__ballot(seen)) continue;  // a set of it was covered earlier in the pass
+                if (lane < gstar) {
+                    // the sets of one node are distinct: claim a free slot each
+                    for (;;) {
+                        const uint32_t prev = atomicCAS(&s_hash[h], kFlatEmpty, j);
+                        if (prev == kFlatEmpty) break;
+                        h = (h + 1u) & (kFlatHash - 1u);
+                    }
+                }
+                if (lane == 0) s_sel[nsel] = i;
+                ++nsel;
+            }
+            if (lane == 0) s_nsel = nsel;
+        }
+        __syncthreads();
+        const uint32_t nsel = s_nsel;
+        for (uint32_t q = threadIdx.x; q < nsel * kFlatMaxGain; q += blockDim.x) {
+            const uint32_t si = q / kFlatMaxGain, l = q % kFlatMaxGain;
+            const uint32_t i = s_sel[si];
+            if (l < gstar) {
+                const uint32_t j = s_sets[i][l];
+                atomicOr(&g.covbits[j >> 5], 1u << (j & 31u));
+            }
+            if (l == 0) {
+                const uint32_t v = list[base + i];
+                g.seeds[r + si] = v;
+                atomicOr(&g.gain[v], kChosen);
+            }
+        }
+        if (threadIdx.x == 0 && nsel) atomicAdd(g.cov, static_cast<unsigned long long>(nsel) * gstar);
+        r += nsel;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kFlatHash; i += blockDim.x) s_hash[i] = kFlatEmpty;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) fs->r = r;
+}
+
+// Every gain is zero: the remaining seeds (rounds r..k-1) are the lowest
+// unchosen ids (listed in order), which cover nothing.
+__global__ void flat_zero_kernel(GreedyState g, const uint32_t *list, uint32_t r) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; r + i < g.k; i += gridDim.x * blockDim.x) {
+        const uint32_t v = list[i];
+        g.seeds[r + i] = v;
+        g.gain[v] |= kChosen;
     }
 }
 
@@ -1903,6 +2174,76 @@ static im_status round_graph(im_ctx *ctx, const GreedyState *dg, uint32_t k, uin
     return IM_OK;
 }
 
+
+// Rounds [*r, k) of one range level by level (see flat_level_kernel), with
+// every gain exact on entry. Leaves *r < k when the largest gain is above
+// kFlatMaxGain (the grid-wide rounds take over, gains still exact).
+static im_status flat_rounds(im_ctx *ctx, const GreedyState &g, uint64_t entries, uint32_t *r_io) {
+    const uint32_t n = g.n, k = g.k;
+    const uint64_t cap = std::max<uint64_t>(std::min<uint64_t>(n, entries), k) + 1;
+    const uint64_t nb_n = (uint64_t(n) + kFlatTile - 1) / kFlatTile;
+    const uint64_t nb_c = (cap + kFlatTile - 1) / kFlatTile;
+    const size_t o_act = 256 + (((nb_n + 1) * 8 + 255) & ~size_t(255));
+    const size_t o_bl = o_act + ((cap * 4 + 255) & ~size_t(255));
+    const size_t o_list = o_bl + (((nb_c + 1) * 8 + 255) & ~size_t(255));
+    const size_t bytes = o_list + cap * 4 + 256;
+    IM_TRY(dev_reserve(ctx, ctx->flat, bytes));
+    char *base = static_cast<char *>(ctx->flat.ptr);
+    auto *fs = reinterpret_cast<FlatState *>(base);
+    auto *bc_n = reinterpret_cast<uint64_t *>(base + 256);  // tiles over node ids (act, zero tail)
+    auto *act = reinterpret_cast<uint32_t *>(base + o_act);
+    auto *bc_c = reinterpret_cast<uint64_t *>(base + o_bl);  // tiles over act (levels)
+    auto *list = reinterpret_cast<uint32_t *>(base + o_list);
+    const uint64_t *nact_p = bc_n + nb_n;    // after the act compaction's scan
+    const uint64_t *nlist_p = bc_c + nb_c;   // after a level compaction's scan
+    hipStream_t st = ctx->stream;
+    const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+    const uint32_t gb_n = static_cast<uint32_t>(std::max<uint64_t>(1, nb_n));
+    const uint32_t gb_c = static_cast<uint32_t>(std::max<uint64_t>(1, nb_c));
+    flat_init_kernel<<<1, 1, 0, st>>>(fs, *r_io);
+    // act: the unchosen nodes with a gain, in id order
+    fill_u64_kernel<<<1, 64, 0, st>>>(bc_n + nb_n, 1, 0);
+    flat_count_kernel<kFlatAct><<<gb_n, kThreads, 0, st>>>(g.gain, nullptr, nullptr, n, fs, bc_n);
+    tile_scan_kernel<<<1, 1024, 0, st>>>(bc_n, nb_n + 1);
+    flat_write_kernel<kFlatAct><<<gb_n, kThreads, 0, st>>>(g.gain, nullptr, nullptr, n, fs, bc_n, act, cap);
+    uint32_t r = *r_io;
+    for (uint32_t level = 0; r < k; ++level) {
+        if (level > 0) {
+            flat_clear_kernel<<<grid_of(cap, kThreads, cu * 8), kThreads, 0, st>>>(g.gain, act, nact_p, fs);
+            flat_recount_kernel<<<grid_of(g.nsets * 16, kThreads, cu * 16), kThreads, 0, st>>>(g);
+        }
+        flat_max_kernel<<<grid_of(cap, kThreads, cu * 8), kThreads, 0, st>>>(g.gain, act, nact_p, fs);
+        fill_u64_kernel<<<1, 64, 0, st>>>(bc_c + nb_c, 1, 0);
+        flat_count_kernel<kFlatLevel><<<gb_c, kThreads, 0, st>>>(g.gain, act, nact_p, 0, fs, bc_c);
+        tile_scan_kernel<<<1, 1024, 0, st>>>(bc_c, nb_c + 1);
+        flat_write_kernel<kFlatLevel><<<gb_c, kThreads, 0, st>>>(g.gain, act, nact_p, 0, fs, bc_c, list, cap);
+        flat_level_kernel<<<1, 1024, 0, st>>>(g, list, nlist_p, fs);
+        IM_HIP(hipGetLastError());
+        FlatState h{};
+        IM_TRY(to_host_sync(ctx, &h, fs, sizeof(h)));
+        if (h.gstar == 0) {
+            // every gain is zero: the lowest unchosen ids, in order
+            fill_u64_kernel<<<1, 64, 0, st>>>(bc_n + nb_n, 1, 0);
+            flat_count_kernel<kFlatUnchosen><<<gb_n, kThreads, 0, st>>>(g.gain, nullptr, nullptr, n, fs, bc_n);
+            tile_scan_kernel<<<1, 1024, 0, st>>>(bc_n, nb_n + 1);
+            flat_write_kernel<kFlatUnchosen><<<gb_n, kThreads, 0, st>>>(g.gain, nullptr, nullptr, n, fs, bc_n, list,
+                                                                       cap);
+            flat_zero_kernel<<<grid_of(k - r, kThreads, 64), kThreads, 0, st>>>(g, list, r);
+            IM_HIP(hipGetLastError());
+            r = k;
+            break;
+        }
+        if (h.gstar > kFlatMaxGain) break;  // gains are exact: the grid-wide rounds go on
+        if (h.r <= r) {
+            set_error("max coverage: a gain level chose no seed");
+            return IM_E_DEVICE;
+        }
+        r = h.r;
+    }
+    *r_io = r;
+    return IM_OK;
+}
+
 im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t k, uint32_t *seeds_host,
                        uint64_t *cov) {
     return max_coverage_on(p->ctx, p, begin, end, k, seeds_host, cov);
@@ -1920,6 +2261,27 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
     const uint64_t ebegin = ends[0], eend = ends[1];
     const uint64_t entries = eend - ebegin;
 
+    if (k == 1) {
+        // one round of Algorithm 2: the node in the most sets of the range;
+        // its count is Cov (a node is in a set at most once). No incidence.
+        IM_TRY(dev_reserve(ctx, ctx->cover, 4ull * n + 256));
+        auto *cnt = static_cast<uint32_t *>(ctx->cover.ptr);
+        auto *key = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->cover.ptr) +
+                                                           ((4ull * n + 255) & ~255ull));
+        hipStream_t st = ctx->stream;
+        const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+        fill_u32_kernel<<<grid_of(n, kThreads, cu * 8), kThreads, 0, st>>>(cnt, n, 0u);
+        fill_u64_kernel<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t *>(key), 1, 0);
+        if (entries)
+            histogram_kernel<<<grid_of(entries, kThreads, cu * 16), kThreads, 0, st>>>(pnodes, ebegin, eend, cnt);
+        argmax_count_kernel<<<grid_of(n, kThreads, cu * 8), kThreads, 0, st>>>(cnt, n, key);
+        IM_HIP(hipGetLastError());
+        unsigned long long h = 0;
+        IM_TRY(to_host_sync(ctx, &h, key, 8));
+        seeds_host[0] = ~static_cast<uint32_t>(h);
+        *cov = h >> 32;
+        return IM_OK;
+    }
     // layout of the working arrays in ctx->cover
     const uint64_t tiles = (uint64_t(n) + kTile - 1) / kTile;
     const uint32_t n1 = (n + (1u << kL1Shift) - 1) >> kL1Shift;
@@ -2029,6 +2391,9 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
         StepHdr *hdr = g.hdr;
         uint32_t grid_from = k;
         IM_TRY(run_wg_cycles(ctx, dg, &hdr, &k, 1, n, nsets, lead, &grid_from));
+        // flat gains: level by level, then (if a level's gain is too large
+        // for it) the grid-wide rounds
+        if (grid_from < k && ctx->greedy_flat_levels) IM_TRY(flat_rounds(ctx, g, entries, &grid_from));
         if (grid_from < k) grid_rounds(grid_from, k);
         IM_HIP(hipGetLastError());
         IM_HIP(hipMemcpyAsync(seeds_host, g.seeds, 4ull * k, hipMemcpyDeviceToHost, st));
@@ -2373,3 +2738,4 @@ im_status first_crossing_items(im_ctx *ctx, const CrossItem *items, uint32_t nit
     return IM_OK;
 }
 }  // namespace im
+

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -67,6 +68,7 @@ struct im_ctx {
     uint64_t lt_stamp = 1;    // next LT walk stamp (never 0: zeroed entries are free)
     DevBuf cover;        // incidence / greedy working arrays
     DevBuf seedbits;     // seed-set bitmap (n bits)
+    DevBuf flat;         // greedy rounds by gain level: state, node lists, tile counts
     DevBuf zflags;       // Estimate-Inf per-sample hit flags
     DevBuf items;        // fused sampler work queue + per-item accumulators
     DevBuf append_dst;   // per-item pool destinations of a fused append
@@ -79,6 +81,7 @@ struct im_ctx {
     uint32_t greedy_cover_blocks = 0;  // 0: automatic
     uint32_t ic_edge_budget = 16384;
     bool ic_plain = false;  // IC draws as plain launches (static assignment, no workgroup tiers)
+    bool greedy_flat_levels = true;  // flat gains: rounds by gain level instead of grid-wide rounds
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 8;           // im_dssa on LT: a draw takes up to this many iterations' sets
@@ -125,6 +128,9 @@ struct im_graph {
     DevBuf edges_lt;             // uint2[m] {src, cumulative thr}
     DevBuf src_cum;              // u64[n+1] cumulative integer source weights, or empty
     uint64_t src_total = 0;      // sum of the source weights (0: uniform sources)
+    // IC, LT: mean RR-set size of the last draw (a staging estimate; draws of
+    // one graph may run on several threads' contexts at once)
+    mutable std::atomic<double> mean_set[2] = {0.0, 0.0};
 };
 
 // Scale of influence estimates (Lemma 1: I(S) = n Pr[S meets an RR set]).

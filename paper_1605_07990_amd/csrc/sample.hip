@@ -1282,7 +1282,10 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
 
     // staging capacity: LT reserves a region per sample, then a bump area
     // for long walks; IC bump-allocates every set.
-    const double hint = size_hint > 0 ? size_hint : (model == IM_IC ? 16.0 : 64.0);
+    // expected set size: the caller's, else this graph's last draws of the
+    // model, else a guess (a guess too small costs a re-run of the batch)
+    const double seen = g->mean_set[model == IM_IC ? 0 : 1].load(std::memory_order_relaxed);
+    const double hint = size_hint > 0 ? size_hint : seen > 0 ? seen : (model == IM_IC ? 16.0 : 64.0);
     uint64_t lt_regions = (model == IM_LT) ? count * kLtCap : 0;
     // IC waves reserve staging in chunks of kStageChunk: allow one partly
     // used chunk per wave on top of the expected sizes
@@ -1291,7 +1294,10 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
     if (mode == SampleMode::Hits && model == IM_IC) cap = 0;
 
     for (int attempt = 0; attempt < 8; ++attempt) {
-        if (cap) IM_TRY(dev_reserve(ctx, ctx->stage, cap * 4));
+        if (cap) {
+            IM_TRY(dev_reserve(ctx, ctx->stage, cap * 4));
+            cap = ctx->stage.bytes / 4;  // all of it: a buffer kept from a larger batch holds more
+        }
         Params p{};
         p.off = static_cast<const uint64_t *>(g->off.ptr);
         p.edges = static_cast<const uint2 *>(edges.ptr);
@@ -1399,6 +1405,9 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         }
         for (uint32_t i = 0; i < nitems; ++i) per_item[i] = ItemTotals{hacc[2 * i], hacc[2 * i + 1]};
         res->total_nodes = hc.total_nodes + hc.nodes_long;
+        if (mode == SampleMode::Pool && count)
+            g->mean_set[model == IM_IC ? 0 : 1].store(double(res->total_nodes) / double(count),
+                                                      std::memory_order_relaxed);
         res->edges = hc.edges + hc.edges_long;
         res->deferred = hc.defer_count;
         res->count = count;

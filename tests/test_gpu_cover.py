@@ -159,15 +159,18 @@ def test_wg_candidate_rounds_agree(im, ctx, pools, name, lead):
         ctx.set_param("greedy_wg_cand_grid_rounds", old[1])
 
 
+@pytest.mark.parametrize("flat", [1, 0])
 @pytest.mark.parametrize("lead", [0, 2])
-def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead):
+def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead, flat):
     """k = n on a graph without edges (every gain reaches zero), flat gains
-    (the grid-wide rounds take over), and more sets than the LDS covered-set
-    bitmap holds."""
-    note(f"one-workgroup candidate rounds: k = n, 400k sets, lead={lead}")
-    old = ctx.get_param("greedy_wg_cand_max_entries"), ctx.get_param("greedy_wg_cand_grid_rounds")
+    (the rounds by gain level, or the grid-wide rounds, take over), and more
+    sets than the LDS covered-set bitmap holds."""
+    note(f"one-workgroup candidate rounds: k = n, 400k sets, lead={lead} flat levels={flat}")
+    old = (ctx.get_param("greedy_wg_cand_max_entries"), ctx.get_param("greedy_wg_cand_grid_rounds"),
+           ctx.get_param("greedy_flat_levels"))
     ctx.set_param("greedy_wg_cand_max_entries", 1 << 62)
     ctx.set_param("greedy_wg_cand_grid_rounds", lead)
+    ctx.set_param("greedy_flat_levels", flat)
     try:
         n = 40
         e = np.array([], np.uint32)
@@ -195,6 +198,11 @@ def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead):
             seeds, cov = p.max_coverage(k)
             oseeds, ocov = op.max_coverage(k)
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), k
+        # more seeds than nodes that appear: the zero-gain tail after the levels
+        for begin, end, k in ((0, 3000, 4000), (5000, 5700, 900)):
+            seeds, cov = p.max_coverage(k, begin, end)
+            oseeds, ocov = op.max_coverage(k, begin, end)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (begin, end, k)
         g = synth.make("cl_20k")
         dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
         og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
@@ -209,6 +217,7 @@ def test_wg_candidate_rounds_edge_cases(im, ctx, oracle_lib, lead):
     finally:
         ctx.set_param("greedy_wg_cand_max_entries", old[0])
         ctx.set_param("greedy_wg_cand_grid_rounds", old[1])
+        ctx.set_param("greedy_flat_levels", old[2])
 
 
 def test_one_workgroup_greedy_large_range(im, ctx, oracle_lib):
