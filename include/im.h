@@ -179,6 +179,23 @@ im_status im_coverage_range(const im_pool *p, uint64_t begin, uint64_t end, cons
                             uint32_t k, uint64_t *cov_out);
 
 /*
+ * The count of im_coverage_range (same arguments, same result) for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation. It calls no hipMalloc,
+ * hipFree or allocating routine; its scratch (counter, seed list, seed
+ * bitmap) is one fixed device array of about 8.3 MiB per GPU, whose address
+ * im_ctx_create takes once per device and which stays held until the process
+ * ends. Limits: the pool's graph has at most 2^26 nodes and k <= 2^16.
+ * Every call on one GPU shares that array (each call clears what it needs),
+ * so calls that overlap on one GPU, from any contexts or threads, race: the
+ * caller must serialise them. Errors: IM_E_ARG (bad range, null pointers,
+ * n or k beyond the limits, seed id >= n), IM_E_STATE (no scratch address
+ * for the pool's device), IM_E_DEVICE.
+ */
+im_status im_coverage_range_noalloc(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds,
+                                    uint32_t k, uint64_t *cov_out);
+
+/*
  * Estimate-Inf (Algorithm 3): draw RR sets of samples 0, 1, 2, ... of
  * stream `stream_key`, and at the first T with #{j <= T : R_j meets S} >=
  * Lambda2 = 1 + (1 + eps_p) Upsilon(eps_p, delta_p) return

@@ -32,7 +32,7 @@ EXPORTS = ["im_ctx_create", "im_ctx_free", "im_graph_load", "im_graph_set_source
            "im_engine_create", "im_engine_free", "im_engine_submit", "im_engine_step", "im_engine_run",
            "im_engine_poll", "im_engine_result", "im_ctx_set_param", "im_ctx_get_param", "im_ssa_eps",
            "im_ssa_eps_preset", "im_ris_theta", "im_ris", "im_engine_submit_estimate", "im_ctx_sync",
-           "im_sample_rr_multi"]
+           "im_coverage_range_noalloc", "im_sample_rr_multi"]
 
 IM_NET_SMALL, IM_NET_MODERATE, IM_NET_LARGE = 0, 1, 2
 REGIMES = {"small": IM_NET_SMALL, "moderate": IM_NET_MODERATE, "large": IM_NET_LARGE}
@@ -155,6 +155,7 @@ def load_library(path: Path | str | None = None):
         "im_max_coverage": (st, [vp, ctypes.c_uint32, u32p, u64p]),
         "im_max_coverage_range": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, u32p, u64p]),
         "im_coverage_range": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint32, u64p]),
+        "im_coverage_range_noalloc": (st, [vp, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint32, u64p]),
         "im_estimate_inf": (st, [vp, ctypes.c_int, u32p, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_uint64, f64p, u64p]),
         "im_ssa": (st, [vp, ctypes.c_int, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
@@ -450,6 +451,15 @@ class Pool:
         s, sp = _u32(seeds)
         cov = ctypes.c_uint64()
         _check(load_library().im_coverage_range(self.h, begin, end, sp, s.shape[0], ctypes.byref(cov)))
+        return int(cov.value)
+
+    def coverage_noalloc(self, seeds, begin: int = 0, end: int | None = None) -> int:
+        """im_coverage_range_noalloc: the same count with the library's fixed
+        per-GPU scratch array instead of allocated buffers."""
+        end = self.count if end is None else end
+        s, sp = _u32(seeds)
+        cov = ctypes.c_uint64()
+        _check(load_library().im_coverage_range_noalloc(self.h, begin, end, sp, s.shape[0], ctypes.byref(cov)))
         return int(cov.value)
 
 

@@ -382,6 +382,7 @@ extern "C" im_status im_ctx_create(int device, void *stream, im_alloc_fn alloc, 
         return IM_E_ARG;
     }
     IM_HIP(hipSetDevice(device));
+    IM_TRY(noalloc_scratch_init(device));
     hipDeviceProp_t prop;
     IM_HIP(hipGetDeviceProperties(&prop, device));
     auto *c = new (std::nothrow) im_ctx();

@@ -12,6 +12,8 @@
 // the previous round's decrements landed; the first rounds (the largest
 // covers) run as grid-wide kernels, the rest in one persistent workgroup.
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "im_device.hpp"
@@ -2739,3 +2741,109 @@ im_status first_crossing_items(im_ctx *ctx, const CrossItem *items, uint32_t nit
 }
 }  // namespace im
 
+// ------------------------------------------- stare step, no allocation ----
+//
+// im_coverage_range_noalloc: the coverage count of im_coverage_range (Eq. 1,
+// the D-SSA stare step) for callers that cannot allocate device memory. Its
+// scratch (a counter, the bad-seed flag, the seed list and the seed bitmap)
+// is the file-scope array below instead of context buffers. Each GPU the
+// library runs on holds one copy of it until the process ends, and every
+// call on that GPU shares it. Host code never passes `scratch` itself to a
+// kernel or a copy: it uses the device address taken once per device by
+// noalloc_scratch_init.
+
+constexpr uint32_t kNaMaxN = 1u << 26;  // nodes: bitmap of 2^21 words (8 MiB)
+constexpr uint32_t kNaMaxK = 1u << 16;  // seeds
+constexpr size_t kNaHead = 256;         // u64 counter at 0, u32 bad-seed flag at 8
+constexpr size_t kNaSeedBytes = 4ull * kNaMaxK;
+constexpr size_t kNaBitBytes = 4ull * (kNaMaxN / 32);
+constexpr size_t kNaBytes = kNaHead + kNaSeedBytes + kNaBitBytes;
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+void *g_na_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+namespace im {
+
+im_status noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kNaMaxDevices) {
+        set_error("device %d beyond the %d the no-allocation scratch table covers", device, kNaMaxDevices);
+        return IM_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (g_na_ptr[device]) return IM_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+        set_error("hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+        return IM_E_DEVICE;
+    }
+    g_na_ptr[device] = ptr;
+    return IM_OK;
+}
+
+}  // namespace im
+
+extern "C" im_status im_coverage_range_noalloc(const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds,
+                                               uint32_t k, uint64_t *cov_out) {
+    using namespace im;
+    clear_error();
+    if (!p || !cov_out || (k && !seeds) || begin > end || end > p->count) {
+        set_error("im_coverage_range_noalloc: bad arguments");
+        return IM_E_ARG;
+    }
+    const uint32_t n = p->g->n;
+    if (n > kNaMaxN || k > kNaMaxK) {
+        set_error("im_coverage_range_noalloc: n = %u, k = %u beyond its fixed scratch (n <= %u, k <= %u)", n, k,
+                  kNaMaxN, kNaMaxK);
+        return IM_E_ARG;
+    }
+    im_ctx *ctx = p->ctx;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_na_mu);
+        if (ctx->device >= 0 && ctx->device < kNaMaxDevices) base = g_na_ptr[ctx->device];
+    }
+    if (!base) {
+        set_error("im_coverage_range_noalloc: no scratch address for device %d", ctx->device);
+        return IM_E_STATE;
+    }
+    char *b = static_cast<char *>(base);
+    auto *cnt = reinterpret_cast<unsigned long long *>(b);
+    auto *bad = reinterpret_cast<uint32_t *>(b + 8);
+    auto *dseeds = reinterpret_cast<uint32_t *>(b + kNaHead);
+    auto *bits = reinterpret_cast<uint32_t *>(b + kNaHead + kNaSeedBytes);
+    const uint64_t words = (uint64_t(n) + 31) / 32;
+    hipStream_t st = ctx->stream;
+    // the array keeps the last call's contents: clear what starts at zero
+    fill_u32_kernel<<<grid_of(words, kThreads, 1024), kThreads, 0, st>>>(bits, words, 0u);
+    fill_u64_kernel<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t *>(cnt), 1, 0);
+    fill_u32_kernel<<<1, 64, 0, st>>>(bad, 1, 0u);
+    IM_HIP(hipGetLastError());
+    // seeds go through the context's pinned host buffer, 1024 at a time
+    for (uint32_t off = 0; off < k; off += 1024) {
+        const uint32_t c = std::min<uint32_t>(1024, k - off);
+        std::memcpy(ctx->host_pinned, seeds + off, 4ull * c);
+        IM_HIP(hipMemcpyAsync(dseeds + off, ctx->host_pinned, 4ull * c, hipMemcpyHostToDevice, st));
+        IM_HIP(hipStreamSynchronize(st));
+    }
+    if (k) seed_bits_kernel<<<grid_of(k, kThreads, 64), kThreads, 0, st>>>(dseeds, k, bits, bad, n);
+    if (end > begin) {
+        coverage_kernel<<<grid_of((end - begin) * 16, kThreads, ctx->cu_count * 16), kThreads, 0, st>>>(
+            static_cast<const uint64_t *>(p->poff.ptr), static_cast<const uint32_t *>(p->pnodes.ptr), begin, end,
+            bits, cnt);
+    }
+    IM_HIP(hipGetLastError());
+    uint64_t head[2] = {0, 0};
+    IM_TRY(to_host_sync(ctx, head, b, 16));
+    if (static_cast<uint32_t>(head[1])) {
+        set_error("im_coverage_range_noalloc: seed id >= n");
+        return IM_E_ARG;
+    }
+    *cov_out = head[0];
+    return IM_OK;
+}

@@ -117,6 +117,12 @@ struct im_ctx {
 // Destroys the cached greedy round graphs of a context (cover.hip).
 void free_round_graphs(im_ctx *ctx);
 
+namespace im {
+// Takes the device address of the no-allocation scratch array on `device`
+// (current), once per device; called by im_ctx_create (cover.hip).
+im_status noalloc_scratch_init(int device);
+}  // namespace im
+
 struct im_graph {
     im_ctx *ctx = nullptr;
     uint32_t n = 0;
