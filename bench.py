@@ -67,12 +67,14 @@ def percentile(xs, q):
     return xs[i]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, steps: int | None = None, warmup: int | None = None):
     """HBM bytes per timed launch of `kernel` (for the IC sampler: its wave
     pass and both workgroup tiers) from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (scaled by a plain copy of known size), or None when the
     kernel's sources, or the query loop that sizes its launches, changed
-    since the counters were taken."""
+    since the counters were taken, or when the record names the bench's
+    --steps / --warmup (which fix the launches averaged) and this run's
+    differ."""
     import hashlib
 
     path = ROOT / "profiles" / "traffic.json"
@@ -80,6 +82,8 @@ def measured_traffic(kernel: str):
         return None
     rec = json.loads(path.read_text()).get(kernel)
     if rec is None:
+        return None
+    if ("steps" in rec and rec["steps"] != steps) or ("warmup" in rec and rec["warmup"] != warmup):
         return None
     h = hashlib.sha256()
     for src in rec["sources"]:
@@ -117,7 +121,8 @@ def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_bytes: int = 16 << 30,
     return out
 
 
-def roofline(kt: dict, model: int, traffic_measured_here: bool = False, traffic_key: str = "") -> dict:
+def roofline(kt: dict, model: int, traffic_measured_here: bool = False, traffic_key: str = "",
+             steps: int | None = None, warmup: int | None = None) -> dict:
     """Roofline of the main sampler kernel from its event timing: algorithmic
     bytes per launch over the mean launch duration, against HBM peak.
     `traffic` (HBM bytes per launch from the committed counter runs) is
@@ -135,7 +140,7 @@ def roofline(kt: dict, model: int, traffic_measured_here: bool = False, traffic_
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
     sec = kt["sample_ms"] * 1e-3
     key = traffic_key or ("lt_main_kernel" if model == 1 else "ic_sampler")
-    traffic = measured_traffic(key) if traffic_measured_here else None
+    traffic = measured_traffic(key, steps, warmup) if traffic_measured_here else None
     out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "launches": kt["sample_launches"],
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
@@ -461,7 +466,7 @@ def run_twitter(args, im, ctx, sync):
            "roofline": roofline(kt, 0, traffic_measured_here=(not args.engine and args.ks is None and not args.param
                                                               and not args.no_speculate
                                                               and args.greedy_wg_max_entries is None),
-                                traffic_key="ic_sampler_twitter")}
+                                traffic_key="ic_sampler_twitter", steps=args.steps, warmup=args.warmup)}
     if args.engine:
         out["config"]["workload"] += ", concurrent through the engine"
     if not args.no_batching_compare:

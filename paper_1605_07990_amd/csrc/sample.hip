@@ -475,6 +475,54 @@ constexpr uint32_t kLtMaxWalk = 640;  // longer walks take the long path (load <
 
 __device__ __forceinline__ uint32_t lt_bucket(uint32_t u) { return (u * 0x9E3779B1u) >> (32 - 7); }
 
+// The first kLtBloomMax nodes of a walk need no table: a 256-bit Bloom filter
+// in four registers per lane says whether a node may already be in the walk,
+// and only then are the walk's staged nodes (its first at most 64, 16 bytes
+// at a time, recently written) scanned for it. Nodes after those go to the
+// table as before, so a lookup checks the filter (and on a hit the staged
+// prefix) and, once the walk is longer, the table.
+constexpr uint32_t kLtBloomMax = 64;
+
+struct LtBloom {
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    __device__ __forceinline__ static uint32_t bit_of(uint32_t u) { return (u * 0x2545F491u) >> 24; }
+    __device__ __forceinline__ bool test(uint32_t b) const {
+        const uint32_t q = b >> 6;
+        const uint64_t w = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
+        return (w >> (b & 63u)) & 1ull;
+    }
+    __device__ __forceinline__ void set(uint32_t b) {
+        const uint64_t m = 1ull << (b & 63u);
+        const uint32_t q = b >> 6;
+        w0 |= q == 0 ? m : 0ull;
+        w1 |= q == 1 ? m : 0ull;
+        w2 |= q == 2 ? m : 0ull;
+        w3 |= q == 3 ? m : 0ull;
+    }
+    __device__ __forceinline__ void clear() { w0 = w1 = w2 = w3 = 0; }
+};
+
+// Whether u is among the first n (<= kLtBloomMax) staged nodes of a walk
+// (the region is 16-byte aligned; entries past n are ignored).
+__device__ __forceinline__ bool lt_in_prefix(const uint32_t *region, uint32_t n, uint32_t u) {
+    const uint4 *r4 = reinterpret_cast<const uint4 *>(region);
+    bool hit = false;
+    // four 16-byte loads in flight at a time
+#pragma unroll 1
+    for (uint32_t i0 = 0; i0 < n; i0 += 16) {
+        uint4 q[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) q[j] = (i0 + 4u * j < n) ? r4[i0 / 4 + j] : make_uint4(~u, ~u, ~u, ~u);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + 4u * j;
+            hit |= (q[j].x == u) | ((q[j].y == u) & (i + 1u < n)) | ((q[j].z == u) & (i + 2u < n)) |
+                   ((q[j].w == u) & (i + 3u < n));
+        }
+    }
+    return hit;
+}
+
 __device__ __forceinline__ uint64_t lt_entry(uint32_t stamp, uint32_t u) {
     return (static_cast<uint64_t>(stamp) << 32) | u;
 }
@@ -561,7 +609,7 @@ __device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint
 }
 
 template <int kMode>
-__global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tables, uint32_t stamp_base) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void lt_main_kernel(Params p, uint64_t *tables, uint32_t stamp_base) {
     const uint32_t lane = lane_id();
     uint64_t *table = tables + (static_cast<uint64_t>(blockIdx.x) * kWave + lane) * kLtTableSlots;
     Stream st(0);
@@ -576,6 +624,7 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
     uint32_t *region = nullptr;
     uint64_t edges_acc = 0, nodes_acc = 0;
     const uint32_t max_walk = min(kLtMaxWalk, p.lt_cap);
+    LtBloom bloom;
 
     for (;;) {
         const bool need = !active && !finished;
@@ -598,8 +647,8 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
                     region = p.stage + static_cast<uint64_t>(t) * p.lt_cap;
                     region[0] = v;
                     len = 1;
-                    // every entry is stale for a new stamp: the first slot is free
-                    table[lt_bucket(v) * kLtBucketSlots] = lt_entry(stamp, v);
+                    bloom.clear();
+                    bloom.set(LtBloom::bit_of(v));
                     a = p.off[v];
                     b = p.off[v + 1];
                     cv = lt_coin(st, s, v);
@@ -627,15 +676,28 @@ __global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tabl
         if (!stop) {
             na = p.off[u];
             nb = p.off[u + 1];
+            // the walk's first kLtBloomMax nodes are in the filter (and staged);
+            // later ones in the table
+            const uint32_t fb = LtBloom::bit_of(u);
+            const bool maybe = bloom.test(fb);
+            const bool tabled = len >= kLtBloomMax;
             const uint64_t want = lt_entry(stamp, u);
             uint32_t bi = lt_bucket(u);
-            const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
-            ulonglong2 q0 = bucket[0], q1 = bucket[1], q2 = bucket[2], q3 = bucket[3];
+            ulonglong2 q0{}, q1{}, q2{}, q3{};
+            if (tabled) {
+                const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+                q0 = bucket[0];
+                q1 = bucket[1];
+                q2 = bucket[2];
+                q3 = bucket[3];
+            }
             cv = lt_coin(st, s, u);  // the next step's coin, while the loads above are in flight
-            asm volatile("" : "+v"(cv));  // keeps it here rather than after the probe
-            for (uint32_t probe = 0; probe < kLtBuckets; ++probe) {
+            asm volatile("" : "+v"(cv));  // keeps it here rather than after the checks
+            if (maybe && lt_in_prefix(region, min(len, kLtBloomMax), u)) stop = true;  // the walk closed a cycle
+            if (!stop && !tabled) bloom.set(fb);
+            for (uint32_t probe = 0; !stop && tabled && probe < kLtBuckets; ++probe) {
                 if (probe) {
-                    bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+                    const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
                     q0 = bucket[0];
                     q1 = bucket[1];
                     q2 = bucket[2];
