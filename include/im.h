@@ -342,9 +342,10 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       65536, i.e. n above 4,194,304);
  *   IM_PARAM_GREEDY_COVER_BLOCKS    workgroups per job that cover a round's
  *       seed, 1..65535, or 0 for the automatic choice (default 0);
- *   IM_PARAM_IC_EDGE_BUDGET         in-edges an IC sample may examine in the
- *       one-wave pass before it is handed to the workgroup tiers,
- *       64..2^31 (default 16384);
+ *   IM_PARAM_IC_EDGE_BUDGET         the most in-edges an IC sample may examine
+ *       in the one-wave pass: a sample whose next frontier batch would take
+ *       it past this is handed to the workgroup tiers before that batch is
+ *       expanded, 64..2^31 (default 16384);
  *   IM_PARAM_GREEDY_CANDIDATES      grid-wide Max-Coverage of one range
  *       (im_max_coverage*, im_ssa*, im_dssa, im_ris) keeps this many 64-node
  *       chunks as candidates, 1..64, together with a bound on every key

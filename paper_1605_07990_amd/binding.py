@@ -116,7 +116,9 @@ def _no_torch() -> bool:
 
 
 def load_library(path: Path | str | None = None):
-    """Load libim.so and declare every entry point's signature."""
+    """Load libim.so (or the library at `path`), declare every entry point's
+    signature, and make it the library every later call of the binding
+    uses."""
     global _lib
     if _lib is not None and path is None:
         return _lib
@@ -188,8 +190,7 @@ def load_library(path: Path | str | None = None):
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    if path is None:
-        _lib = lib
+    _lib = lib
     return lib
 
 
@@ -292,10 +293,11 @@ class Context:
             lib.im_ctx_free(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit torch may already be gone: the allocator hooks
         # must not be called then, so the memory is left to the process exit
-        if sys.is_finalizing():
+        # (the check is bound at definition: module globals may be gone then)
+        if _finalizing():
             return
         try:
             self.close()
@@ -333,8 +335,8 @@ class Graph:
         if getattr(self, "h", None):
             self.ctx._release(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # bound at definition: module globals may be gone at exit
             return
         try:
             self.close()
@@ -388,8 +390,8 @@ class Pool:
         if getattr(self, "h", None):
             self.graph.ctx._release(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # bound at definition: module globals may be gone at exit
             return
         try:
             self.close()
@@ -523,8 +525,8 @@ class Engine:
             self.ctx._release(self)
             self._graphs.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # bound at definition: module globals may be gone at exit
             return
         try:
             self.close()

@@ -586,7 +586,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     if (c->ev_group) (void)hipEventDestroy(c->ev_group);
     free_round_graphs(c);
-    for (DevBuf *b : {&c->stage, &c->sample_meta, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits, &c->flat,
+    for (DevBuf *b : {&c->stage, &c->sample_meta, &c->handoff, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits, &c->flat,
                       &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);

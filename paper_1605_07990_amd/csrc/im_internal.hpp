@@ -57,6 +57,7 @@ struct im_ctx {
     // Reusable work buffers, grown on demand and kept for the context's life.
     DevBuf stage;        // sampler staging: RR sets before compaction
     DevBuf sample_meta;  // per-sample size / staging offset / hit flags
+    DevBuf handoff;      // IC search states handed from one sampler tier to the next
     DevBuf counters;     // small device counters (tickets, cursors, flags)
     DevBuf scan_tmp;     // scan partials
     DevBuf slots;        // long-path visited stamps + queues

@@ -53,6 +53,24 @@ struct GrpLarge {
     static constexpr uint32_t kHbits = 14;  // 16384
 };
 
+// Hand-over records (IC): a sample the wave pass hands to the small tier, or
+// the small tier to the large one, carries its search state, and the next
+// tier resumes it instead of starting over. A record is a header [t, head,
+// tail, edges low, edges high, 0, 0, 0] and queue[0, tail): the state at the
+// start of the frontier batch that was not finished, so every node reached
+// before that batch is queued and the first `head` of them are expanded (the
+// set reached does not depend on the order of expansion). Samples handed on
+// past the records available start over, as does the long path.
+constexpr uint32_t kHoHdr = 8;
+constexpr uint32_t kHoStrideWave = kHoHdr + kIcQcap;
+constexpr uint32_t kHoStrideSmall = kHoHdr + GrpSmall::kQcap;
+constexpr uint32_t kHoMaxWave = 1u << 16;  // records per launch
+constexpr uint32_t kHoMaxSmall = 1u << 14;
+static_assert(kIcQcap <= GrpSmall::kQcap && GrpSmall::kQcap <= GrpLarge::kQcap,
+              "a tier must hold the queue of the tier before it");
+static_assert((1u << GrpSmall::kHbits) >= 2 * kIcQcap && (1u << GrpLarge::kHbits) >= 2 * GrpSmall::kQcap,
+              "a resumed queue must fit a tier's visited set");
+
 struct Counters {
     uint32_t ticket;        // next sample of the main pass
     uint32_t defer_count;   // samples handed on by the main pass (IC: to the workgroup tier; LT: to the long path)
@@ -102,8 +120,12 @@ struct Params {
     uint8_t *z;           // per sample (hits mode)
     uint32_t lt_cap;
     uint32_t ticket_block;  // IC: consecutive samples a wave takes per ticket
-    uint32_t edge_budget;   // IC: edges a wave examines before a workgroup takes the sample over
+    uint32_t edge_budget;   // IC: the most in-edges a wave examines for one sample; larger ones go to a workgroup
     uint32_t plain;         // IC: 1 = static assignment (wave w takes samples w, w + W, ...), no tickets
+    uint32_t *ho_wave;      // IC: hand-over records of the wave pass (kHoStrideWave words each)
+    uint32_t *ho_small;     // IC: hand-over records of the small workgroup tier (kHoStrideSmall words each)
+    uint32_t ho_wave_cap;   // records available in each (0: none)
+    uint32_t ho_small_cap;
 };
 
 // The work item owning global slot t.
@@ -345,11 +367,14 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
         wave_sync();
 
         bool heavy = false;
+        // the state at the start of the current frontier batch (what a
+        // hand-over record carries)
+        uint32_t hb = 0, tb = 1;
+        uint64_t eb = 0;
         while (head < tail && !hit) {
-            if (sample_edges >= p.edge_budget) {  // a workgroup finishes it
-                heavy = true;
-                break;
-            }
+            hb = head;
+            tb = tail;
+            eb = sample_edges;
             const uint32_t nb = min(tail - head, static_cast<uint32_t>(kWave));
             uint32_t cg = 0;
             uint64_t a = 0, b = 0;
@@ -359,9 +384,18 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                 b = p.off[v + 1];
                 if (b > a) cg = static_cast<uint32_t>(((b - 1) >> 2) - (a >> 2) + 1);
             }
+            const uint64_t batch_edges = wave_sum_u64(b - a);
+            // a workgroup finishes a sample that would examine more in-edges
+            // than the budget; checked before the batch is expanded, so that
+            // a batch holding a high in-degree node (hundreds of thousands of
+            // in-edges on a power-law graph) is never expanded here first
+            if (sample_edges + batch_edges > p.edge_budget) {
+                heavy = true;
+                break;
+            }
+            sample_edges += batch_edges;
             const uint32_t inc = wave_inclusive_scan(cg);
             const uint32_t groups = __shfl(inc, kWave - 1, kWave);
-            sample_edges += wave_sum_u64(b - a);
             pre[lane] = inc - cg;
             fa[lane] = a;
             fb[lane] = b;
@@ -422,9 +456,22 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
 
         const bool overflow = (tail > kIcQcap) || (__ballot(full) != 0) || heavy;
         if (overflow && !hit) {
+            uint32_t d = 0;
             if (lane == 0) {
-                const uint32_t d = atomicAdd(&p.cnt->defer_count, 1u);
+                d = atomicAdd(&p.cnt->defer_count, 1u);
                 p.defer_list[d] = t;
+            }
+            d = __shfl(d, 0, kWave);
+            if (d < p.ho_wave_cap) {  // queue[0, tb) is untouched by the unfinished batch
+                uint32_t *rec = p.ho_wave + static_cast<uint64_t>(d) * kHoStrideWave;
+                for (uint32_t i = lane; i < tb; i += kWave) rec[kHoHdr + i] = queue[i];
+                if (lane == 0) {
+                    rec[0] = t;
+                    rec[1] = hb;
+                    rec[2] = tb;
+                    rec[3] = static_cast<uint32_t>(eb);
+                    rec[4] = static_cast<uint32_t>(eb >> 32);
+                }
             }
         } else if (kMode == 1) {
             if (lane == 0) p.z[t] = hit ? 1 : 0;
@@ -474,54 +521,6 @@ constexpr uint32_t kLtTableSlots = kLtBuckets * kLtBucketSlots;
 constexpr uint32_t kLtMaxWalk = 640;  // longer walks take the long path (load <= 5/8)
 
 __device__ __forceinline__ uint32_t lt_bucket(uint32_t u) { return (u * 0x9E3779B1u) >> (32 - 7); }
-
-// The first kLtBloomMax nodes of a walk need no table: a 256-bit Bloom filter
-// in four registers per lane says whether a node may already be in the walk,
-// and only then are the walk's staged nodes (its first at most 64, 16 bytes
-// at a time, recently written) scanned for it. Nodes after those go to the
-// table as before, so a lookup checks the filter (and on a hit the staged
-// prefix) and, once the walk is longer, the table.
-constexpr uint32_t kLtBloomMax = 64;
-
-struct LtBloom {
-    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-    __device__ __forceinline__ static uint32_t bit_of(uint32_t u) { return (u * 0x2545F491u) >> 24; }
-    __device__ __forceinline__ bool test(uint32_t b) const {
-        const uint32_t q = b >> 6;
-        const uint64_t w = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
-        return (w >> (b & 63u)) & 1ull;
-    }
-    __device__ __forceinline__ void set(uint32_t b) {
-        const uint64_t m = 1ull << (b & 63u);
-        const uint32_t q = b >> 6;
-        w0 |= q == 0 ? m : 0ull;
-        w1 |= q == 1 ? m : 0ull;
-        w2 |= q == 2 ? m : 0ull;
-        w3 |= q == 3 ? m : 0ull;
-    }
-    __device__ __forceinline__ void clear() { w0 = w1 = w2 = w3 = 0; }
-};
-
-// Whether u is among the first n (<= kLtBloomMax) staged nodes of a walk
-// (the region is 16-byte aligned; entries past n are ignored).
-__device__ __forceinline__ bool lt_in_prefix(const uint32_t *region, uint32_t n, uint32_t u) {
-    const uint4 *r4 = reinterpret_cast<const uint4 *>(region);
-    bool hit = false;
-    // four 16-byte loads in flight at a time
-#pragma unroll 1
-    for (uint32_t i0 = 0; i0 < n; i0 += 16) {
-        uint4 q[4];
-#pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) q[j] = (i0 + 4u * j < n) ? r4[i0 / 4 + j] : make_uint4(~u, ~u, ~u, ~u);
-#pragma unroll
-        for (uint32_t j = 0; j < 4; ++j) {
-            const uint32_t i = i0 + 4u * j;
-            hit |= (q[j].x == u) | ((q[j].y == u) & (i + 1u < n)) | ((q[j].z == u) & (i + 2u < n)) |
-                   ((q[j].w == u) & (i + 3u < n));
-        }
-    }
-    return hit;
-}
 
 __device__ __forceinline__ uint64_t lt_entry(uint32_t stamp, uint32_t u) {
     return (static_cast<uint64_t>(stamp) << 32) | u;
@@ -609,7 +608,7 @@ __device__ __forceinline__ uint64_t lt_pick(const uint2 *edges, uint64_t a, uint
 }
 
 template <int kMode>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void lt_main_kernel(Params p, uint64_t *tables, uint32_t stamp_base) {
+__global__ __launch_bounds__(kWave) void lt_main_kernel(Params p, uint64_t *tables, uint32_t stamp_base) {
     const uint32_t lane = lane_id();
     uint64_t *table = tables + (static_cast<uint64_t>(blockIdx.x) * kWave + lane) * kLtTableSlots;
     Stream st(0);
@@ -624,7 +623,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
     uint32_t *region = nullptr;
     uint64_t edges_acc = 0, nodes_acc = 0;
     const uint32_t max_walk = min(kLtMaxWalk, p.lt_cap);
-    LtBloom bloom;
 
     for (;;) {
         const bool need = !active && !finished;
@@ -647,8 +645,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
                     region = p.stage + static_cast<uint64_t>(t) * p.lt_cap;
                     region[0] = v;
                     len = 1;
-                    bloom.clear();
-                    bloom.set(LtBloom::bit_of(v));
+                    // every entry is stale for a new stamp: the first slot is free
+                    table[lt_bucket(v) * kLtBucketSlots] = lt_entry(stamp, v);
                     a = p.off[v];
                     b = p.off[v + 1];
                     cv = lt_coin(st, s, v);
@@ -676,28 +674,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
         if (!stop) {
             na = p.off[u];
             nb = p.off[u + 1];
-            // the walk's first kLtBloomMax nodes are in the filter (and staged);
-            // later ones in the table
-            const uint32_t fb = LtBloom::bit_of(u);
-            const bool maybe = bloom.test(fb);
-            const bool tabled = len >= kLtBloomMax;
             const uint64_t want = lt_entry(stamp, u);
             uint32_t bi = lt_bucket(u);
-            ulonglong2 q0{}, q1{}, q2{}, q3{};
-            if (tabled) {
-                const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
-                q0 = bucket[0];
-                q1 = bucket[1];
-                q2 = bucket[2];
-                q3 = bucket[3];
-            }
+            const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+            ulonglong2 q0 = bucket[0], q1 = bucket[1], q2 = bucket[2], q3 = bucket[3];
             cv = lt_coin(st, s, u);  // the next step's coin, while the loads above are in flight
-            asm volatile("" : "+v"(cv));  // keeps it here rather than after the checks
-            if (maybe && lt_in_prefix(region, min(len, kLtBloomMax), u)) stop = true;  // the walk closed a cycle
-            if (!stop && !tabled) bloom.set(fb);
-            for (uint32_t probe = 0; !stop && tabled && probe < kLtBuckets; ++probe) {
+            asm volatile("" : "+v"(cv));  // keeps it here rather than after the probe
+            for (uint32_t probe = 0; probe < kLtBuckets; ++probe) {
                 if (probe) {
-                    const ulonglong2 *bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
+                    bucket = reinterpret_cast<const ulonglong2 *>(table + bi * kLtBucketSlots);
                     q0 = bucket[0];
                     q1 = bucket[1];
                     q2 = bucket[2];
@@ -782,12 +767,17 @@ __device__ __forceinline__ bool grp_insert(uint32_t *vis, uint32_t u, bool &full
 
 // IC samples handed on by the previous tier, one workgroup per sample: each
 // level's frontier (up to kThreads nodes at a time) is laid out by a block
-// scan of its aligned 4-edge groups, which all threads then expand. Samples
-// too large for this tier's LDS go on to the next tier's list.
+// scan of its aligned 4-edge groups, which all threads then expand. A sample
+// with a hand-over record (in_rec, in_stride words each, the first in_cap of
+// the list) resumes from it. Samples too large for this tier's LDS go on to
+// the next tier's list, with a record of their own when out_cap allows.
 template <int kMode, typename Tier>
 __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, const uint32_t *in_list,
                                                                   const uint32_t *in_count, uint32_t *in_ticket,
-                                                                  uint32_t *out_list, uint32_t *out_count) {
+                                                                  uint32_t *out_list, uint32_t *out_count,
+                                                                  const uint32_t *in_rec, uint32_t in_stride,
+                                                                  uint32_t in_cap, uint32_t *out_rec,
+                                                                  uint32_t out_stride, uint32_t out_cap) {
     constexpr int kGrpThreads = Tier::kThreads;
     constexpr uint32_t kGrpQcap = Tier::kQcap;
     constexpr uint32_t kGrpHbits = Tier::kHbits;
@@ -799,7 +789,7 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
     __shared__ uint64_t s_b[kGrpThreads];
     __shared__ uint64_t s_scan[kGrpThreads / kWave];
     __shared__ unsigned long long s_edges;
-    __shared__ uint32_t s_t, s_tail, s_flags;  // flags: 1 hit, 2 too large
+    __shared__ uint32_t s_t, s_d, s_tail, s_flags;  // flags: 1 hit, 2 too large
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < kGrpHcap; i += blockDim.x) s_vis[i] = 0u;
     __syncthreads();
@@ -807,15 +797,34 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
         if (tid == 0) {
             const uint32_t d = atomicAdd(in_ticket, 1u);
             s_t = d < *in_count ? in_list[d] : 0xFFFFFFFFu;
+            s_d = d;
         }
         __syncthreads();
         const uint32_t t = s_t;
         if (t == 0xFFFFFFFFu) break;
+        const uint32_t d = s_d;
         const WorkItem &it = item_of(p, t);
         const Stream st(it.key);
         const uint32_t *seedbits = it.seedbits;
         const uint64_t s = it.s0 + (t - it.start);
-        if (tid == 0) {
+        uint32_t head = 0, levels = 0;
+        // the sender's record, when it left one for this sample (its
+        // queue holds no seed: a hit would have ended the sample there)
+        const uint32_t *rec = (d < in_cap) ? in_rec + static_cast<uint64_t>(d) * in_stride : nullptr;
+        const bool resume = rec != nullptr && rec[0] == t && rec[2] <= kGrpQcap && rec[1] < rec[2];
+        if (resume) {
+            const uint32_t rt = rec[2];
+            head = rec[1];
+            for (uint32_t i = tid; i < rt; i += blockDim.x) s_queue[i] = rec[kHoHdr + i];
+            if (tid == 0) {
+                s_tail = rt;
+                s_flags = 0u;
+                s_edges = static_cast<unsigned long long>(rec[3]) | (static_cast<unsigned long long>(rec[4]) << 32);
+            }
+            __syncthreads();
+            bool full = false;  // cannot fill: the set is at least twice the largest record
+            for (uint32_t i = tid; i < rt; i += blockDim.x) grp_insert<kGrpHbits>(s_vis, s_queue[i], full);
+        } else if (tid == 0) {
             const uint32_t v0 = pick_source(st, s, p.src_cum, p.n);
             bool full = false;
             grp_insert<kGrpHbits>(s_vis, v0, full);
@@ -825,10 +834,16 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
             s_edges = 0;
         }
         __syncthreads();
-        uint32_t head = 0, levels = 0;
+        // the state at the start of the current frontier batch (what a
+        // hand-over record carries)
+        uint32_t hb = head, tb = 0;
+        uint64_t eb = 0;
         for (;;) {
             const uint32_t tail = s_tail;
             if (head >= tail || s_flags != 0u) break;
+            hb = head;
+            tb = tail;
+            eb = s_edges;  // this batch's edges are added after the scan's barriers
             ++levels;
             const uint32_t nb = min(tail - head, static_cast<uint32_t>(kGrpThreads));
             uint64_t a = 0, b = 0, cg = 0;
@@ -839,9 +854,10 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
                 if (b > a) cg = ((b - 1) >> 2) - (a >> 2) + 1;
             }
             const uint64_t de = b - a;
-            if (de) atomicAdd(&s_edges, static_cast<unsigned long long>(de));
             uint64_t groups = 0;
             const uint64_t pre = block_scan_excl(cg, s_scan, groups);
+            // after the scan's barriers: every thread has read s_edges above
+            if (de) atomicAdd(&s_edges, static_cast<unsigned long long>(de));
             s_pre[tid] = pre;
             s_a[tid] = a;
             s_b[tid] = b;
@@ -885,8 +901,22 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
         }
         if ((flags & 2u) && !(flags & 1u)) {
             if (tid == 0) {
-                const uint32_t d = atomicAdd(out_count, 1u);
-                out_list[d] = t;
+                const uint32_t d2 = atomicAdd(out_count, 1u);
+                out_list[d2] = t;
+                s_d = d2;
+            }
+            __syncthreads();
+            const uint32_t d2 = s_d;
+            if (d2 < out_cap) {  // s_queue[0, tb) is untouched by the unfinished batch
+                uint32_t *orec = out_rec + static_cast<uint64_t>(d2) * out_stride;
+                for (uint32_t i = tid; i < tb; i += blockDim.x) orec[kHoHdr + i] = s_queue[i];
+                if (tid == 0) {
+                    orec[0] = t;
+                    orec[1] = hb;
+                    orec[2] = tb;
+                    orec[3] = static_cast<uint32_t>(eb);
+                    orec[4] = static_cast<uint32_t>(eb >> 32);
+                }
             }
         } else if (kMode == 1) {
             if (tid == 0) {
@@ -1328,6 +1358,14 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         ctx->lt_stamp = 1;
     }
     Meta meta = meta_view(ctx, count);
+    // hand-over records between the IC tiers (plain launches have no tiers)
+    uint32_t ho_wave_cap = 0, ho_small_cap = 0;
+    if (model == IM_IC && !ctx->ic_plain) {
+        ho_wave_cap = static_cast<uint32_t>(std::min<uint64_t>(count, kHoMaxWave));
+        ho_small_cap = static_cast<uint32_t>(std::min<uint64_t>(count, kHoMaxSmall));
+        IM_TRY(dev_reserve(ctx, ctx->handoff,
+                           (uint64_t(ho_wave_cap) * kHoStrideWave + uint64_t(ho_small_cap) * kHoStrideSmall) * 4 + 256));
+    }
     auto *cnt = static_cast<Counters *>(ctx->counters.ptr);
     // device work queue: items, then their accumulators
     auto *ditems = static_cast<WorkItem *>(ctx->items.ptr);
@@ -1385,6 +1423,10 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         const bool plain = model == IM_IC && ctx->ic_plain;
         p.plain = plain ? 1u : 0u;
         if (plain) p.edge_budget = 0xFFFFFFFFu;
+        p.ho_wave = ho_wave_cap ? static_cast<uint32_t *>(ctx->handoff.ptr) : nullptr;
+        p.ho_small = ho_small_cap ? p.ho_wave + uint64_t(ho_wave_cap) * kHoStrideWave : nullptr;
+        p.ho_wave_cap = ho_wave_cap;
+        p.ho_small_cap = ho_small_cap;
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);
         zero_u64_kernel<<<1, 256, 0, st>>>(reinterpret_cast<uint64_t *>(dacc), 2ull * nitems);
@@ -1426,14 +1468,18 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
             Counters *c = cnt;
             if (mode == SampleMode::Pool) {
                 ic_group_kernel<0, GrpSmall><<<cu * 5, GrpSmall::kThreads, 0, st>>>(
-                    p, p.defer_list, &c->defer_count, &c->defer_ticket, p.large_list, &c->large_count);
+                    p, p.defer_list, &c->defer_count, &c->defer_ticket, p.large_list, &c->large_count, p.ho_wave,
+                    kHoStrideWave, p.ho_wave_cap, p.ho_small, kHoStrideSmall, p.ho_small_cap);
                 ic_group_kernel<0, GrpLarge><<<cu, GrpLarge::kThreads, 0, st>>>(
-                    p, p.large_list, &c->large_count, &c->large_ticket, p.long_list, &c->long_count);
+                    p, p.large_list, &c->large_count, &c->large_ticket, p.long_list, &c->long_count, p.ho_small,
+                    kHoStrideSmall, p.ho_small_cap, nullptr, 0, 0);
             } else {
                 ic_group_kernel<1, GrpSmall><<<cu * 5, GrpSmall::kThreads, 0, st>>>(
-                    p, p.defer_list, &c->defer_count, &c->defer_ticket, p.large_list, &c->large_count);
+                    p, p.defer_list, &c->defer_count, &c->defer_ticket, p.large_list, &c->large_count, p.ho_wave,
+                    kHoStrideWave, p.ho_wave_cap, p.ho_small, kHoStrideSmall, p.ho_small_cap);
                 ic_group_kernel<1, GrpLarge><<<cu, GrpLarge::kThreads, 0, st>>>(
-                    p, p.large_list, &c->large_count, &c->large_ticket, p.long_list, &c->long_count);
+                    p, p.large_list, &c->large_count, &c->large_ticket, p.long_list, &c->long_count, p.ho_small,
+                    kHoStrideSmall, p.ho_small_cap, nullptr, 0, 0);
             }
             if (ctx->timing) IM_HIP(hipEventRecord(ctx->ev_group, st));
         }
