@@ -129,6 +129,36 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
     return x;
 }
 
+// The same inclusive prefix sum with DPP row shifts inside each row of 16
+// lanes, each row then adding the totals of the rows before it (read with
+// v_readlane): VALU latency only, where every __shfl above is an LDS
+// permute and a wait. Call it with every lane of the wave active.
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xF, 0xF, false));  // row_shr:1
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xF, 0xF, false));  // row_shr:2
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xF, 0xF, false));  // row_shr:4
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xF, 0xF, false));  // row_shr:8
+    const uint32_t r0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 15));
+    const uint32_t r1 = r0 + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 31));
+    const uint32_t r2 = r1 + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 47));
+    const uint32_t row = lane_id() >> 4;
+    return x + (row == 0 ? 0u : row == 1 ? r0 : row == 2 ? r1 : r2);
+}
+
+// The wave's total from an inclusive scan (its last lane).
+__device__ __forceinline__ uint32_t wave_scan_total(uint32_t inc) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(inc), kWave - 1));
+}
+
+// Sum of a wave's 64-bit values: the DPP scan when every value is below
+// 2^24 (the sum then fits 32 bits), else the shuffle reduction.
+__device__ __forceinline__ uint64_t wave_sum_small_u64(uint64_t x) {
+    if (__ballot(x >= (1ull << 24)) == 0) return wave_scan_total(wave_scan_u32(static_cast<uint32_t>(x)));
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
@@ -152,10 +182,14 @@ __device__ __forceinline__ uint64_t block_scan_excl(uint64_t x, uint64_t *smem, 
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x / kWave;
     uint64_t inc = x;
+    if (__ballot(x >= (1ull << 26)) == 0) {  // the wave's sum fits 32 bits: the DPP scan
+        inc = wave_scan_u32(static_cast<uint32_t>(x));
+    } else {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint64_t y = __shfl_up(inc, d, kWave);
-        if (lane >= static_cast<uint32_t>(d)) inc += y;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint64_t y = __shfl_up(inc, d, kWave);
+            if (lane >= static_cast<uint32_t>(d)) inc += y;
+        }
     }
     if (lane == kWave - 1) smem[wave] = inc;
     __syncthreads();

@@ -277,6 +277,38 @@ __device__ __forceinline__ bool vis_insert(uint32_t *vis, uint32_t u, bool &full
     }
 }
 
+// vis_insert in two steps, so that a lane's first probes of several nodes
+// are in flight together: vis_probe makes the first attempt (the old word),
+// vis_settle decides from it and, on a slot held by another node, probes on.
+template <bool kBitmap>
+__device__ __forceinline__ uint32_t vis_probe(uint32_t *vis, uint32_t u) {
+    if constexpr (kBitmap) {
+        return atomicOr(&vis[u >> 5], 1u << (u & 31u));
+    } else {
+        return atomicCAS(&vis[(u * 2654435761u) >> (32 - kIcHbits)], 0u, u + 1u);
+    }
+}
+
+template <bool kBitmap>
+__device__ __forceinline__ bool vis_settle(uint32_t *vis, uint32_t u, uint32_t old, bool &full) {
+    if constexpr (kBitmap) {
+        return !(old & (1u << (u & 31u)));
+    } else {
+        const uint32_t key = u + 1u;
+        if (old == 0u) return true;
+        if (old == key) return false;
+        uint32_t h = (u * 2654435761u) >> (32 - kIcHbits);
+        for (uint32_t probe = 1; probe < kIcHcap; ++probe) {
+            h = (h + 1u) & (kIcHcap - 1u);
+            const uint32_t o = atomicCAS(&vis[h], 0u, key);
+            if (o == 0u) return true;
+            if (o == key) return false;
+        }
+        full = true;
+        return false;
+    }
+}
+
 template <bool kBitmap>
 __device__ __forceinline__ uint32_t vis_slot(const uint32_t *vis, uint32_t u) {
     if constexpr (kBitmap) {
@@ -384,7 +416,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                 b = p.off[v + 1];
                 if (b > a) cg = static_cast<uint32_t>(((b - 1) >> 2) - (a >> 2) + 1);
             }
-            const uint64_t batch_edges = wave_sum_u64(b - a);
+            const uint64_t batch_edges = wave_sum_small_u64(b - a);
             // a workgroup finishes a sample that would examine more in-edges
             // than the budget; checked before the batch is expanded, so that
             // a batch holding a high in-degree node (hundreds of thousands of
@@ -394,8 +426,8 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                 break;
             }
             sample_edges += batch_edges;
-            const uint32_t inc = wave_inclusive_scan(cg);
-            const uint32_t groups = __shfl(inc, kWave - 1, kWave);
+            const uint32_t inc = wave_scan_u32(cg);
+            const uint32_t groups = wave_scan_total(inc);
             pre[lane] = inc - cg;
             fa[lane] = a;
             fb[lane] = b;
@@ -420,9 +452,14 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                     uint2 rec[4];
                     bool live[4];
                     ic_group_live(p.edges, g, ea, eb, coins, rec, live);
+                    // the first probes of the four records go out together;
+                    // a probe that meets another node goes on alone
+                    uint32_t old[4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) old[q] = live[q] ? vis_probe<kBitmap>(vis, rec[q].x) : 0u;
 #pragma unroll
                     for (uint32_t q = 0; q < 4; ++q) {
-                        if (live[q] && vis_insert<kBitmap>(vis, rec[q].x, full)) {
+                        if (live[q] && vis_settle<kBitmap>(vis, rec[q].x, old[q], full)) {
                             if (q == 0) f0 = rec[q].x;
                             else if (q == 1) f1 = rec[q].x;
                             else if (q == 2) f2 = rec[q].x;
@@ -765,6 +802,30 @@ __device__ __forceinline__ bool grp_insert(uint32_t *vis, uint32_t u, bool &full
     return false;
 }
 
+// grp_insert in two steps (as vis_probe / vis_settle): the first attempt,
+// then the decision from its old word, probing on past another node.
+template <uint32_t kHbits>
+__device__ __forceinline__ uint32_t grp_probe(uint32_t *vis, uint32_t u) {
+    return atomicCAS(&vis[(u * 2654435761u) >> (32 - kHbits)], 0u, u + 1u);
+}
+
+template <uint32_t kHbits>
+__device__ __forceinline__ bool grp_settle(uint32_t *vis, uint32_t u, uint32_t old, bool &full) {
+    constexpr uint32_t kHcap = 1u << kHbits;
+    const uint32_t key = u + 1u;
+    if (old == 0u) return true;
+    if (old == key) return false;
+    uint32_t h = (u * 2654435761u) >> (32 - kHbits);
+    for (uint32_t probe = 1; probe < kHcap; ++probe) {
+        h = (h + 1u) & (kHcap - 1u);
+        const uint32_t o = atomicCAS(&vis[h], 0u, key);
+        if (o == 0u) return true;
+        if (o == key) return false;
+    }
+    full = true;
+    return false;
+}
+
 // IC samples handed on by the previous tier, one workgroup per sample: each
 // level's frontier (up to kThreads nodes at a time) is laid out by a block
 // scan of its aligned 4-edge groups, which all threads then expand. A sample
@@ -878,13 +939,23 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
                 uint2 rec[4];
                 bool live[4];
                 ic_group_live(p.edges, g, ea, eb, coins, rec, live);
+                uint32_t old[4];
 #pragma unroll
-                for (uint32_t q = 0; q < 4; ++q) {
-                    if (live[q] && grp_insert<kGrpHbits>(s_vis, rec[q].x, full)) {
-                        const uint32_t pos = atomicAdd(&s_tail, 1u);
-                        if (pos < kGrpQcap) s_queue[pos] = rec[q].x;
-                        else atomicOr(&s_flags, 2u);
-                        if (kMode == 1 && test_bit(seedbits, rec[q].x)) atomicOr(&s_flags, 1u);
+                for (uint32_t q = 0; q < 4; ++q) old[q] = live[q] ? grp_probe<kGrpHbits>(s_vis, rec[q].x) : 0u;
+                uint32_t fresh = 0;  // bit q: record q reached a new node
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q)
+                    if (live[q] && grp_settle<kGrpHbits>(s_vis, rec[q].x, old[q], full)) fresh |= 1u << q;
+                if (fresh) {  // one queue reservation for the thread's new nodes
+                    uint32_t pos = atomicAdd(&s_tail, static_cast<uint32_t>(__popc(fresh)));
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) {
+                        if (fresh & (1u << q)) {
+                            if (pos < kGrpQcap) s_queue[pos] = rec[q].x;
+                            else atomicOr(&s_flags, 2u);
+                            if (kMode == 1 && test_bit(seedbits, rec[q].x)) atomicOr(&s_flags, 1u);
+                            ++pos;
+                        }
                     }
                 }
                 if (full) atomicOr(&s_flags, 2u);
