@@ -63,10 +63,16 @@ __global__ void offsets_kernel(const uint32_t *dst, uint64_t m, uint32_t n, uint
     }
 }
 
+// IC records {src, threshold}, padded with zero records to whole aligned
+// 4-edge groups (a sampler lane reads a group's 32 bytes with two 16-byte
+// loads; the pad is never live: it lies past every node's in-edge range).
+__host__ __device__ inline uint64_t ic_records(uint64_t m) { return ((m + 3) & ~3ull) + 4; }
+
 __global__ void ic_edges_kernel(const uint32_t *src, const float *w, uint64_t m, uint2 *edges) {
-    for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < m;
+    const uint64_t total = ic_records(m);
+    for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        edges[e] = make_uint2(src[e], to_threshold(static_cast<double>(w[e])));
+        edges[e] = e < m ? make_uint2(src[e], to_threshold(static_cast<double>(w[e]))) : make_uint2(0u, 0u);
     }
 }
 
@@ -156,7 +162,7 @@ im_status graph_build(im_graph *g, const uint32_t *src_h, const uint32_t *dst_h,
     if ((rc = dev_alloc(ctx, d_src, mb * 4)) || (rc = dev_alloc(ctx, d_dst, mb * 4)) ||
         (w_ic_h && (rc = dev_alloc(ctx, d_wic, mb * 4))) || (w_lt_h && (rc = dev_alloc(ctx, d_wlt, mb * 4))) ||
         (rc = dev_alloc(ctx, d_cnt, sizeof(BuildCounters))) || (rc = dev_alloc(ctx, g->off, (size_t(n) + 1) * 8)) ||
-        (w_ic_h && (rc = dev_alloc(ctx, g->edges_ic, mb * 8))) ||
+        (w_ic_h && (rc = dev_alloc(ctx, g->edges_ic, ic_records(m) * 8))) ||
         (w_lt_h && (rc = dev_alloc(ctx, g->edges_lt, mb * 8)))) {
         cleanup();
         return rc;
@@ -194,7 +200,7 @@ im_status graph_build(im_graph *g, const uint32_t *src_h, const uint32_t *dst_h,
         return IM_E_ARG;
     }
     offsets_kernel<<<grid_for(m + 1, cu), 256, 0, st>>>(d32, m, n, off);
-    if (w_ic_h && m) ic_edges_kernel<<<grid_for(m, cu), 256, 0, st>>>(s32, wic, m, static_cast<uint2 *>(g->edges_ic.ptr));
+    if (w_ic_h) ic_edges_kernel<<<grid_for(ic_records(m), cu), 256, 0, st>>>(s32, wic, m, static_cast<uint2 *>(g->edges_ic.ptr));
     if (w_lt_h) {
         lt_edges_kernel<<<grid_for(n, cu), 256, 0, st>>>(s32, wlt, off, n, static_cast<uint2 *>(g->edges_lt.ptr), cnt);
     } else {

@@ -131,7 +131,7 @@ struct im_graph {
     uint32_t models = 0;         // bit 0: IC weights present, bit 1: LT weights present
     uint32_t max_in = 0;         // largest in-degree
     DevBuf off;                  // u64[n+1]
-    DevBuf edges_ic;             // uint2[m] {src, thr}
+    DevBuf edges_ic;             // uint2 {src, thr}: m records, then zero records to whole 4-edge groups + 4
     DevBuf edges_lt;             // uint2[m] {src, cumulative thr}
     DevBuf src_cum;              // u64[n+1] cumulative integer source weights, or empty
     uint64_t src_total = 0;      // sum of the source weights (0: uniform sources)

@@ -231,10 +231,10 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
 // ---------------------------------------------------------------- IC ----
 
 // The live edges among the four in-edge records of 4-edge group g of a node
-// whose in-edges are [ea, eb). The four loads are issued together (an index
-// outside the range is clipped into it, and its slot is never live), and
-// liveness is decided without a branch, so that the compiler does not move
-// each load behind its own test and wait for them one by one.
+// whose in-edges are [ea, eb). The group's 32 bytes come in two 16-byte
+// loads (the record array is padded to whole aligned groups, so they stay
+// in it; records outside [ea, eb) belong to other nodes or the pad and are
+// never live), and liveness is decided without a branch.
 __device__ __forceinline__ void ic_group_live(const uint2 *edges, uint64_t g, uint64_t ea, uint64_t eb,
                                               const uint4 &coins, uint2 (&rec)[4], bool (&live)[4]) {
     if (eb <= ea) {
@@ -245,11 +245,12 @@ __device__ __forceinline__ void ic_group_live(const uint2 *edges, uint64_t g, ui
         }
         return;
     }
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-        const uint64_t e = (g << 2) + q;
-        rec[q] = edges[e < ea ? ea : (e < eb ? e : eb - 1)];
-    }
+    const uint4 *gp = reinterpret_cast<const uint4 *>(edges + (g << 2));
+    const uint4 lo = gp[0], hi = gp[1];
+    rec[0] = make_uint2(lo.x, lo.y);
+    rec[1] = make_uint2(lo.z, lo.w);
+    rec[2] = make_uint2(hi.x, hi.y);
+    rec[3] = make_uint2(hi.z, hi.w);
 #pragma unroll
     for (uint32_t q = 0; q < 4; ++q) {
         const uint64_t e = (g << 2) + q;
