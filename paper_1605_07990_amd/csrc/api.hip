@@ -172,27 +172,34 @@ struct AheadCover {
     std::thread th;
     bool running = false;            // started and not joined
     std::atomic<bool> done{false};   // the thread has returned
-    const im_pool *pool = nullptr;   // the pool it reads
+    const im_pool *pool = nullptr;   // the run's pool (which run the cover belongs to)
     im_pool *orphan = nullptr;       // owned: the run that started it has returned
+    im_pool snap;                    // what it reads: a copy of the pool's first sets, or the pool as it was
+    bool stared = false;             // that held [N_t, 2 N_t) too, and cov_c was counted
     im_status rc = IM_OK;
     std::string err;
     uint64_t nt = 0, cov = 0, cov_c = 0;
     std::vector<uint32_t> seeds;
 
-    void start(im_ctx *h, const im_pool *p, uint64_t n_t, uint32_t k) {
+    // `copy` describes what the helper reads: a pool over its own buffers
+    // holding the first copy.count sets, or the run's pool itself (which
+    // then does not move until the cover is joined)
+    void start(im_ctx *h, const im_pool *p, const im_pool &copy, uint64_t n_t, uint32_t k) {
         nt = n_t;
         pool = p;
+        snap = copy;
+        stared = copy.count >= 2 * n_t;
         seeds.assign(k, 0u);
         rc = IM_OK;
         done = false;
         running = true;
-        th = std::thread([this, h, p, k] {
+        th = std::thread([this, h, k] {
             if (hipSetDevice(h->device) != hipSuccess) {
                 rc = IM_E_DEVICE;
                 err = "hipSetDevice failed in the cover thread";
             } else {
-                rc = max_coverage_on(h, p, 0, nt, k, seeds.data(), &cov);
-                if (rc == IM_OK) rc = coverage_range_on(h, p, nt, 2 * nt, seeds.data(), k, &cov_c);
+                rc = max_coverage_on(h, &snap, 0, nt, k, seeds.data(), &cov);
+                if (rc == IM_OK && stared) rc = coverage_range_on(h, &snap, nt, 2 * nt, seeds.data(), k, &cov_c);
                 if (rc == IM_OK) rc = hipStreamSynchronize(h->stream) == hipSuccess ? IM_OK : IM_E_DEVICE;
                 if (rc != IM_OK) err = im_last_error();
             }
@@ -201,6 +208,31 @@ struct AheadCover {
     }
     bool busy() const { return running && !done; }
 };
+
+// Copy the first `upto` sets of pool p into helper h's prefix buffers, on
+// the run's stream (after the work that wrote them), with h's stream made
+// to wait for the copy, and describe the copy as a pool: a helper covers
+// it, so the run's pool may grow and move meanwhile.
+static im_status copy_prefix(im_ctx *ctx, const im_pool *p, im_ctx *h, uint64_t upto, im_pool *copy) {
+    uint64_t tot = p->total;  // every set copied: all node entries
+    if (upto < p->count) IM_TRY(to_host_sync(ctx, &tot, static_cast<const uint64_t *>(p->poff.ptr) + upto, 8));
+    IM_TRY(dev_reserve(h, h->prefix_off, (upto + 1) * 8));
+    IM_TRY(dev_reserve(h, h->prefix_nodes, std::max<uint64_t>(tot, 1) * 4));
+    IM_HIP(hipMemcpyAsync(h->prefix_off.ptr, p->poff.ptr, (upto + 1) * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    if (tot) IM_HIP(hipMemcpyAsync(h->prefix_nodes.ptr, p->pnodes.ptr, tot * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (!h->ev_ready) IM_HIP(hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
+    IM_HIP(hipEventRecord(h->ev_ready, ctx->stream));
+    IM_HIP(hipStreamWaitEvent(h->stream, h->ev_ready, 0));
+    *copy = *p;
+    copy->ctx = h;
+    copy->poff = h->prefix_off;
+    copy->pnodes = h->prefix_nodes;
+    copy->count = upto;
+    copy->total = tot;
+    copy->cap_sets = upto;
+    copy->cap_nodes = tot;
+    return IM_OK;
+}
 
 constexpr int kAheadSlots = 3;
 
@@ -278,6 +310,7 @@ static void copy_greedy_params(const im_ctx *from, im_ctx *to) {
     to->greedy_wg_cand_max_entries = from->greedy_wg_cand_max_entries;
     to->greedy_wg_cand_grid_rounds = from->greedy_wg_cand_grid_rounds;
     to->greedy_wg_cand_batch = from->greedy_wg_cand_batch;
+    to->greedy_flat_levels = from->greedy_flat_levels;
 }
 
 // Helper context i (0..2) of ctx for later iterations' Max-Coverage.
@@ -585,9 +618,10 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_begin) (void)hipEventDestroy(c->ev_begin);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     if (c->ev_group) (void)hipEventDestroy(c->ev_group);
+    if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
     free_round_graphs(c);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->handoff, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits, &c->flat,
-                      &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
+                      &c->prefix_off, &c->prefix_nodes, &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     if (c->owns_stream) (void)hipStreamDestroy(c->stream);
@@ -1109,11 +1143,22 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     // later iterations' covers running on helper contexts (slot i = helper
     // i); a slot still busy with a dropped cover of an earlier run is left
     // alone until it is done
+    // (an IC run with side sampling keeps one helper fewer: the run's
+    // stream, the side stream and two helpers fill the four hardware queues)
     AheadCover *ahead = ctx->dssa_greedy_ahead ? ahead_slots(ctx) : nullptr;
-    const uint32_t n_ahead = ahead ? ctx->dssa_greedy_ahead : 0u;
-    // every cover of this run is done before the pool's buffers may move
+    const uint32_t ahead_max = (model == IM_IC && ctx->speculate) ? kAheadSlots - 1 : kAheadSlots;
+    // A run that draws ahead (LT) has every set a helper needs long before
+    // it is covered and grows its pool rarely: helpers read the pool itself,
+    // and every cover of the run is joined before the pool may move. Other
+    // runs grow the pool every iteration: each helper covers its own copy
+    // of the greedy sets, started as soon as those are drawn (not for k = 1,
+    // whose cover is one count and argmax, shorter than the copy's wait).
+    const bool helper_copies = !(model == IM_LT && ctx->dssa_draw_ahead > 1);
+    const uint32_t n_ahead =
+        (ahead && !(helper_copies && k < 2)) ? std::min<uint32_t>(ctx->dssa_greedy_ahead, ahead_max) : 0u;
     auto join_ahead = [&]() {
         im_status r = IM_OK;
+        if (helper_copies) return r;
         for (uint32_t i = 0; i < n_ahead; ++i) {
             if (ahead[i].pool != pool) continue;
             const im_status x = join_slot(ahead, int(i));
@@ -1163,12 +1208,14 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
             }
             if (aux) spec.start(aux, pool, pool->count, 4 * nt - pool->count);
         }
-        // the next iterations whose sets are all drawn are covered on the
-        // helper contexts meanwhile (at most one per helper)
+        // the next iterations whose greedy sets [0, N) are drawn are covered
+        // on the helper contexts meanwhile (at most one per helper); with
+        // copies, an iteration whose stare sets [N, 2N) were not drawn yet
+        // has its stare count taken here when it comes
         bool synced = false;
         for (uint32_t j = 1; j <= n_ahead; ++j) {
             const uint64_t nj = nt << j;
-            if (double(nj >> 1) >= c.n_max || 2 * nj > pool->count) break;
+            if (double(nj >> 1) >= c.n_max || (helper_copies ? nj : 2 * nj) > pool->count) break;
             bool have = false;
             for (uint32_t i = 0; i < n_ahead; ++i) have = have || (ahead[i].pool == pool && ahead[i].nt == nj);
             if (have) continue;
@@ -1181,7 +1228,10 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
                     clear_error();
                     continue;  // go on without this helper
                 }
-                if (!synced) {
+                im_pool copy = *pool;
+                if (helper_copies) {
+                    rc = copy_prefix(ctx, pool, h, std::min<uint64_t>(pool->count, 2 * nj), &copy);
+                } else if (!synced) {
                     // the pool's sets were written on this context's stream
                     if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
                         set_error("stream synchronize failed");
@@ -1189,7 +1239,7 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
                     }
                     synced = true;
                 }
-                if (rc == IM_OK) ahead[i].start(h, pool, nj, k);
+                if (rc == IM_OK) ahead[i].start(h, pool, copy, nj, k);
                 break;
             }
             if (rc != IM_OK) break;
@@ -1209,6 +1259,11 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
             cov_c = m.cov_c;
             ms_cover_last = now_ms() - t0;
             st->ms_cover += ms_cover_last;
+            if (!m.stared) {  // its stare sets were drawn after it started
+                t0 = now_ms();
+                if ((rc = coverage_range(pool, nt, 2 * nt, seeds.data(), k, &cov_c))) break;
+                st->ms_verify += now_ms() - t0;
+            }
         } else {
             if ((rc = max_coverage(pool, 0, nt, k, seeds.data(), &cov))) break;
             ms_cover_last = now_ms() - t0;

@@ -70,6 +70,8 @@ struct im_ctx {
     DevBuf cover;        // incidence / greedy working arrays
     DevBuf seedbits;     // seed-set bitmap (n bits)
     DevBuf flat;         // greedy rounds by gain level: state, node lists, tile counts
+    DevBuf prefix_off;   // a helper context's copy of the first sets of the pool it covers: offsets
+    DevBuf prefix_nodes; //   and node entries
     DevBuf zflags;       // Estimate-Inf per-sample hit flags
     DevBuf items;        // fused sampler work queue + per-item accumulators
     DevBuf append_dst;   // per-item pool destinations of a fused append
@@ -97,6 +99,7 @@ struct im_ctx {
     // optional event timing of the main sampler launches
     bool timing = false;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr, ev_group = nullptr;
+    hipEvent_t ev_ready = nullptr;  // a helper context: its copy of a pool's sets is written
     im_kernel_times times{};
 
     // second sampling context on its own stream (same device and allocator,
