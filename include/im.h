@@ -411,7 +411,12 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       uncovered sets was covered earlier in the level (exactly the
  *       rounds' argmaxes), then the gains are recounted for the next level;
  *       levels with g* above 16 use the grid-wide rounds; 0: grid-wide
- *       rounds, two launches each (default 1).
+ *       rounds, two launches each (default 1);
+ *   IM_PARAM_GREEDY_DENSE           1: Max-Coverage of a range holding fewer
+ *       entries than half the graph's nodes runs over the nodes the range
+ *       holds, numbered by rank in id order (the same picks: a node outside
+ *       the range has gain 0, and the rounds after every set is covered
+ *       take the lowest unpicked ids); 0: over all n nodes (default 1).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -430,7 +435,8 @@ typedef enum {
     IM_PARAM_DSSA_GREEDY_AHEAD = 12,
     IM_PARAM_GREEDY_WG_CAND_BATCH = 13,
     IM_PARAM_IC_PLAIN = 14,
-    IM_PARAM_GREEDY_FLAT_LEVELS = 15
+    IM_PARAM_GREEDY_FLAT_LEVELS = 15,
+    IM_PARAM_GREEDY_DENSE = 16
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

@@ -43,6 +43,7 @@ IM_PARAM_GREEDY_CANDIDATES, IM_PARAM_GREEDY_CANDIDATES_BATCH, IM_PARAM_DSSA_DRAW
 IM_PARAM_GREEDY_GRAPH, IM_PARAM_GREEDY_WG_CAND_MAX_ENTRIES, IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS = 9, 10, 11
 IM_PARAM_DSSA_GREEDY_AHEAD, IM_PARAM_GREEDY_WG_CAND_BATCH, IM_PARAM_IC_PLAIN = 12, 13, 14
 IM_PARAM_GREEDY_FLAT_LEVELS = 15
+IM_PARAM_GREEDY_DENSE = 16
 PARAMS = {"greedy_cover_blocks": IM_PARAM_GREEDY_COVER_BLOCKS, "ic_edge_budget": IM_PARAM_IC_EDGE_BUDGET, "greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK,
           "dssa_speculate": IM_PARAM_DSSA_SPECULATE, "greedy_mark_min_chunks": IM_PARAM_GREEDY_MARK_MIN_CHUNKS,
           "greedy_candidates": IM_PARAM_GREEDY_CANDIDATES, "greedy_candidates_batch": IM_PARAM_GREEDY_CANDIDATES_BATCH,
@@ -51,7 +52,8 @@ PARAMS = {"greedy_cover_blocks": IM_PARAM_GREEDY_COVER_BLOCKS, "ic_edge_budget":
           "greedy_wg_cand_grid_rounds": IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS,
           "dssa_greedy_ahead": IM_PARAM_DSSA_GREEDY_AHEAD,
           "greedy_wg_cand_batch": IM_PARAM_GREEDY_WG_CAND_BATCH,
-          "ic_plain": IM_PARAM_IC_PLAIN, "greedy_flat_levels": IM_PARAM_GREEDY_FLAT_LEVELS}
+          "ic_plain": IM_PARAM_IC_PLAIN, "greedy_flat_levels": IM_PARAM_GREEDY_FLAT_LEVELS,
+          "greedy_dense": IM_PARAM_GREEDY_DENSE}
 
 IM_ALGO_SSA, IM_ALGO_DSSA, IM_ALGO_ESTIMATE = 0, 1, 2
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}

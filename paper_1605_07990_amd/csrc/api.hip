@@ -311,6 +311,7 @@ static void copy_greedy_params(const im_ctx *from, im_ctx *to) {
     to->greedy_wg_cand_grid_rounds = from->greedy_wg_cand_grid_rounds;
     to->greedy_wg_cand_batch = from->greedy_wg_cand_batch;
     to->greedy_flat_levels = from->greedy_flat_levels;
+    to->greedy_dense = from->greedy_dense;
 }
 
 // Helper context i (0..2) of ctx for later iterations' Max-Coverage.
@@ -512,6 +513,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 1) break;
         c->greedy_flat_levels = value != 0;
         return IM_OK;
+    case IM_PARAM_GREEDY_DENSE:
+        if (value > 1) break;
+        c->greedy_dense = value != 0;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -569,6 +574,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
     case IM_PARAM_GREEDY_FLAT_LEVELS:
         *value = c->greedy_flat_levels ? 1 : 0;
         return IM_OK;
+    case IM_PARAM_GREEDY_DENSE:
+        *value = c->greedy_dense ? 1 : 0;
+        return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
     return IM_E_ARG;
@@ -621,7 +629,7 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
     free_round_graphs(c);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->handoff, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits, &c->flat,
-                      &c->prefix_off, &c->prefix_nodes, &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
+                      &c->prefix_off, &c->prefix_nodes, &c->dense, &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     if (c->owns_stream) (void)hipStreamDestroy(c->stream);

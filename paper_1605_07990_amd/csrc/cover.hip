@@ -2251,16 +2251,12 @@ im_status max_coverage(const im_pool *p, uint64_t begin, uint64_t end, uint32_t 
     return max_coverage_on(p->ctx, p, begin, end, k, seeds_host, cov);
 }
 
-im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, uint32_t k,
-                          uint32_t *seeds_host, uint64_t *cov) {
-    const uint32_t n = p->g->n;
+// Algorithm 2 over sets [begin, end) of a pool whose node ids are below n,
+// entries [ebegin, eend) of pnodes.
+static im_status greedy_on(im_ctx *ctx, uint32_t n, const uint64_t *poff, const uint32_t *pnodes, uint64_t begin,
+                           uint64_t end, uint64_t ebegin, uint64_t eend, uint32_t k, uint32_t *seeds_host,
+                           uint64_t *cov) {
     const uint64_t nsets = end - begin;
-    const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);
-    const auto *pnodes = static_cast<const uint32_t *>(p->pnodes.ptr);
-    uint64_t ends[2] = {0, 0};
-    IM_TRY(to_host_sync(ctx, &ends[0], poff + begin, 8));
-    IM_TRY(to_host_sync(ctx, &ends[1], poff + end, 8));
-    const uint64_t ebegin = ends[0], eend = ends[1];
     const uint64_t entries = eend - ebegin;
 
     if (k == 1) {
@@ -2454,6 +2450,173 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
     IM_HIP(hipMemcpyAsync(seeds_host, g.seeds, 4ull * k, hipMemcpyDeviceToHost, st));
     IM_TRY(to_host_sync(ctx, cov, dcov, 8));
     return IM_OK;
+}
+
+// ---- the greedy over the nodes a range holds ----
+//
+// Every per-node array and pass of the greedy (gains, incidence offsets,
+// the maximum index, their scans) is sized by the graph's n. On a graph much
+// larger than the range (a D-SSA iteration's sets on the Twitter-shaped
+// graph hold a few million entries of its 41.7 M nodes), the greedy runs
+// over the nodes the range holds instead, numbered by rank in id order, so
+// that the lowest-id tie-break picks the same nodes. A node the range does
+// not hold has gain 0, so it is picked only once every set is covered; the
+// rounds from that point are filled here with the lowest unpicked ids, as
+// Algorithm 2 over all of V picks them.
+
+__global__ void mark_nodes_kernel(const uint32_t *pnodes, uint64_t eb, uint64_t ee, unsigned long long *bits) {
+    for (uint64_t e = eb + blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < ee;
+         e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t v = pnodes[e];
+        atomicOr(&bits[v >> 6], 1ull << (v & 63u));
+    }
+}
+
+__global__ void word_counts_kernel(const unsigned long long *bits, uint64_t words, uint32_t *cnt) {
+    for (uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; w < words;
+         w += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        cnt[w] = static_cast<uint32_t>(__popcll(bits[w]));
+}
+
+// rank[w]: the held nodes below word w
+__global__ void dense_entries_kernel(const uint32_t *pnodes, uint64_t eb, uint64_t ee,
+                                     const unsigned long long *bits, const uint64_t *rank, uint32_t *out) {
+    for (uint64_t e = eb + blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < ee;
+         e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t v = pnodes[e];
+        const unsigned long long below = bits[v >> 6] & ((1ull << (v & 63u)) - 1ull);
+        out[e - eb] = static_cast<uint32_t>(rank[v >> 6] + static_cast<uint64_t>(__popcll(below)));
+    }
+}
+
+__global__ void dense_ids_kernel(const unsigned long long *bits, uint64_t words, const uint64_t *rank, uint32_t *ids) {
+    for (uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; w < words;
+         w += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        unsigned long long b = bits[w];
+        uint64_t r = rank[w];
+        while (b) {
+            ids[r++] = static_cast<uint32_t>(w * 64 + static_cast<uint64_t>(__ffsll(static_cast<long long>(b)) - 1));
+            b &= b - 1ull;
+        }
+    }
+}
+
+// offsets of sets [begin, begin + nsets] relative to the first
+__global__ void rebase_offsets_kernel(const uint64_t *poff, uint64_t begin, uint64_t nsets, uint64_t *out) {
+    const uint64_t base = poff[begin];
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i <= nsets;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        out[i] = poff[begin + i] - base;
+}
+
+__global__ void map_ids_kernel(const uint32_t *ids, const uint32_t *dense, uint32_t k, uint32_t *out) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < k; r += gridDim.x * blockDim.x) out[r] = ids[dense[r]];
+}
+
+static im_status greedy_dense(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, uint64_t ebegin,
+                              uint64_t eend, uint32_t k, uint32_t *seeds_host, uint64_t *cov) {
+    const uint32_t n = p->g->n;
+    const uint64_t nsets = end - begin, entries = eend - ebegin;
+    const uint64_t words = (uint64_t(n) + 63) / 64;
+    const uint64_t tiles = (words + kTile - 1) / kTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return at;
+    };
+    const size_t o_bits = take(8 * words), o_cnt = take(4 * words), o_rank = take(8 * (words + 1)),
+                 o_tsum = take(8 * (tiles + 1)), o_ent = take(4 * (entries + 1)), o_off = take(8 * (nsets + 1)),
+                 o_ids = take(4 * (std::min<uint64_t>(n, entries) + 1)), o_dseeds = take(4ull * k),
+                 o_seeds = take(4ull * k);
+    IM_TRY(dev_reserve(ctx, ctx->dense, off));
+    char *base = static_cast<char *>(ctx->dense.ptr);
+    auto *bits = reinterpret_cast<unsigned long long *>(base + o_bits);
+    auto *cnt = reinterpret_cast<uint32_t *>(base + o_cnt);
+    auto *rank = reinterpret_cast<uint64_t *>(base + o_rank);
+    auto *tsum = reinterpret_cast<uint64_t *>(base + o_tsum);
+    auto *ent = reinterpret_cast<uint32_t *>(base + o_ent);
+    auto *doff = reinterpret_cast<uint64_t *>(base + o_off);
+    auto *ids = reinterpret_cast<uint32_t *>(base + o_ids);
+    auto *dseeds = reinterpret_cast<uint32_t *>(base + o_dseeds);
+    auto *oseeds = reinterpret_cast<uint32_t *>(base + o_seeds);
+    const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);
+    const auto *pnodes = static_cast<const uint32_t *>(p->pnodes.ptr);
+    hipStream_t st = ctx->stream;
+    const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+    fill_u64_kernel<<<grid_of(words, kThreads, cu * 8), kThreads, 0, st>>>(reinterpret_cast<uint64_t *>(bits), words,
+                                                                           0);
+    mark_nodes_kernel<<<grid_of(entries, kThreads, cu * 16), kThreads, 0, st>>>(pnodes, ebegin, eend, bits);
+    word_counts_kernel<<<grid_of(words, kThreads, cu * 8), kThreads, 0, st>>>(bits, words, cnt);
+    tile_sums_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(cnt, words, tsum);
+    tile_scan_kernel<<<1, 1024, 0, st>>>(tsum, tiles);
+    tile_apply_kernel<<<static_cast<uint32_t>(tiles), kThreads, 0, st>>>(cnt, words, tsum, rank);
+    dense_entries_kernel<<<grid_of(entries, kThreads, cu * 16), kThreads, 0, st>>>(pnodes, ebegin, eend, bits, rank,
+                                                                                   ent);
+    dense_ids_kernel<<<grid_of(words, kThreads, cu * 8), kThreads, 0, st>>>(bits, words, rank, ids);
+    rebase_offsets_kernel<<<grid_of(nsets + 1, kThreads, cu * 4), kThreads, 0, st>>>(poff, begin, nsets, doff);
+    IM_HIP(hipGetLastError());
+    uint64_t held = 0;
+    IM_TRY(to_host_sync(ctx, &held, rank + words, 8));
+    if (held == 0 || held > n) {
+        set_error("max coverage: %llu nodes held by a range of %llu entries", static_cast<unsigned long long>(held),
+                  static_cast<unsigned long long>(entries));
+        return IM_E_DEVICE;
+    }
+    // every held node picked covers every set: rounds past them have gain 0
+    const uint32_t kd = static_cast<uint32_t>(std::min<uint64_t>(k, held));
+    std::vector<uint32_t> picks(k);
+    IM_TRY(greedy_on(ctx, static_cast<uint32_t>(held), doff, ent, 0, nsets, 0, entries, kd, picks.data(), cov));
+    IM_HIP(hipMemcpyAsync(dseeds, picks.data(), 4ull * kd, hipMemcpyHostToDevice, st));
+    map_ids_kernel<<<grid_of(kd, kThreads, 64), kThreads, 0, st>>>(ids, dseeds, kd, oseeds);
+    IM_HIP(hipGetLastError());
+    IM_HIP(hipMemcpyAsync(picks.data(), oseeds, 4ull * kd, hipMemcpyDeviceToHost, st));
+    IM_HIP(hipStreamSynchronize(st));
+    uint32_t positive = kd;
+    if (*cov == nsets) {
+        // the picks with a gain: the fewest whose sets cover the range
+        uint32_t lo = 1, hi = kd;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            uint64_t c = 0;
+            IM_TRY(coverage_range_on(ctx, p, begin, end, picks.data(), mid, &c));
+            if (c == nsets) hi = mid;
+            else lo = mid + 1;
+        }
+        positive = nsets ? lo : 0;
+    }
+    std::copy(picks.begin(), picks.begin() + positive, seeds_host);
+    if (positive < k) {  // gain 0 everywhere: the lowest ids not picked yet
+        std::vector<uint32_t> taken(picks.begin(), picks.begin() + positive);
+        std::sort(taken.begin(), taken.end());
+        uint32_t r = positive, v = 0;
+        size_t t = 0;
+        while (r < k && v < n) {
+            while (t < taken.size() && taken[t] < v) ++t;
+            if (t < taken.size() && taken[t] == v) {
+                ++v;
+                continue;
+            }
+            seeds_host[r++] = v++;
+        }
+    }
+    return IM_OK;
+}
+
+im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, uint32_t k,
+                          uint32_t *seeds_host, uint64_t *cov) {
+    const uint32_t n = p->g->n;
+    const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);
+    const auto *pnodes = static_cast<const uint32_t *>(p->pnodes.ptr);
+    uint64_t ends[2] = {0, 0};
+    IM_TRY(to_host_sync(ctx, &ends[0], poff + begin, 8));
+    IM_TRY(to_host_sync(ctx, &ends[1], poff + end, 8));
+    const uint64_t ebegin = ends[0], eend = ends[1];
+    const uint64_t entries = eend - ebegin;
+    // the ranked form once the range holds fewer entries than half the nodes
+    if (ctx->greedy_dense && k && entries && 2 * entries <= n)
+        return greedy_dense(ctx, p, begin, end, ebegin, eend, k, seeds_host, cov);
+    return greedy_on(ctx, n, poff, pnodes, begin, end, ebegin, eend, k, seeds_host, cov);
 }
 
 im_status first_crossing(im_ctx *ctx, uint64_t count, uint64_t need, int64_t *index, uint64_t *hits) {

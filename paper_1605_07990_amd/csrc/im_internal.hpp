@@ -70,6 +70,7 @@ struct im_ctx {
     DevBuf cover;        // incidence / greedy working arrays
     DevBuf seedbits;     // seed-set bitmap (n bits)
     DevBuf flat;         // greedy rounds by gain level: state, node lists, tile counts
+    DevBuf dense;        // greedy over the nodes a range holds: node bitmap, ranks, ranked entries, ids
     DevBuf prefix_off;   // a helper context's copy of the first sets of the pool it covers: offsets
     DevBuf prefix_nodes; //   and node entries
     DevBuf zflags;       // Estimate-Inf per-sample hit flags
@@ -85,6 +86,7 @@ struct im_ctx {
     uint32_t ic_edge_budget = 16384;
     bool ic_plain = false;  // IC draws as plain launches (static assignment, no workgroup tiers)
     bool greedy_flat_levels = true;  // flat gains: rounds by gain level instead of grid-wide rounds
+    bool greedy_dense = true;        // a range holding few of the nodes: the greedy over the nodes it holds
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 8;           // im_dssa on LT: a draw takes up to this many iterations' sets

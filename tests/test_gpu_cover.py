@@ -268,3 +268,43 @@ def test_greedy_round_graph_replays(im, ctx, pools, graph):
         ctx.set_param("greedy_graph", old[0])
         ctx.set_param("greedy_candidates", old[1])
         ctx.set_param("greedy_wg_cand_max_entries", old[2])
+
+
+@pytest.mark.parametrize("dense", [1, 0])
+def test_greedy_over_held_nodes_matches_oracle(im, ctx, oracle_lib, dense):
+    """Max-Coverage of ranges holding fewer entries than half the nodes runs
+    over the nodes the range holds (ranked in id order) when the parameter
+    is on: the picks equal Algorithm 2 over all nodes, including rounds
+    after every set is covered (the lowest unpicked ids, nodes outside the
+    range among them) and k above the number of nodes the range holds."""
+    note(f"greedy over held nodes: dense={dense}")
+    old = ctx.get_param("greedy_dense")
+    ctx.set_param("greedy_dense", dense)
+    try:
+        g = synth.make("cl_mid")
+        dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+        og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+        p = im.Pool(dg, 0, 21)
+        p.sample(3000)
+        op = oracle_lib.Pool(og, 21)
+        op.extend(3000)
+        for begin, end, k in ((0, 3000, 1), (0, 3000, 10), (0, 3000, 400), (700, 1900, 2500), (17, 41, 100),
+                              (2999, 3000, 3), (0, 3000, 5000)):
+            seeds, cov = p.max_coverage(k, begin, end)
+            oseeds, ocov = op.max_coverage(k, begin, end)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (begin, end, k)
+        # every set a single source node: the held nodes are the sources
+        n = 200_000
+        e = np.array([], np.uint32)
+        dg = im.Graph(ctx, n, e, e, w_ic=np.array([], np.float32))
+        og = oracle_lib.Graph(0, n, e, e, np.array([], np.float32))
+        p = im.Pool(dg, 0, 22)
+        p.sample(5000)
+        op = oracle_lib.Pool(og, 22)
+        op.extend(5000)
+        for begin, end, k in ((0, 100, 150), (250, 4250, 60), (0, 5000, 5200)):
+            seeds, cov = p.max_coverage(k, begin, end)
+            oseeds, ocov = op.max_coverage(k, begin, end)
+            assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (begin, end, k)
+    finally:
+        ctx.set_param("greedy_dense", old)
