@@ -492,9 +492,11 @@ def run_twitter(args, im, ctx, sync):
     return out, cpu
 
 
-def greedy_roofline(im, dg, sync, progress, sets: int = 1 << 20, ks=(100, 1000)) -> dict:
+def greedy_roofline(im, dg, sync, progress, sets: int = 72_672, ks=(100, 1000)) -> dict:
     """Max-Coverage (Algorithm 2: the node-to-set incidence, then k greedy
-    rounds; im_max_coverage_range) over a pool of `sets` RR sets (key 0),
+    rounds; im_max_coverage_range) over a pool of `sets` RR sets (key 0; the
+    default is the greedy range N_t of the last iteration of a k = 100 D-SSA
+    run on the Twitter-shaped graph),
     host wall time around synchronised calls, best of two per k, against
     the HBM stream peak with the streaming bytes of the method: the
     incidence's three passes of 4 B per pool entry plus 8 B per node, and

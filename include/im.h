@@ -412,8 +412,8 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       rounds' argmaxes), then the gains are recounted for the next level;
  *       levels with g* above 16 use the grid-wide rounds; 0: grid-wide
  *       rounds, two launches each (default 1);
- *   IM_PARAM_GREEDY_DENSE           1: Max-Coverage of a range holding fewer
- *       entries than half the graph's nodes runs over the nodes the range
+ *   IM_PARAM_GREEDY_DENSE           1: Max-Coverage (k > 1) of a range holding
+ *       fewer entries than half the graph's nodes runs over the nodes the range
  *       holds, numbered by rank in id order (the same picks: a node outside
  *       the range has gain 0, and the rounds after every set is covered
  *       take the lowest unpicked ids); 0: over all n nodes (default 1).

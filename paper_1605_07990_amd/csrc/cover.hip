@@ -2468,7 +2468,9 @@ __global__ void mark_nodes_kernel(const uint32_t *pnodes, uint64_t eb, uint64_t 
     for (uint64_t e = eb + blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < ee;
          e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
         const uint32_t v = pnodes[e];
-        atomicOr(&bits[v >> 6], 1ull << (v & 63u));
+        const unsigned long long m = 1ull << (v & 63u);
+        // a node in many sets of the range sets its bit once, not once per set
+        if (!(__atomic_load_n(&bits[v >> 6], __ATOMIC_RELAXED) & m)) atomicOr(&bits[v >> 6], m);
     }
 }
 
@@ -2614,7 +2616,8 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
     const uint64_t ebegin = ends[0], eend = ends[1];
     const uint64_t entries = eend - ebegin;
     // the ranked form once the range holds fewer entries than half the nodes
-    if (ctx->greedy_dense && k && entries && 2 * entries <= n)
+    // (k = 1 is one count and argmax over the nodes, no cheaper that way)
+    if (ctx->greedy_dense && k > 1 && entries && 2 * entries <= n)
         return greedy_dense(ctx, p, begin, end, ebegin, eend, k, seeds_host, cov);
     return greedy_on(ctx, n, poff, pnodes, begin, end, ebegin, eend, k, seeds_host, cov);
 }
