@@ -30,6 +30,8 @@ CANDIDATES = {
     "greedy_wg_cand_grid_rounds": [0, 4, 8, 16, 32],
     "dssa_greedy_ahead": [0, 1, 2],
     "greedy_wg_cand_batch": [0, 1 << 20, 1 << 21, 1 << 23, 1 << 62],
+    "greedy_flat_levels": [1, 0],
+    "greedy_dense": [1, 0],
 }
 
 
