@@ -275,8 +275,32 @@ __device__ __forceinline__ void refresh_m2_one(const GreedyState &g, uint32_t d)
     if (m != 0ull && ld<kWg>(g.m1 + ((~static_cast<uint32_t>(m)) >> kL1Shift)) != m) g.m2[d] = m2_lane<kWg>(g, d);
 }
 
+// Largest value over a wave with DPP row shifts (a running maximum inside
+// each row of 16 lanes, then the four row maxima read with v_readlane): VALU
+// latency only, where the shuffle reduction is twelve LDS permutes and waits
+// for a 64-bit key. Call it with every lane of the wave active.
+__device__ __forceinline__ uint32_t wave_max_u32_dpp(uint32_t x) {
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xF, 0xF, false)));
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xF, 0xF, false)));
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xF, 0xF, false)));
+    x = max(x, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xF, 0xF, false)));
+    const uint32_t a = max(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 15)),
+                           static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 31)));
+    const uint32_t b = max(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 47)),
+                           static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 63)));
+    return max(a, b);
+}
+
+// The wave's largest 64-bit key: the largest high word, then the largest low
+// word among the lanes that hold it.
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long x) {
+    const uint32_t hi = wave_max_u32_dpp(static_cast<uint32_t>(x >> 32));
+    const uint32_t lo = wave_max_u32_dpp(static_cast<uint32_t>(x >> 32) == hi ? static_cast<uint32_t>(x) : 0u);
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x, unsigned long long *smem) {
-    x = wave_max_u64(x);
+    x = wave_max_key(x);
     if (lane_id() == 0) smem[threadIdx.x / kWave] = x;
     __syncthreads();
     unsigned long long m = 0;
@@ -364,7 +388,7 @@ __device__ __forceinline__ void refresh_block(const GreedyState &g, uint32_t r, 
             }
         }
         best = m > best ? m : best;
-        const unsigned long long gm = wave_max_u64(m);
+        const unsigned long long gm = wave_max_key(m);
         if (lane == 0) g.m2[c0 >> kL2Shift] = gm;
     }
     best = block_max_u64(best, smem);
@@ -1090,13 +1114,14 @@ __device__ void wg_rounds(const GreedyState &g, const StepHdr &h, uint64_t words
                 }
             }
         }
-        const unsigned long long wbest = wave_max_u64(best);
+        const unsigned long long wbest = wave_max_key(best);
         if (wbest <= h.thresh) {  // the same value in every wave
             stalled = true;
             break;
         }
         const unsigned long long holder = __ballot(best == wbest);
-        const uint32_t sv = __shfl(bslot, static_cast<int>(__ffsll(holder)) - 1, kWave);
+        const uint32_t sv = static_cast<uint32_t>(
+            __builtin_amdgcn_readlane(static_cast<int>(bslot), static_cast<int>(__ffsll(holder)) - 1));
         const uint32_t v = ~static_cast<uint32_t>(wbest & 0xFFFFFFFFull);
         if (tid == 0) {
             gseeds[r] = v;
@@ -1404,7 +1429,7 @@ __global__ __launch_bounds__(kThreads) void argmax_count_kernel(const uint32_t *
         const unsigned long long key = (static_cast<unsigned long long>(cnt[v]) << 32) | static_cast<uint32_t>(~v);
         best = key > best ? key : best;
     }
-    best = wave_max_u64(best);
+    best = wave_max_key(best);
     if (lane_id() == 0 && best) atomicMax(out, best);
 }
 
