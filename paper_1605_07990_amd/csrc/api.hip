@@ -517,6 +517,9 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
         if (value > 1) break;
         c->greedy_dense = value != 0;
         return IM_OK;
+    case IM_PARAM_DSSA_IC_MIN_DRAW:
+        c->dssa_ic_min_draw = value;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -576,6 +579,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_GREEDY_DENSE:
         *value = c->greedy_dense ? 1 : 0;
+        return IM_OK;
+    case IM_PARAM_DSSA_IC_MIN_DRAW:
+        *value = c->dssa_ic_min_draw;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
@@ -1193,9 +1199,15 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         uint64_t target = 2 * nt;
         if (model == IM_LT && pool->count < target && ctx->dssa_draw_ahead > 1)
             target = std::max(target, std::min(most, 2 * nt * ctx->dssa_draw_ahead));
-        if (pool->count < target && (rc = join_ahead())) break;
+        // likewise an IC run with k = 1, whose cover (one count and argmax)
+        // cannot hide a draw, while its draws are small: up to the largest
+        // 2 N_{t+j} within the minimum draw
+        if (model == IM_IC && k == 1 && pool->count < target)
+            while (2 * target <= ctx->dssa_ic_min_draw && 2 * target <= most) target *= 2;
+        const bool drew = pool->count < target;
+        if (drew && (rc = join_ahead())) break;
         if ((rc = pool_extend_to(pool, target, nullptr))) break;
-        const double ms_fresh = now_ms() - t_fresh;  // this iteration's own draw, if any
+        const double ms_fresh = drew ? now_ms() - t_fresh : 0.0;  // this iteration's own draw, if any
         st->ms_sample += now_ms() - t0;
         // draw the next iteration's new sets [2 N_t, 4 N_t) while this one is
         // covered (they are dropped if this iteration stops), when the cover
@@ -1328,9 +1340,13 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     if (rc == IM_OK) {
         st->edges = pool->edges;
         if (pool->count > st->n_sets) {
-            // drawn ahead (LT only): an LT walk examines one in-edge list
-            // per node it holds, so the used sets' edges are their sizes
-            rc = to_host_sync(ctx, &st->edges, static_cast<const uint64_t *>(pool->poff.ptr) + st->n_sets, 8);
+            // drawn ahead: the used sets' edges. An LT walk examines one
+            // in-edge list per node it holds, so they are their sizes; an IC
+            // set examines every in-edge of its nodes
+            if (model == IM_LT)
+                rc = to_host_sync(ctx, &st->edges, static_cast<const uint64_t *>(pool->poff.ptr) + st->n_sets, 8);
+            else
+                rc = pool_ic_edges(pool, st->n_sets, &st->edges);
         }
         std::memcpy(seeds_out, seeds.data(), 4ull * k);
     }

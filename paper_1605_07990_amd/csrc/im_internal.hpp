@@ -90,6 +90,7 @@ struct im_ctx {
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 8;           // im_dssa on LT: a draw takes up to this many iterations' sets
+    uint64_t dssa_ic_min_draw = 131072;     // im_dssa on IC, k = 1: a draw takes later iterations' sets up to this many
     double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
     bool greedy_graph = false;        // replay cached graphs of a range's per-round launches
     uint64_t greedy_wg_cand_max_entries = ~0ull;  // ranges up to this many entries: one-workgroup candidate rounds
@@ -221,6 +222,9 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
 
 // Append a fused batch, item by item, to the items' pools in sample order.
 im_status pool_append_items(im_ctx *ctx, const AppendItem *items, uint32_t nitems);
+// In-edges the first `sets` IC sets of pool p examined (the sum of their
+// nodes' in-degrees, what their draws counted), on p's context.
+im_status pool_ic_edges(const im_pool *p, uint64_t sets, uint64_t *edges);
 
 // Draw samples [s0, s0+count) of stream `key` for `model`. Pool mode leaves
 // the sets in ctx->stage with per-sample (offset, size) in ctx->sample_meta;

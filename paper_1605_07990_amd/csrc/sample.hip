@@ -1658,6 +1658,44 @@ static im_status grow_pool(im_pool *p, uint64_t need_sets, uint64_t need_nodes) 
     return IM_OK;
 }
 
+}  // namespace im
+
+namespace {
+
+// Sum of the in-degrees of pool entries [0, entries) into *out.
+__global__ void ic_entry_edges_kernel(const uint32_t *pnodes, uint64_t entries, const uint64_t *off,
+                                      unsigned long long *out) {
+    uint64_t acc = 0;
+    for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < entries;
+         e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t v = pnodes[e];
+        acc += off[v + 1] - off[v];
+    }
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0 && acc) atomicAdd(out, static_cast<unsigned long long>(acc));
+}
+
+}  // namespace
+
+namespace im {
+
+im_status pool_ic_edges(const im_pool *p, uint64_t sets, uint64_t *edges) {
+    im_ctx *ctx = p->ctx;
+    uint64_t entries = 0;
+    IM_TRY(to_host_sync(ctx, &entries, static_cast<const uint64_t *>(p->poff.ptr) + sets, 8));
+    IM_TRY(dev_reserve(ctx, ctx->counters, 256));
+    // past the sampler's counters, which the same stream uses before and after
+    auto *sum = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->counters.ptr) + 192);
+    static_assert(sizeof(Counters) <= 192, "the edge sum sits after the sampler counters");
+    zero_u64_kernel<<<1, 64, 0, ctx->stream>>>(reinterpret_cast<uint64_t *>(sum), 1);
+    if (entries)
+        ic_entry_edges_kernel<<<blocks_for(entries, 256, static_cast<uint32_t>(ctx->cu_count) * 8), 256, 0,
+                                ctx->stream>>>(static_cast<const uint32_t *>(p->pnodes.ptr), entries,
+                                               static_cast<const uint64_t *>(p->g->off.ptr), sum);
+    IM_HIP(hipGetLastError());
+    return to_host_sync(ctx, edges, sum, 8);
+}
+
 im_status pool_append_items(im_ctx *ctx, const AppendItem *items, uint32_t nitems) {
     if (nitems == 0) return IM_OK;
     hipStream_t st = ctx->stream;
