@@ -362,13 +362,12 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       its longest walk), 1..64 (default 8; IC draws are not affected).
  *       While it is above 1, LT runs do not draw the next iteration's sets
  *       on the side (IM_PARAM_DSSA_SPECULATE applies to IC runs);
- *   IM_PARAM_DSSA_IC_MIN_DRAW       when im_dssa on the IC model with k = 1
- *       (whose cover, one count and argmax, cannot hide a draw) must draw
+ *   IM_PARAM_DSSA_IC_MIN_DRAW       when im_dssa on the IC model must draw
  *       the RR sets of iteration t, it also draws later iterations' sets in
  *       the same launches, up to the largest 2 N_{t+j} not above this many
  *       sets (a small IC launch lasts about as long as its deepest samples,
  *       whatever its size); 0 or a value below 2 N_t: no more than
- *       iteration t's (default 131072);
+ *       iteration t's (default 262144);
  *   IM_PARAM_GREEDY_GRAPH           1: the k rounds of a grid-wide
  *       Max-Coverage of one range (two launches per round) are replayed
  *       from a HIP graph built the second time the same round count and

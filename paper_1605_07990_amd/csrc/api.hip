@@ -1199,10 +1199,10 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         uint64_t target = 2 * nt;
         if (model == IM_LT && pool->count < target && ctx->dssa_draw_ahead > 1)
             target = std::max(target, std::min(most, 2 * nt * ctx->dssa_draw_ahead));
-        // likewise an IC run with k = 1, whose cover (one count and argmax)
-        // cannot hide a draw, while its draws are small: up to the largest
-        // 2 N_{t+j} within the minimum draw
-        if (model == IM_IC && k == 1 && pool->count < target)
+        // likewise an IC run while its draws are small (a small IC launch
+        // lasts about as long as its deepest samples, whatever its size): up
+        // to the largest 2 N_{t+j} within the minimum draw
+        if (model == IM_IC && pool->count < target)
             while (2 * target <= ctx->dssa_ic_min_draw && 2 * target <= most) target *= 2;
         const bool drew = pool->count < target;
         if (drew && (rc = join_ahead())) break;

@@ -90,7 +90,7 @@ struct im_ctx {
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
     uint32_t greedy_candidates_batch = 32;  // the engine's batched rounds
     uint32_t dssa_draw_ahead = 8;           // im_dssa on LT: a draw takes up to this many iterations' sets
-    uint64_t dssa_ic_min_draw = 131072;     // im_dssa on IC, k = 1: a draw takes later iterations' sets up to this many
+    uint64_t dssa_ic_min_draw = 262144;     // im_dssa on IC: a draw takes later iterations' sets up to this many
     double greedy_stall_rate = 0.15;  // running share of rounds that re-derive the candidates
     bool greedy_graph = false;        // replay cached graphs of a range's per-round launches
     uint64_t greedy_wg_cand_max_entries = ~0ull;  // ranges up to this many entries: one-workgroup candidate rounds

@@ -147,23 +147,24 @@ def test_dssa_draw_ahead_changes_nothing(im, ctx, oracle_lib, name, k, ahead):
 
 
 @pytest.mark.parametrize("name", ["nethept", "cl_mid", "rmat16"])
-@pytest.mark.parametrize("min_draw", [131072, 0, 4096])
-def test_dssa_ic_one_seed_draw_ahead_matches_oracle(im, ctx, oracle_lib, name, min_draw):
-    """IC D-SSA with k = 1 drawing later iterations' sets with the first
-    ones (up to the largest 2 N_t within the minimum draw) gives the
-    oracle's run, edges included: a run that stops inside a block drawn
-    ahead counts only the in-edges of the sets it used."""
+@pytest.mark.parametrize("min_draw", [262144, 0, 4096])
+def test_dssa_ic_draw_ahead_matches_oracle(im, ctx, oracle_lib, name, min_draw):
+    """IC D-SSA drawing later iterations' sets with the first ones (up to
+    the largest 2 N_t within the minimum draw) gives the oracle's run, edges
+    included: a run that stops inside a block drawn ahead counts only the
+    in-edges of the sets it used. k = 1 (no greedy rounds, no helpers) and
+    k = 20 (helpers covering drawn-ahead iterations)."""
     g = synth.make(name)
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
     og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
-    note(f"dssa IC k=1 min draw {min_draw} {name}")
+    note(f"dssa IC min draw {min_draw} {name}")
     old = ctx.get_param("dssa_ic_min_draw")
     try:
         ctx.set_param("dssa_ic_min_draw", min_draw)
-        for key, eps in ((0, 0.1), (7, 0.2), (11, 0.05)):
-            seeds, st = dg.dssa(0, 1, eps, 1.0 / g.n, key)
-            oseeds, ost = og.dssa(1, eps, 1.0 / g.n, key)
-            assert seeds.tolist() == oseeds.tolist()
+        for k, key, eps in ((1, 0, 0.1), (1, 7, 0.2), (1, 11, 0.05), (20, 3, 0.1), (20, 5, 0.2)):
+            seeds, st = dg.dssa(0, k, eps, 1.0 / g.n, key)
+            oseeds, ost = og.dssa(k, eps, 1.0 / g.n, key)
+            assert seeds.tolist() == oseeds.tolist(), (k, key)
             _compare(st, ost, "dssa")
     finally:
         ctx.set_param("dssa_ic_min_draw", old)
