@@ -334,7 +334,11 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *   IM_PARAM_DSSA_SPECULATE         1: im_dssa draws the next iteration's
  *       new RR sets on a second stream (own work buffers, from a helper
  *       thread) while the current iteration is covered, and drops them if
- *       it stops; 0: strictly one step after another (default 1);
+ *       it stops; 0: strictly one step after another (default 1). Runs
+ *       that draw ahead (LT with IM_PARAM_DSSA_DRAW_AHEAD above 1, IC with
+ *       IM_PARAM_DSSA_IC_MIN_DRAW above 0) never sample on the side, and
+ *       may then use three helpers for later iterations' covers instead of
+ *       two;
  *   IM_PARAM_GREEDY_MARK_MIN_CHUNKS per-round Max-Coverage launches on a
  *       graph with more than this many 64-node chunks have the cover step
  *       mark every chunk it touches and re-derive only those; on smaller
@@ -361,13 +365,14 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       identical whenever they are drawn; a launch lasts about as long as
  *       its longest walk), 1..64 (default 8; IC draws are not affected).
  *       While it is above 1, LT runs do not draw the next iteration's sets
- *       on the side (IM_PARAM_DSSA_SPECULATE applies to IC runs);
+ *       on the side;
  *   IM_PARAM_DSSA_IC_MIN_DRAW       when im_dssa on the IC model must draw
  *       the RR sets of iteration t, it also draws later iterations' sets in
  *       the same launches, up to the largest 2 N_{t+j} not above this many
  *       sets (a small IC launch lasts about as long as its deepest samples,
  *       whatever its size); 0 or a value below 2 N_t: no more than
- *       iteration t's (default 262144);
+ *       iteration t's (default 262144). While it is above 0, IC runs do not
+ *       draw the next iteration's sets on the side;
  *   IM_PARAM_GREEDY_GRAPH           1: the k rounds of a grid-wide
  *       Max-Coverage of one range (two launches per round) are replayed
  *       from a HIP graph built the second time the same round count and

@@ -1157,10 +1157,18 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
     // later iterations' covers running on helper contexts (slot i = helper
     // i); a slot still busy with a dropped cover of an earlier run is left
     // alone until it is done
-    // (an IC run with side sampling keeps one helper fewer: the run's
-    // stream, the side stream and two helpers fill the four hardware queues)
+    // Side sampling (the next iteration's new sets drawn on a second stream
+    // while this one is covered) is for runs that draw one iteration at a
+    // time: a run that draws ahead (LT, or IC with a minimum draw) has the
+    // next sets already, and a side draw it turns out not to need is still
+    // waited for at its end. A run that may sample on the side keeps one
+    // helper fewer (the run's stream, the side stream and two helpers fill
+    // the four hardware queues).
+    const bool draws_ahead =
+        (model == IM_LT && ctx->dssa_draw_ahead > 1) || (model == IM_IC && ctx->dssa_ic_min_draw > 0);
+    const bool side_sampling = ctx->speculate && !draws_ahead;
     AheadCover *ahead = ctx->dssa_greedy_ahead ? ahead_slots(ctx) : nullptr;
-    const uint32_t ahead_max = (model == IM_IC && ctx->speculate) ? kAheadSlots - 1 : kAheadSlots;
+    const uint32_t ahead_max = side_sampling ? kAheadSlots - 1 : kAheadSlots;
     // A run that draws ahead (LT) has every set a helper needs long before
     // it is covered and grows its pool rarely: helpers read the pool itself,
     // and every cover of the run is joined before the pool may move. Other
@@ -1213,13 +1221,10 @@ extern "C" im_status im_dssa(const im_graph *g, im_model model, uint32_t k, doub
         // covered (they are dropped if this iteration stops), when the cover
         // step is expected to take at least half as long as that draw: the
         // last iteration's cover time, or about 15 us per greedy round
-        // (not for LT drawing ahead: its next draw takes several iterations'
-        // sets at once, and a draw the run turns out not to need would still
-        // be waited for at the end)
+        // (not for runs that draw ahead, above)
         if (ms_fresh > 0) ms_draw = ms_fresh;
         const double est_cover = std::max(ms_cover_last, 0.015 * k);
-        const bool ahead_lt = model == IM_LT && ctx->dssa_draw_ahead > 1;
-        if (ctx->speculate && !ahead_lt && double(nt) < c.n_max && 2 * nt <= max_batch(model) &&
+        if (side_sampling && double(nt) < c.n_max && 2 * nt <= max_batch(model) &&
             est_cover >= ms_draw && pool->count < 4 * nt) {
             if (!aux_tried) {
                 aux_tried = true;

@@ -102,19 +102,22 @@ def test_query_errors(im, ctx):
 @pytest.mark.parametrize("name,model,k", [("rmat16", 1, 40), ("nethept", 0, 50), ("rmat20", 1, 100)])
 def test_dssa_speculation_changes_nothing(im, ctx, name, model, k):
     """Drawing the next iteration's sets on the second stream while the
-    current one is covered gives the same run as drawing them afterwards."""
+    current one is covered gives the same run as drawing them afterwards
+    (IC runs with their minimum draw off, which side sampling needs)."""
     g = synth.make(name)
     w = g.w_ic if model == 0 else g.w_lt
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w if model == 0 else None, w_lt=w if model == 1 else None)
     note(f"dssa speculation on/off {name}")
-    old = ctx.get_param("dssa_speculate")
+    old = ctx.get_param("dssa_speculate"), ctx.get_param("dssa_ic_min_draw")
     try:
+        ctx.set_param("dssa_ic_min_draw", 0)
         out = {}
         for flag in (1, 0):
             ctx.set_param("dssa_speculate", flag)
             out[flag] = [dg.dssa(model, k, 0.1, 1.0 / g.n, key) for key in (0, 1, 2)]
     finally:
-        ctx.set_param("dssa_speculate", old)
+        ctx.set_param("dssa_speculate", old[0])
+        ctx.set_param("dssa_ic_min_draw", old[1])
     for (s1, st1), (s0, st0) in zip(out[1], out[0]):
         assert s1.tolist() == s0.tolist()
         for key in ("iterations", "n_sets", "cov", "cov_c", "edges", "it_cov", "it_cov_c", "eps_t", "i_hat"):
