@@ -52,11 +52,13 @@ def lt_bytes(steps: int, sets: int) -> int:
     return 36 * steps + 8 * sets
 
 
-def ic_bytes(steps: int, nodes: int, sets: int) -> int:
+def ic_bytes(steps: int, nodes: int, sets: int, edge_bytes: int = 8) -> int:
     """Algorithmic bytes of IC sampling: per visited node 16 B of offsets and
-    4 B pool write, 8 B per in-edge examined, about 4 B of visited check per
-    newly reached node; 8 B per set offset."""
-    return 16 * nodes + 8 * steps + 4 * max(nodes - sets, 0) + 4 * nodes + 8 * sets
+    4 B pool write, 8 B per in-edge examined ({src, threshold}), about 4 B of
+    visited check per newly reached node; 8 B per set offset. With
+    edge_bytes=4: the same count for the compact form of a graph whose
+    in-edges of each node share one threshold (16 B node record, 4 B src)."""
+    return 16 * nodes + edge_bytes * steps + 4 * max(nodes - sets, 0) + 4 * nodes + 8 * sets
 
 
 def percentile(xs, q):
@@ -122,7 +124,7 @@ def gather_bandwidth(segs=(32, 64, 128, 256, 512), buffer_bytes: int = 16 << 30,
 
 
 def roofline(kt: dict, model: int, traffic_measured_here: bool = False, traffic_key: str = "",
-             steps: int | None = None, warmup: int | None = None) -> dict:
+             steps: int | None = None, warmup: int | None = None, compact: bool = False) -> dict:
     """Roofline of the main sampler kernel from its event timing: algorithmic
     bytes per launch over the mean launch duration, against HBM peak.
     `traffic` (HBM bytes per launch from the committed counter runs) is
@@ -146,6 +148,13 @@ def roofline(kt: dict, model: int, traffic_measured_here: bool = False, traffic_
             "avg_launch_ms": round(ms_per_launch, 5), "algorithmic_bytes_per_launch": round(bytes_per_launch),
            "sampler_sets_per_s": round(kt["sample_sets"] / sec) if sec else None,
            "sampler_steps_per_s": round(kt["sample_steps"] / sec) if sec else None}
+    if model == 0 and compact:
+        # the sampler read the compact form (4 B per in-edge, the threshold
+        # once per node): the same rate counted in the bytes it needs
+        cb = ic_bytes(kt["sample_steps"], kt["sample_nodes"], kt["sample_sets"], edge_bytes=4) / launches
+        ca = cb / (ms_per_launch * 1e-3) / 1e9 if ms_per_launch > 0 else 0.0
+        out["compact_form"] = {"algorithmic_bytes_per_launch": round(cb), "achieved": round(ca, 2),
+                               "frac": round(ca / HBM_PEAK_GBS, 5)}
     if model == 0 and kt.get("group_launches"):
         out["workgroup_tier"] = {"ms_per_launch": round(kt["group_ms"] / kt["group_launches"], 5),
                                  "samples": kt["group_samples"], "edges": kt["group_edges"],
@@ -320,7 +329,7 @@ def run_pokec64(args, im, ctx, sync):
                       "k": "log-uniform [1,500]", "eps": [0.05, 0.1, 0.2], "delta": "1/n", "queries_per_step": 64},
            "edges_per_s": round(edges / dt, 1), "p50_ms": round(percentile(lat, 50), 3),
            "p99_ms": round(percentile(lat, 99), 3), "rr_sets_per_step": sets // max(args.steps, 1),
-           "roofline": roofline(kt, 0)}
+           "roofline": roofline(kt, 0, compact=bool(dg.info()[2] & 4) and ctx.get_param("ic_compact") == 1)}
     if args.compare_plain:
         # the same 64 queries one after another through im_ssa
         sync()
@@ -466,7 +475,8 @@ def run_twitter(args, im, ctx, sync):
            "roofline": roofline(kt, 0, traffic_measured_here=(not args.engine and args.ks is None and not args.param
                                                               and not args.no_speculate
                                                               and args.greedy_wg_max_entries is None),
-                                traffic_key="ic_sampler_twitter", steps=args.steps, warmup=args.warmup)}
+                                traffic_key="ic_sampler_twitter", steps=args.steps, warmup=args.warmup,
+                                compact=bool(dg.info()[2] & 4) and ctx.get_param("ic_compact") == 1)}
     if args.engine:
         out["config"]["workload"] += ", concurrent through the engine"
     if not args.no_batching_compare:

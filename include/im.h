@@ -104,7 +104,11 @@ im_status im_graph_set_source_weights(im_graph *g, const uint32_t *node_w);
 void im_graph_free(im_graph *g);
 
 /* Graph properties: n, m, which models it holds weights for (bit 0 IC,
- * bit 1 LT). */
+ * bit 1 LT) and bit 2: every node's IC in-edges share one threshold (the
+ * weighted cascade w(u,v) = 1/d_in(v) of Section 7 is such a graph), so
+ * the device also holds the compact IC form: per node {first in-edge,
+ * in-degree, thr} in 16 bytes, per edge its u32 src. IC draws read that
+ * form (IM_PARAM_IC_COMPACT); their sets are the same in either form. */
 im_status im_graph_info(const im_graph *g, uint32_t *n, uint64_t *m, uint32_t *models);
 
 /*
@@ -427,7 +431,11 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       fewer entries than half the graph's nodes runs over the nodes the range
  *       holds, numbered by rank in id order (the same picks: a node outside
  *       the range has gain 0, and the rounds after every set is covered
- *       take the lowest unpicked ids); 0: over all n nodes (default 1).
+ *       take the lowest unpicked ids); 0: over all n nodes (default 1);
+ *   IM_PARAM_IC_COMPACT            1: IC draws on a graph that holds the
+ *       compact IC form (im_graph_info bit 2) read it: 16 bytes per
+ *       expanded node and 4 per examined in-edge, against 16 + 8; 0: the
+ *       {src, thr} records (default 1). The sets drawn are the same.
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {
@@ -448,7 +456,8 @@ typedef enum {
     IM_PARAM_IC_PLAIN = 14,
     IM_PARAM_GREEDY_FLAT_LEVELS = 15,
     IM_PARAM_GREEDY_DENSE = 16,
-    IM_PARAM_DSSA_IC_MIN_DRAW = 17
+    IM_PARAM_DSSA_IC_MIN_DRAW = 17,
+    IM_PARAM_IC_COMPACT = 18
 } im_param;
 im_status im_ctx_set_param(im_ctx *ctx, im_param param, uint64_t value);
 im_status im_ctx_get_param(const im_ctx *ctx, im_param param, uint64_t *value);

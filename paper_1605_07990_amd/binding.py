@@ -45,6 +45,7 @@ IM_PARAM_DSSA_GREEDY_AHEAD, IM_PARAM_GREEDY_WG_CAND_BATCH, IM_PARAM_IC_PLAIN = 1
 IM_PARAM_GREEDY_FLAT_LEVELS = 15
 IM_PARAM_GREEDY_DENSE = 16
 IM_PARAM_DSSA_IC_MIN_DRAW = 17
+IM_PARAM_IC_COMPACT = 18
 PARAMS = {"greedy_cover_blocks": IM_PARAM_GREEDY_COVER_BLOCKS, "ic_edge_budget": IM_PARAM_IC_EDGE_BUDGET, "greedy_wg_max_entries": IM_PARAM_GREEDY_WG_MAX_ENTRIES, "ic_ticket_block": IM_PARAM_IC_TICKET_BLOCK,
           "dssa_speculate": IM_PARAM_DSSA_SPECULATE, "greedy_mark_min_chunks": IM_PARAM_GREEDY_MARK_MIN_CHUNKS,
           "greedy_candidates": IM_PARAM_GREEDY_CANDIDATES, "greedy_candidates_batch": IM_PARAM_GREEDY_CANDIDATES_BATCH,
@@ -54,7 +55,8 @@ PARAMS = {"greedy_cover_blocks": IM_PARAM_GREEDY_COVER_BLOCKS, "ic_edge_budget":
           "dssa_greedy_ahead": IM_PARAM_DSSA_GREEDY_AHEAD,
           "greedy_wg_cand_batch": IM_PARAM_GREEDY_WG_CAND_BATCH,
           "ic_plain": IM_PARAM_IC_PLAIN, "greedy_flat_levels": IM_PARAM_GREEDY_FLAT_LEVELS,
-          "greedy_dense": IM_PARAM_GREEDY_DENSE, "dssa_ic_min_draw": IM_PARAM_DSSA_IC_MIN_DRAW}
+          "greedy_dense": IM_PARAM_GREEDY_DENSE, "dssa_ic_min_draw": IM_PARAM_DSSA_IC_MIN_DRAW,
+          "ic_compact": IM_PARAM_IC_COMPACT}
 
 IM_ALGO_SSA, IM_ALGO_DSSA, IM_ALGO_ESTIMATE = 0, 1, 2
 ALGOS = {"ssa": IM_ALGO_SSA, "dssa": IM_ALGO_DSSA, IM_ALGO_SSA: IM_ALGO_SSA, IM_ALGO_DSSA: IM_ALGO_DSSA}

@@ -331,15 +331,11 @@ im_status aux_ctx(im_ctx *ctx, im_ctx **out) {
         IM_HIP(hipEventCreate(&a->ev_group));
     }
     a->timing = ctx->timing;
-    a->greedy_wg_max_entries = ctx->greedy_wg_max_entries;
-    a->greedy_mark_min_chunks = ctx->greedy_mark_min_chunks;
-    a->greedy_cover_blocks = ctx->greedy_cover_blocks;
+    copy_greedy_params(ctx, a);
     a->ic_edge_budget = ctx->ic_edge_budget;
-    a->greedy_candidates = ctx->greedy_candidates;
-    a->greedy_candidates_batch = ctx->greedy_candidates_batch;
     a->ic_ticket_block = ctx->ic_ticket_block;
-    a->greedy_wg_cand_max_entries = ctx->greedy_wg_cand_max_entries;
-    a->greedy_wg_cand_grid_rounds = ctx->greedy_wg_cand_grid_rounds;
+    a->ic_plain = ctx->ic_plain;
+    a->ic_compact = ctx->ic_compact;
     *out = a;
     return IM_OK;
 }
@@ -520,6 +516,10 @@ extern "C" im_status im_ctx_set_param(im_ctx *c, im_param param, uint64_t value)
     case IM_PARAM_DSSA_IC_MIN_DRAW:
         c->dssa_ic_min_draw = value;
         return IM_OK;
+    case IM_PARAM_IC_COMPACT:
+        if (value > 1) break;
+        c->ic_compact = value != 0;
+        return IM_OK;
     }
     set_error("im_ctx_set_param: bad parameter %d or value %llu", int(param), static_cast<unsigned long long>(value));
     return IM_E_ARG;
@@ -582,6 +582,9 @@ extern "C" im_status im_ctx_get_param(const im_ctx *c, im_param param, uint64_t 
         return IM_OK;
     case IM_PARAM_DSSA_IC_MIN_DRAW:
         *value = c->dssa_ic_min_draw;
+        return IM_OK;
+    case IM_PARAM_IC_COMPACT:
+        *value = c->ic_compact ? 1 : 0;
         return IM_OK;
     }
     set_error("im_ctx_get_param: bad parameter %d", int(param));
@@ -678,6 +681,8 @@ extern "C" void im_graph_free(im_graph *g) {
     dev_free(g->ctx, g->off);
     dev_free(g->ctx, g->edges_ic);
     dev_free(g->ctx, g->edges_lt);
+    dev_free(g->ctx, g->nodes_ic);
+    dev_free(g->ctx, g->srcs_ic);
     dev_free(g->ctx, g->src_cum);
     delete g;
 }

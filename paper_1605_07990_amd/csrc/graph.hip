@@ -11,6 +11,15 @@
 //         taken left to right in FP64 over the node's in-edges; in-edge i
 //         is the one kept iff thr_{i-1} <= coin < thr_i (the live-edge form
 //         of the threshold model, Kempe et al. 2003).
+//
+// When every in-edge of each node carries the same IC threshold (the
+// weighted cascade w(u,v) = 1/d_in(v) of the paper's experiments is one
+// such case) the IC sampler reads a second, compact form:
+//   nodes[v] = {first in-edge (low, high word), in-degree, threshold}, one
+//     aligned 16-byte load per expanded node instead of the offset pair;
+//   srcs[e] = src of edge e (4 bytes instead of 8), padded like the records.
+// The coins are compared with the same thresholds, so the sets drawn are
+// the same in either form.
 #include "im_device.hpp"
 #include "im_internal.hpp"
 
@@ -20,6 +29,7 @@ constexpr uint32_t kBadId = 1u;
 constexpr uint32_t kBadOrder = 2u;
 constexpr uint32_t kBadWeight = 4u;
 constexpr uint32_t kLtSum = 8u;
+constexpr uint32_t kIcMixed = 16u;  // some node's IC in-edges differ in threshold
 
 struct BuildCounters {
     uint32_t flags;
@@ -73,6 +83,33 @@ __global__ void ic_edges_kernel(const uint32_t *src, const float *w, uint64_t m,
     for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
         edges[e] = e < m ? make_uint2(src[e], to_threshold(static_cast<double>(w[e]))) : make_uint2(0u, 0u);
+    }
+}
+
+// Whether some node's in-edges carry different IC thresholds: edge e is
+// compared with edge e-1 when both enter the same node.
+__global__ void ic_uniform_kernel(const uint32_t *dst, const uint2 *edges, uint64_t m, BuildCounters *cnt) {
+    bool mixed = false;
+    for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x + 1; e < m;
+         e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        mixed |= dst[e] == dst[e - 1] && edges[e].y != edges[e - 1].y;
+    if (__ballot(mixed) != 0 && imd::lane_id() == 0) atomicOr(&cnt->flags, kIcMixed);
+}
+
+// The compact IC form: sources padded to whole groups, and per node its
+// first in-edge, in-degree and threshold (0 for a node with no in-edges).
+__global__ void ic_compact_srcs_kernel(const uint2 *edges, uint64_t m, uint32_t *srcs) {
+    const uint64_t total = ic_records(m);
+    for (uint64_t e = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        srcs[e] = e < m ? edges[e].x : 0u;
+}
+
+__global__ void ic_compact_nodes_kernel(const uint64_t *off, const uint2 *edges, uint32_t n, uint4 *nodes) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint64_t a = off[v], b = off[v + 1];
+        nodes[v] = make_uint4(static_cast<uint32_t>(a), static_cast<uint32_t>(a >> 32), static_cast<uint32_t>(b - a),
+                              b > a ? edges[a].y : 0u);
     }
 }
 
@@ -200,7 +237,10 @@ im_status graph_build(im_graph *g, const uint32_t *src_h, const uint32_t *dst_h,
         return IM_E_ARG;
     }
     offsets_kernel<<<grid_for(m + 1, cu), 256, 0, st>>>(d32, m, n, off);
-    if (w_ic_h) ic_edges_kernel<<<grid_for(ic_records(m), cu), 256, 0, st>>>(s32, wic, m, static_cast<uint2 *>(g->edges_ic.ptr));
+    if (w_ic_h) {
+        ic_edges_kernel<<<grid_for(ic_records(m), cu), 256, 0, st>>>(s32, wic, m, static_cast<uint2 *>(g->edges_ic.ptr));
+        if (m > 1) ic_uniform_kernel<<<grid_for(m, cu), 256, 0, st>>>(d32, static_cast<const uint2 *>(g->edges_ic.ptr), m, cnt);
+    }
     if (w_lt_h) {
         lt_edges_kernel<<<grid_for(n, cu), 256, 0, st>>>(s32, wlt, off, n, static_cast<uint2 *>(g->edges_lt.ptr), cnt);
     } else {
@@ -213,8 +253,19 @@ im_status graph_build(im_graph *g, const uint32_t *src_h, const uint32_t *dst_h,
         set_error("im_graph_load: LT in-weights of some node sum above 1");
         return IM_E_LT_WEIGHTS;
     }
+    if (w_ic_h && !(hc.flags & kIcMixed)) {
+        IM_TRY(dev_alloc(ctx, g->srcs_ic, ic_records(m) * 4));
+        IM_TRY(dev_alloc(ctx, g->nodes_ic, size_t(n) * 16));
+        const auto *rec = static_cast<const uint2 *>(g->edges_ic.ptr);
+        ic_compact_srcs_kernel<<<grid_for(ic_records(m), cu), 256, 0, st>>>(rec, m, static_cast<uint32_t *>(g->srcs_ic.ptr));
+        ic_compact_nodes_kernel<<<grid_for(n, cu), 256, 0, st>>>(off, rec, n, static_cast<uint4 *>(g->nodes_ic.ptr));
+        if ((e = hipGetLastError()) || (e = hipStreamSynchronize(st))) {
+            set_error("compact IC form: %s", hipGetErrorString(e));
+            return IM_E_DEVICE;
+        }
+    }
     g->max_in = hc.max_in;
-    g->models = (w_ic_h ? 1u : 0u) | (w_lt_h ? 2u : 0u);
+    g->models = (w_ic_h ? 1u : 0u) | (w_lt_h ? 2u : 0u) | (g->nodes_ic.ptr ? 4u : 0u);
     return IM_OK;
 }
 

@@ -85,6 +85,7 @@ struct im_ctx {
     uint32_t greedy_cover_blocks = 0;  // 0: automatic
     uint32_t ic_edge_budget = 16384;
     bool ic_plain = false;  // IC draws as plain launches (static assignment, no workgroup tiers)
+    bool ic_compact = true;  // IC draws read the graph's compact form when it has one
     bool greedy_flat_levels = true;  // flat gains: rounds by gain level instead of grid-wide rounds
     bool greedy_dense = true;        // a range holding few of the nodes: the greedy over the nodes it holds
     uint32_t greedy_candidates = 0;         // one range; 0: two launches per grid-wide round
@@ -139,6 +140,10 @@ struct im_graph {
     DevBuf off;                  // u64[n+1]
     DevBuf edges_ic;             // uint2 {src, thr}: m records, then zero records to whole 4-edge groups + 4
     DevBuf edges_lt;             // uint2[m] {src, cumulative thr}
+    // IC thresholds that depend only on the target node: the compact form
+    // (empty otherwise)
+    DevBuf nodes_ic;             // uint4[n] {first in-edge low, high, in-degree, thr}
+    DevBuf srcs_ic;              // u32 src per edge, zero-padded like edges_ic
     DevBuf src_cum;              // u64[n+1] cumulative integer source weights, or empty
     uint64_t src_total = 0;      // sum of the source weights (0: uniform sources)
     // IC, LT: mean RR-set size of the last draw (a staging estimate; draws of

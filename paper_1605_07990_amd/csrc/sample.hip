@@ -126,6 +126,10 @@ struct Params {
     uint32_t *ho_small;     // IC: hand-over records of the small workgroup tier (kHoStrideSmall words each)
     uint32_t ho_wave_cap;   // records available in each (0: none)
     uint32_t ho_small_cap;
+    // IC: the graph's compact form (null: read off and the records); the
+    // long path always reads off and the records
+    const uint4 *nodes;     // {first in-edge low, high, in-degree, thr}
+    const uint32_t *srcs;   // src per edge, zero-padded to whole groups + 4
 };
 
 // The work item owning global slot t.
@@ -230,6 +234,22 @@ __global__ void init_counters_kernel(Counters *c, unsigned long long cursor0) {
 
 // ---------------------------------------------------------------- IC ----
 
+// In-edges [a, a + deg) of frontier node v and, in the compact form, the
+// threshold they share (one aligned 16-byte load instead of the offset
+// pair).
+__device__ __forceinline__ void ic_node(const Params &p, uint32_t v, uint64_t &a, uint32_t &deg, uint32_t &thr) {
+    if (p.nodes) {
+        const uint4 r = p.nodes[v];
+        a = static_cast<uint64_t>(r.x) | (static_cast<uint64_t>(r.y) << 32);
+        deg = r.z;
+        thr = r.w;
+    } else {
+        a = p.off[v];
+        deg = static_cast<uint32_t>(p.off[v + 1] - a);
+        thr = 0u;
+    }
+}
+
 // The live edges among the four in-edge records of 4-edge group g of a node
 // whose in-edges are [ea, eb). The group's 32 bytes come in two 16-byte
 // loads (the record array is padded to whole aligned groups, so they stay
@@ -255,6 +275,34 @@ __device__ __forceinline__ void ic_group_live(const uint2 *edges, uint64_t g, ui
     for (uint32_t q = 0; q < 4; ++q) {
         const uint64_t e = (g << 2) + q;
         live[q] = (e >= ea) & (e < eb) & ic_live(word_of(coins, q), rec[q].y);
+    }
+}
+
+// ic_group_live on either form: in the compact one the group's four
+// sources are one aligned 16-byte load and `thr` is the node's threshold.
+__device__ __forceinline__ void ic_group_read(const Params &p, uint64_t g, uint64_t ea, uint64_t eb, uint32_t thr,
+                                              const uint4 &coins, uint2 (&rec)[4], bool (&live)[4]) {
+    if (!p.srcs) {
+        ic_group_live(p.edges, g, ea, eb, coins, rec, live);
+        return;
+    }
+    if (eb <= ea) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            rec[q] = make_uint2(0u, 0u);
+            live[q] = false;
+        }
+        return;
+    }
+    const uint4 s4 = reinterpret_cast<const uint4 *>(p.srcs)[g];
+    rec[0] = make_uint2(s4.x, thr);
+    rec[1] = make_uint2(s4.y, thr);
+    rec[2] = make_uint2(s4.z, thr);
+    rec[3] = make_uint2(s4.w, thr);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint64_t e = (g << 2) + q;
+        live[q] = (e >= ea) & (e < eb) & ic_live(word_of(coins, q), thr);
     }
 }
 
@@ -347,7 +395,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
     __shared__ uint32_t s_vis[kIcWaves][kIcHcap];
     __shared__ uint32_t s_pre[kIcWaves][kWave];
     __shared__ uint64_t s_a[kIcWaves][kWave];
-    __shared__ uint64_t s_b[kIcWaves][kWave];
+    __shared__ uint2 s_b[kIcWaves][kWave];  // {in-degree, thr}
 
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x / kWave;
@@ -355,7 +403,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
     uint32_t *vis = s_vis[wave];
     uint32_t *pre = s_pre[wave];
     uint64_t *fa = s_a[wave];
-    uint64_t *fb = s_b[wave];
+    uint2 *fb = s_b[wave];
     for (uint32_t i = lane; i < kIcHcap; i += kWave) vis[i] = 0u;
     wave_sync();
     uint64_t edges_acc = 0, nodes_acc = 0;
@@ -409,15 +457,13 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
             tb = tail;
             eb = sample_edges;
             const uint32_t nb = min(tail - head, static_cast<uint32_t>(kWave));
-            uint32_t cg = 0;
-            uint64_t a = 0, b = 0;
+            uint32_t cg = 0, deg = 0, thr = 0;
+            uint64_t a = 0;
             if (lane < nb) {
-                const uint32_t v = queue[head + lane];
-                a = p.off[v];
-                b = p.off[v + 1];
-                if (b > a) cg = static_cast<uint32_t>(((b - 1) >> 2) - (a >> 2) + 1);
+                ic_node(p, queue[head + lane], a, deg, thr);
+                if (deg) cg = static_cast<uint32_t>(((a + deg - 1) >> 2) - (a >> 2) + 1);
             }
-            const uint64_t batch_edges = wave_sum_small_u64(b - a);
+            const uint64_t batch_edges = wave_sum_small_u64(deg);
             // a workgroup finishes a sample that would examine more in-edges
             // than the budget; checked before the batch is expanded, so that
             // a batch holding a high in-degree node (hundreds of thousands of
@@ -431,7 +477,7 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
             const uint32_t groups = wave_scan_total(inc);
             pre[lane] = inc - cg;
             fa[lane] = a;
-            fb[lane] = b;
+            fb[lane] = make_uint2(deg, thr);
             head += nb;
             wave_sync();
 
@@ -447,12 +493,14 @@ __global__ __launch_bounds__(kIcWaves *kWave) void ic_main_kernel(Params p) {
                         if (pre[mid] <= w) lo = mid;
                         else hi = mid - 1;
                     }
-                    const uint64_t ea = fa[lo], eb = fb[lo];
+                    const uint64_t ea = fa[lo];
+                    const uint2 db = fb[lo];
+                    const uint64_t eb = ea + db.x;
                     const uint64_t g = (ea >> 2) + (w - pre[lo]);
                     const uint4 coins = ic_coins(st, s, g);
                     uint2 rec[4];
                     bool live[4];
-                    ic_group_live(p.edges, g, ea, eb, coins, rec, live);
+                    ic_group_read(p, g, ea, eb, db.y, coins, rec, live);
                     // the first probes of the four records go out together;
                     // a probe that meets another node goes on alone
                     uint32_t old[4];
@@ -848,7 +896,7 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
     __shared__ uint32_t s_vis[kGrpHcap];
     __shared__ uint64_t s_pre[kGrpThreads];
     __shared__ uint64_t s_a[kGrpThreads];
-    __shared__ uint64_t s_b[kGrpThreads];
+    __shared__ uint2 s_b[kGrpThreads];  // {in-degree, thr}
     __shared__ uint64_t s_scan[kGrpThreads / kWave];
     __shared__ unsigned long long s_edges;
     __shared__ uint32_t s_t, s_d, s_tail, s_flags;  // flags: 1 hit, 2 too large
@@ -908,21 +956,20 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
             eb = s_edges;  // this batch's edges are added after the scan's barriers
             ++levels;
             const uint32_t nb = min(tail - head, static_cast<uint32_t>(kGrpThreads));
-            uint64_t a = 0, b = 0, cg = 0;
+            uint64_t a = 0, cg = 0;
+            uint32_t deg = 0, thr = 0;
             if (tid < nb) {
-                const uint32_t v = s_queue[head + tid];
-                a = p.off[v];
-                b = p.off[v + 1];
-                if (b > a) cg = ((b - 1) >> 2) - (a >> 2) + 1;
+                ic_node(p, s_queue[head + tid], a, deg, thr);
+                if (deg) cg = ((a + deg - 1) >> 2) - (a >> 2) + 1;
             }
-            const uint64_t de = b - a;
+            const uint64_t de = deg;
             uint64_t groups = 0;
             const uint64_t pre = block_scan_excl(cg, s_scan, groups);
             // after the scan's barriers: every thread has read s_edges above
             if (de) atomicAdd(&s_edges, static_cast<unsigned long long>(de));
             s_pre[tid] = pre;
             s_a[tid] = a;
-            s_b[tid] = b;
+            s_b[tid] = make_uint2(deg, thr);
             __syncthreads();
             head += nb;
             for (uint64_t w = tid; w < groups; w += blockDim.x) {
@@ -933,13 +980,15 @@ __global__ __launch_bounds__(Tier::kThreads) void ic_group_kernel(Params p, cons
                     if (s_pre[mid] <= w) lo = mid;
                     else hi = mid - 1;
                 }
-                const uint64_t ea = s_a[lo], eb = s_b[lo];
+                const uint64_t ea = s_a[lo];
+                const uint2 db = s_b[lo];
+                const uint64_t eb = ea + db.x;
                 const uint64_t g = (ea >> 2) + (w - s_pre[lo]);
                 const uint4 coins = ic_coins(st, s, g);
                 bool full = false;
                 uint2 rec[4];
                 bool live[4];
-                ic_group_live(p.edges, g, ea, eb, coins, rec, live);
+                ic_group_read(p, g, ea, eb, db.y, coins, rec, live);
                 uint32_t old[4];
 #pragma unroll
                 for (uint32_t q = 0; q < 4; ++q) old[q] = live[q] ? grp_probe<kGrpHbits>(s_vis, rec[q].x) : 0u;
@@ -1498,6 +1547,10 @@ im_status sample_items(im_ctx *ctx, const im_graph *g, im_model model, const Sam
         p.ho_wave = ho_wave_cap ? static_cast<uint32_t *>(ctx->handoff.ptr) : nullptr;
         p.ho_small = ho_small_cap ? p.ho_wave + uint64_t(ho_wave_cap) * kHoStrideWave : nullptr;
         p.ho_wave_cap = ho_wave_cap;
+        if (model == IM_IC && ctx->ic_compact && g->nodes_ic.ptr) {
+            p.nodes = static_cast<const uint4 *>(g->nodes_ic.ptr);
+            p.srcs = static_cast<const uint32_t *>(g->srcs_ic.ptr);
+        }
         p.ho_small_cap = ho_small_cap;
 
         init_counters_kernel<<<1, 1, 0, st>>>(cnt, lt_regions);

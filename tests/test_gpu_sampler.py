@@ -330,3 +330,51 @@ def test_fused_pools_argument_errors(im, ctx):
         im.Pool.sample_multi([a, a], [5, 5])  # a pool twice
     assert e.value.status == -1
     assert a.count == 0 and b.count == 0
+
+
+@pytest.mark.parametrize("name", ["nethept", "heavy6000", "rmat12", "nethept_mixed"])
+def test_compact_ic_form_matches_records_and_oracle(im, ctx, oracle_lib, name):
+    """Graphs whose IC in-edges of each node share one threshold (weighted
+    cascade, a constant p) hold the compact IC form (graph info bit 2) and
+    IC draws read it; the sets must be the oracle's and the same as from the
+    {src, thr} records (IM_PARAM_IC_COMPACT = 0), in pool and hits mode.
+    Graphs with mixed thresholds (trivalency; weighted cascade with one
+    weight changed) hold no compact form."""
+    if name == "heavy6000":
+        n, deg = 6000, 40
+        rng = np.random.default_rng(n + deg)
+        dst = np.repeat(np.arange(n, dtype=np.uint32), deg)
+        src = rng.integers(0, n, size=n * deg).astype(np.uint32)
+        keep = src != dst
+        pairs = np.unique(np.stack([dst[keep], src[keep]], axis=1), axis=0)
+        g = synth.from_edges(name, n, pairs[:, 1], pairs[:, 0], w_ic=np.full(pairs.shape[0], 0.3, dtype=np.float32))
+        w, uniform, count = g.w_ic, True, 300
+    else:
+        g = synth.make("nethept" if name == "nethept_mixed" else name)
+        w, uniform, count = g.w_ic, name != "rmat12", 20000
+        if name == "nethept_mixed":
+            # one in-edge of a node with several gets another weight
+            indeg = np.bincount(g.dst, minlength=g.n)
+            e = int(np.flatnonzero(indeg[g.dst] > 3)[0])
+            w = g.w_ic.copy()
+            w[e] = np.float32(min(1.0, float(w[e]) * 2.0))
+            uniform = False
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w)
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, w)
+    assert bool(dg.info()[2] & 4) == uniform
+    note(f"compact IC form {name} uniform={uniform} count={count}")
+    op = oracle_lib.Pool(og, 31)
+    op.extend(count)
+    seeds = np.array([0, 1], dtype=np.uint32)
+    est = og.estimate_inf(seeds, 0.2, 0.1, 5000.0, 99)
+    assert ctx.get_param("ic_compact") == 1
+    try:
+        for compact in (1, 0):
+            ctx.set_param("ic_compact", compact)
+            pool = im.Pool(dg, 0, 31)
+            pool.sample(count // 3)
+            pool.sample(count - count // 3)  # an append
+            assert_pool_equal(pool, op, 0, count)
+            assert dg.estimate_inf(0, seeds, 0.2, 0.1, 5000.0, 99) == est
+    finally:
+        ctx.set_param("ic_compact", 1)
