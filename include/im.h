@@ -400,8 +400,9 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *       stream and thread, once the pool holds their sets: iteration t's
  *       Max-Coverage reads only R_t, so the result is the one the iteration
  *       would compute; if the run stops first it is dropped and im_dssa
- *       returns without waiting for it (see im_ctx_sync). The pool never
- *       grows while a helper runs (default 3);
+ *       returns without waiting for it (see im_ctx_sync). A helper covers
+ *       its own copy of R_t, except in LT runs that draw ahead, whose pool
+ *       does not grow while a helper reads it (default 3);
  *   IM_PARAM_GREEDY_WG_CAND_BATCH  the engine's batched Max-Coverage runs
  *       IM_PARAM_GREEDY_WG_CAND_GRID_ROUNDS grid-wide rounds and then
  *       one-workgroup rounds over candidate nodes, a workgroup per query,
