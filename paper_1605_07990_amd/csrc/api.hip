@@ -638,7 +638,8 @@ extern "C" void im_ctx_free(im_ctx *c) {
     if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
     free_round_graphs(c);
     for (DevBuf *b : {&c->stage, &c->sample_meta, &c->handoff, &c->counters, &c->scan_tmp, &c->slots, &c->cover, &c->seedbits, &c->flat,
-                      &c->prefix_off, &c->prefix_nodes, &c->dense, &c->zflags, &c->lt_tables, &c->items, &c->append_dst})
+                      &c->prefix_off, &c->prefix_nodes, &c->dense, &c->zflags, &c->lt_tables, &c->items, &c->append_dst,
+                      &c->k1_cnt})
         dev_free(c, *b);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     if (c->owns_stream) (void)hipStreamDestroy(c->stream);
@@ -711,6 +712,8 @@ extern "C" im_status im_pool_create(im_ctx *ctx, const im_graph *g, im_model mod
     }
     auto *p = new (std::nothrow) im_pool();
     if (!p) return IM_E_OOM;
+    static std::atomic<uint64_t> pools_made{0};
+    p->serial = pools_made.fetch_add(1, std::memory_order_relaxed) + 1;
     p->ctx = ctx;
     p->g = g;
     p->model = model;

@@ -2640,6 +2640,37 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
     IM_TRY(to_host_sync(ctx, &ends[1], poff + end, 8));
     const uint64_t ebegin = ends[0], eend = ends[1];
     const uint64_t entries = eend - ebegin;
+    if (k == 1 && begin == 0) {
+        // one round over a prefix [0, end): SSA and D-SSA ask for prefixes
+        // of one pool that double, so the counts of the last prefix are kept
+        // and only the new sets' entries are added (integer counts: the
+        // result is the full count's)
+        const void *was = ctx->k1_cnt.ptr;
+        IM_TRY(dev_reserve(ctx, ctx->k1_cnt, 4ull * n + 256));
+        auto *cnt = static_cast<uint32_t *>(ctx->k1_cnt.ptr);
+        auto *key = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->k1_cnt.ptr) +
+                                                           ((4ull * n + 255) & ~255ull));
+        hipStream_t st = ctx->stream;
+        const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+        uint64_t from = ctx->k1_end;
+        if (ctx->k1_cnt.ptr != was || ctx->k1_serial != p->serial || eend < ctx->k1_end) {
+            fill_u32_kernel<<<grid_of(n, kThreads, cu * 8), kThreads, 0, st>>>(cnt, n, 0u);
+            from = 0;
+        }
+        ctx->k1_serial = 0;  // until the counts below are in
+        fill_u64_kernel<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t *>(key), 1, 0);
+        if (eend > from)
+            histogram_kernel<<<grid_of(eend - from, kThreads, cu * 16), kThreads, 0, st>>>(pnodes, from, eend, cnt);
+        argmax_count_kernel<<<grid_of(n, kThreads, cu * 8), kThreads, 0, st>>>(cnt, n, key);
+        IM_HIP(hipGetLastError());
+        unsigned long long h = 0;
+        IM_TRY(to_host_sync(ctx, &h, key, 8));
+        ctx->k1_serial = p->serial;
+        ctx->k1_end = eend;
+        seeds_host[0] = ~static_cast<uint32_t>(h);
+        *cov = h >> 32;
+        return IM_OK;
+    }
     // the ranked form once the range holds fewer entries than half the nodes
     // (k = 1 is one count and argmax over the nodes, no cheaper that way)
     if (ctx->greedy_dense && k > 1 && entries && 2 * entries <= n)

@@ -68,6 +68,11 @@ struct im_ctx {
     uint32_t lt_lanes = 0;    // lanes the tables cover
     uint64_t lt_stamp = 1;    // next LT walk stamp (never 0: zeroed entries are free)
     DevBuf cover;        // incidence / greedy working arrays
+    // Max-Coverage with k = 1 over growing prefixes of one pool: the counts
+    // of node entries [0, k1_end) of pool k1_serial, then the argmax key
+    DevBuf k1_cnt;
+    uint64_t k1_serial = 0;  // 0: no counts held
+    uint64_t k1_end = 0;
     DevBuf seedbits;     // seed-set bitmap (n bits)
     DevBuf flat;         // greedy rounds by gain level: state, node lists, tile counts
     DevBuf dense;        // greedy over the nodes a range holds: node bitmap, ranks, ranked entries, ids
@@ -172,6 +177,7 @@ struct im_pool {
     DevBuf poff;             // u64[cap_sets+1]
     DevBuf pnodes;           // u32[cap_nodes]
     double mean_size = 0.0;  // running mean set size (staging estimate)
+    uint64_t serial = 0;     // unique per pool made (a copy of a prefix keeps it: same sets)
 };
 
 namespace im {

@@ -308,3 +308,34 @@ def test_greedy_over_held_nodes_matches_oracle(im, ctx, oracle_lib, dense):
             assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (begin, end, k)
     finally:
         ctx.set_param("greedy_dense", old)
+
+
+def test_one_seed_over_growing_prefixes(im, ctx, oracle_lib):
+    """Max-Coverage with k = 1 over a prefix [0, end) keeps the node counts
+    of the last prefix of the same pool and adds only the new sets' entries
+    (SSA and D-SSA double their prefixes). Every answer must be the oracle's:
+    growing, repeated and shrinking prefixes, a range not at 0, another
+    pool in between, and a prefix reaching sets appended after the last
+    call."""
+    g = synth.make("nethept")
+    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
+    og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
+    p, q = im.Pool(dg, 0, 41), im.Pool(dg, 0, 42)
+    op, oq = oracle_lib.Pool(og, 41), oracle_lib.Pool(og, 42)
+    p.sample(20000)
+    op.extend(30000)
+    q.sample(5000)
+    oq.extend(5000)
+    note("k = 1 over growing prefixes")
+    steps = [(p, op, 0, 1000), (p, op, 0, 4000), (p, op, 0, 4000), (q, oq, 0, 3000), (p, op, 0, 16000),
+             (p, op, 1000, 5000), (p, op, 0, 20000), (p, op, 0, 2000), (p, op, 0, 8000), (q, oq, 0, 5000)]
+    def same(pool, opool, begin, end):
+        seeds, cov = pool.max_coverage(1, begin, end)
+        oseeds, ocov = opool.max_coverage(1, begin, end)
+        assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (pool.key, begin, end)
+
+    for pool, opool, begin, end in steps:
+        same(pool, opool, begin, end)
+    p.sample(10000)  # appended: the next prefix holds sets drawn after the counts were taken
+    same(p, op, 0, 30000)
+    same(p, op, 0, 25000)

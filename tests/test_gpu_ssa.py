@@ -39,6 +39,7 @@ def _compare(st, ost, algo):
 @pytest.mark.parametrize("algo,name,model,k,eps,key", [
     ("ssa", "nethept", 0, 50, 0.1, 0),
     ("dssa", "nethept", 0, 50, 0.1, 0),
+    ("ssa", "nethept", 0, 1, 0.1, 2),
     ("ssa", "cl_small", 1, 10, 0.2, 3),
     ("dssa", "cl_small", 1, 10, 0.2, 3),
     ("ssa", "rmat12", 0, 25, 0.1, 5),
