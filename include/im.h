@@ -107,8 +107,10 @@ void im_graph_free(im_graph *g);
  * bit 1 LT) and bit 2: every node's IC in-edges share one threshold (the
  * weighted cascade w(u,v) = 1/d_in(v) of Section 7 is such a graph), so
  * the device also holds the compact IC form: per node {first in-edge,
- * in-degree, thr} in 16 bytes, per edge its u32 src. IC draws read that
- * form (IM_PARAM_IC_COMPACT); their sets are the same in either form. */
+ * in-degree, thr} in 16 bytes, per edge its u32 src (built unless
+ * IM_PARAM_IC_COMPACT was 0 at load, or its memory could not be had). IC
+ * draws read that form (IM_PARAM_IC_COMPACT); their sets are the same in
+ * either form. */
 im_status im_graph_info(const im_graph *g, uint32_t *n, uint64_t *m, uint32_t *models);
 
 /*
@@ -436,7 +438,9 @@ im_status im_ctx_set_timing(im_ctx *ctx, int enable);
  *   IM_PARAM_IC_COMPACT            1: IC draws on a graph that holds the
  *       compact IC form (im_graph_info bit 2) read it: 16 bytes per
  *       expanded node and 4 per examined in-edge, against 16 + 8; 0: the
- *       {src, thr} records (default 1). The sets drawn are the same.
+ *       {src, thr} records (default 1). The sets drawn are the same. The
+ *       value when a graph is loaded decides whether the form is built
+ *       (4 m + 16 n bytes, left out if that memory cannot be had).
  * Errors: IM_E_ARG (unknown parameter or value out of range).
  */
 typedef enum {

@@ -253,9 +253,19 @@ im_status graph_build(im_graph *g, const uint32_t *src_h, const uint32_t *dst_h,
         set_error("im_graph_load: LT in-weights of some node sum above 1");
         return IM_E_LT_WEIGHTS;
     }
-    if (w_ic_h && !(hc.flags & kIcMixed)) {
-        IM_TRY(dev_alloc(ctx, g->srcs_ic, ic_records(m) * 4));
-        IM_TRY(dev_alloc(ctx, g->nodes_ic, size_t(n) * 16));
+    // the compact IC form is optional: not built when the context's draws
+    // would not read it, and left out when its memory is not there (draws
+    // then read the records)
+    if (w_ic_h && ctx->ic_compact && !(hc.flags & kIcMixed)) {
+        if (dev_alloc(ctx, g->srcs_ic, ic_records(m) * 4) != IM_OK ||
+            dev_alloc(ctx, g->nodes_ic, size_t(n) * 16) != IM_OK) {
+            dev_free(ctx, g->srcs_ic);
+            dev_free(ctx, g->nodes_ic);
+            (void)hipGetLastError();  // a failed hipMalloc is reported once more here; not an error of the load
+            clear_error();
+        }
+    }
+    if (g->nodes_ic.ptr) {
         const auto *rec = static_cast<const uint2 *>(g->edges_ic.ptr);
         ic_compact_srcs_kernel<<<grid_for(ic_records(m), cu), 256, 0, st>>>(rec, m, static_cast<uint32_t *>(g->srcs_ic.ptr));
         ic_compact_nodes_kernel<<<grid_for(n, cu), 256, 0, st>>>(off, rec, n, static_cast<uint4 *>(g->nodes_ic.ptr));

@@ -332,14 +332,15 @@ def test_fused_pools_argument_errors(im, ctx):
     assert a.count == 0 and b.count == 0
 
 
-@pytest.mark.parametrize("name", ["nethept", "heavy6000", "rmat12", "nethept_mixed"])
+@pytest.mark.parametrize("name", ["nethept", "heavy6000", "rmat12", "nethept_mixed", "nethept_off"])
 def test_compact_ic_form_matches_records_and_oracle(im, ctx, oracle_lib, name):
     """Graphs whose IC in-edges of each node share one threshold (weighted
     cascade, a constant p) hold the compact IC form (graph info bit 2) and
     IC draws read it; the sets must be the oracle's and the same as from the
     {src, thr} records (IM_PARAM_IC_COMPACT = 0), in pool and hits mode.
     Graphs with mixed thresholds (trivalency; weighted cascade with one
-    weight changed) hold no compact form."""
+    weight changed) hold no compact form, nor does one loaded while the
+    parameter is 0."""
     if name == "heavy6000":
         n, deg = 6000, 40
         rng = np.random.default_rng(n + deg)
@@ -350,8 +351,8 @@ def test_compact_ic_form_matches_records_and_oracle(im, ctx, oracle_lib, name):
         g = synth.from_edges(name, n, pairs[:, 1], pairs[:, 0], w_ic=np.full(pairs.shape[0], 0.3, dtype=np.float32))
         w, uniform, count = g.w_ic, True, 300
     else:
-        g = synth.make("nethept" if name == "nethept_mixed" else name)
-        w, uniform, count = g.w_ic, name != "rmat12", 20000
+        g = synth.make(name.split("_")[0])
+        w, uniform, count = g.w_ic, name in ("nethept", "heavy6000"), 20000
         if name == "nethept_mixed":
             # one in-edge of a node with several gets another weight
             indeg = np.bincount(g.dst, minlength=g.n)
@@ -359,7 +360,11 @@ def test_compact_ic_form_matches_records_and_oracle(im, ctx, oracle_lib, name):
             w = g.w_ic.copy()
             w[e] = np.float32(min(1.0, float(w[e]) * 2.0))
             uniform = False
-    dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w)
+    ctx.set_param("ic_compact", 0 if name == "nethept_off" else 1)
+    try:
+        dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=w)
+    finally:
+        ctx.set_param("ic_compact", 1)
     og = oracle_lib.Graph(0, g.n, g.src, g.dst, w)
     assert bool(dg.info()[2] & 4) == uniform
     note(f"compact IC form {name} uniform={uniform} count={count}")
