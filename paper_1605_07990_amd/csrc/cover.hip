@@ -1433,6 +1433,9 @@ __global__ __launch_bounds__(kThreads) void argmax_count_kernel(const uint32_t *
     if (lane_id() == 0 && best) atomicMax(out, best);
 }
 
+// dst[0] = cnt[v]: one node's count, read on the stream between launches.
+__global__ void pick_u32_kernel(const uint32_t *cnt, uint32_t v, uint32_t *dst) { dst[0] = cnt[v]; }
+
 // Sets in [begin, end) that contain a node of the seed bitmap.
 __global__ __launch_bounds__(kThreads) void coverage_kernel(const uint64_t *poff, const uint32_t *pnodes, uint64_t begin,
                                                             uint64_t end, const uint32_t *seedbits,
@@ -1961,7 +1964,40 @@ im_status coverage_range(const im_pool *p, uint64_t begin, uint64_t end, const u
 
 im_status coverage_range_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_t end, const uint32_t *seeds_host,
                             uint32_t k, uint64_t *cov) {
-    IM_TRY(set_seed_bits(ctx, p->g->n, seeds_host, k));
+    const uint32_t n = p->g->n;
+    if (k == 1 && seeds_host[0] < n && end > begin && ctx->k1_serial == p->serial && ctx->k1_cnt.ptr) {
+        // one seed s, and the context holds the node counts of this pool's
+        // entries up to exactly where the range starts (the stare step
+        // after a one-seed Max-Coverage of [0, begin)): the sets of the
+        // range that hold s are its count over the range's entries (a set
+        // holds a node once), read before and after adding them, and the
+        // counts then cover [0, end) for the next, doubled prefix
+        const auto *poff = static_cast<const uint64_t *>(p->poff.ptr);
+        uint64_t ends[2] = {0, 0};
+        IM_TRY(to_host_sync(ctx, &ends[0], poff + begin, 8));
+        IM_TRY(to_host_sync(ctx, &ends[1], poff + end, 8));
+        if (ends[0] == ctx->k1_end) {
+            auto *cnt = static_cast<uint32_t *>(ctx->k1_cnt.ptr);
+            auto *two = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->k1_cnt.ptr) +
+                                                     ((4ull * n + 255) & ~255ull) + 8);
+            hipStream_t st = ctx->stream;
+            const uint32_t cu = static_cast<uint32_t>(ctx->cu_count);
+            ctx->k1_serial = 0;  // until the counts below are in
+            pick_u32_kernel<<<1, 1, 0, st>>>(cnt, seeds_host[0], two);
+            if (ends[1] > ends[0])
+                histogram_kernel<<<grid_of(ends[1] - ends[0], kThreads, cu * 16), kThreads, 0, st>>>(
+                    static_cast<const uint32_t *>(p->pnodes.ptr), ends[0], ends[1], cnt);
+            pick_u32_kernel<<<1, 1, 0, st>>>(cnt, seeds_host[0], two + 1);
+            IM_HIP(hipGetLastError());
+            uint32_t h[2] = {0, 0};
+            IM_TRY(to_host_sync(ctx, h, two, 8));
+            ctx->k1_serial = p->serial;
+            ctx->k1_end = ends[1];
+            *cov = h[1] - h[0];
+            return IM_OK;
+        }
+    }
+    IM_TRY(set_seed_bits(ctx, n, seeds_host, k));
     IM_TRY(dev_reserve(ctx, ctx->counters, 256));
     auto *out = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->counters.ptr) + 128);
     hipStream_t st = ctx->stream;
@@ -2287,7 +2323,7 @@ static im_status greedy_on(im_ctx *ctx, uint32_t n, const uint64_t *poff, const 
     if (k == 1) {
         // one round of Algorithm 2: the node in the most sets of the range;
         // its count is Cov (a node is in a set at most once). No incidence.
-        IM_TRY(dev_reserve(ctx, ctx->cover, 4ull * n + 256));
+        IM_TRY(dev_reserve(ctx, ctx->cover, 4ull * n + 512));  // counts, then the key
         auto *cnt = static_cast<uint32_t *>(ctx->cover.ptr);
         auto *key = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->cover.ptr) +
                                                            ((4ull * n + 255) & ~255ull));
@@ -2646,7 +2682,7 @@ im_status max_coverage_on(im_ctx *ctx, const im_pool *p, uint64_t begin, uint64_
         // and only the new sets' entries are added (integer counts: the
         // result is the full count's)
         const void *was = ctx->k1_cnt.ptr;
-        IM_TRY(dev_reserve(ctx, ctx->k1_cnt, 4ull * n + 256));
+        IM_TRY(dev_reserve(ctx, ctx->k1_cnt, 4ull * n + 512));  // counts, then the key and two picks
         auto *cnt = static_cast<uint32_t *>(ctx->k1_cnt.ptr);
         auto *key = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->k1_cnt.ptr) +
                                                            ((4ull * n + 255) & ~255ull));

@@ -313,10 +313,13 @@ def test_greedy_over_held_nodes_matches_oracle(im, ctx, oracle_lib, dense):
 def test_one_seed_over_growing_prefixes(im, ctx, oracle_lib):
     """Max-Coverage with k = 1 over a prefix [0, end) keeps the node counts
     of the last prefix of the same pool and adds only the new sets' entries
-    (SSA and D-SSA double their prefixes). Every answer must be the oracle's:
-    growing, repeated and shrinking prefixes, a range not at 0, another
-    pool in between, and a prefix reaching sets appended after the last
-    call."""
+    (SSA and D-SSA double their prefixes); a one-seed coverage count over
+    [end, 2 end) right after it (D-SSA's stare step) is the seed's count over
+    the range's entries and leaves the counts at [0, 2 end). Every answer
+    must be the oracle's: growing, repeated and shrinking prefixes, a range
+    not at 0, another pool in between, stares that do and do not start
+    where the counts end, and a prefix reaching sets appended after the
+    last call."""
     g = synth.make("nethept")
     dg = im.Graph(ctx, g.n, g.src, g.dst, w_ic=g.w_ic)
     og = oracle_lib.Graph(0, g.n, g.src, g.dst, g.w_ic)
@@ -333,9 +336,23 @@ def test_one_seed_over_growing_prefixes(im, ctx, oracle_lib):
         seeds, cov = pool.max_coverage(1, begin, end)
         oseeds, ocov = opool.max_coverage(1, begin, end)
         assert (seeds.tolist(), cov) == (oseeds.tolist(), ocov), (pool.key, begin, end)
+        return seeds
+
+    def stare(pool, opool, seeds, begin, end):
+        assert pool.coverage(seeds, begin, end) == opool.coverage(seeds, begin, end), (pool.key, begin, end)
 
     for pool, opool, begin, end in steps:
-        same(pool, opool, begin, end)
+        seeds = same(pool, opool, begin, end)
+        if begin == 0 and 2 * end <= pool.count:
+            stare(pool, opool, seeds, end, 2 * end)  # starts where the counts end
+            stare(pool, opool, seeds, end, 2 * end)  # the counts now reach 2 end: the plain count
+            other = np.array([(int(seeds[0]) + 1) % g.n], dtype=np.uint32)
+            stare(pool, opool, other, 2 * end, min(pool.count, 3 * end))  # another node, at the counts' end
+    seeds = same(p, op, 0, 4000)
+    stare(p, op, seeds, 2000, 6000)  # a range that does not start where the counts end
+    same(p, op, 0, 6000)
     p.sample(10000)  # appended: the next prefix holds sets drawn after the counts were taken
+    seeds = same(p, op, 0, 15000)
+    stare(p, op, seeds, 15000, 30000)
     same(p, op, 0, 30000)
     same(p, op, 0, 25000)
