@@ -45,3 +45,22 @@ def test_synthetic_lt_weights_are_valid(oracle_lib, synth_lib):
         g = synth_lib.make(name)
         oracle_lib.Graph(oracle_lib.LT, g.n, g.src, g.dst, g.w_lt)
         oracle_lib.Graph(oracle_lib.IC, g.n, g.src, g.dst, g.w_ic)
+
+
+def test_synthetic_ic_thresholds_shared_per_node(oracle_lib, synth_lib):
+    """The weighted cascade (w(u,v) = 1/d_in(v)) gives every in-edge of a
+    node the same threshold, which is what lets the device hold the compact
+    IC form for the NetHEPT- and Twitter-shaped inputs; trivalency weights
+    differ within a node and keep the {src, thr} records."""
+    def shared(g):
+        thr = oracle_lib.Graph(oracle_lib.IC, g.n, g.src, g.dst, g.w_ic).thresholds()
+        same = g.dst[1:] == g.dst[:-1]
+        return bool(np.all(thr[1:][same] == thr[:-1][same]))
+
+    for name in ("cl_small", "nethept"):
+        g = synth_lib.make(name)
+        assert shared(g), name
+        indeg = np.bincount(g.dst, minlength=g.n)
+        w = 1.0 / indeg[g.dst]  # rounded down to fp32 by the generator
+        assert np.all(g.w_ic <= w) and np.allclose(g.w_ic, w, rtol=1e-6, atol=0), name
+    assert not shared(synth_lib.make("rmat12"))
